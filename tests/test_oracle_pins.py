@@ -1,0 +1,319 @@
+"""Pins of the FP64 oracle to closed forms, to the Kalman-filter identity,
+to library routines and to brute force (CPU only)."""
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg
+import scipy.stats
+
+from oracle import analysis, domain_analysis, forecast, forecast_normals, philox4x32_10
+from oracle.letkf import ensemble_mean_perturbations, slope_synthesis
+from workload.geometry import (build_geometry, fried_slope_matrix, global_domain, window_domains,
+                               DomainMap)
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ---------------------------------------------------------------- Philox / noise
+def test_philox_known_answers():
+    for line in open(os.path.join(GOLDEN, "philox4x32_10_kat.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        w = [int(t, 16) for t in line.split()]
+        out = philox4x32_10(np.array(w[0:4]), np.array(w[4:6]))
+        assert [int(v) for v in out] == w[6:10]
+
+
+def test_forecast_normals_are_standard_normal():
+    z = forecast_normals(seed=12345, frame=7, n_act=500, m=128).ravel()
+    assert abs(z.mean()) < 0.02 and abs(z.var() - 1) < 0.02
+    assert scipy.stats.kstest(z, "norm").pvalue > 1e-3
+    # distinct frames / seeds / members give independent streams
+    z2 = forecast_normals(seed=12345, frame=8, n_act=500, m=128).ravel()
+    z3 = forecast_normals(seed=12346, frame=7, n_act=500, m=128).ravel()
+    assert abs(np.corrcoef(z, z2)[0, 1]) < 0.02 and abs(np.corrcoef(z, z3)[0, 1]) < 0.02
+    # counter layout: member j of actuator a does not alias actuator j member a
+    zz = forecast_normals(seed=1, frame=0, n_act=8, m=8)
+    assert not np.allclose(zz, zz.T)
+
+
+def test_forecast_normals_large_frame_uses_high_word():
+    a = forecast_normals(seed=3, frame=5, n_act=4, m=4)
+    b = forecast_normals(seed=3, frame=5 + (1 << 32), n_act=4, m=4)
+    assert not np.allclose(a, b)
+
+
+# ---------------------------------------------------------------- helpers
+def _rand_domain(rng, m, nE, pO, scale=1.0):
+    Xp = rng.standard_normal((nE, m)) * scale
+    Xp -= Xp.mean(axis=1, keepdims=True)
+    Yp = rng.standard_normal((pO, m)) * scale
+    Yp -= Yp.mean(axis=1, keepdims=True)
+    return Xp, rng.standard_normal(nE), Yp, rng.standard_normal(pO), rng.uniform(0.5, 2.0, pO)
+
+
+# ---------------------------------------------------------------- closed forms
+def test_m2_closed_form():
+    """m = 2, X' = [u, -u], Y' = [v, -v]: mean gain 2uc/(1+2s), spread (1+2s)^-1/2."""
+    rng = np.random.default_rng(0)
+    u = rng.standard_normal(5)
+    v = rng.standard_normal(7)
+    d = rng.standard_normal(7)
+    r = rng.uniform(0.5, 3, 7)
+    xbar = rng.standard_normal(5)
+    s = v @ (r * v)
+    c = v @ (r * d)
+    res = domain_analysis(np.stack([u, -u], 1), xbar, np.stack([v, -v], 1), d, r)
+    mean_a = res["Z"].mean(axis=1)
+    np.testing.assert_allclose(mean_a, xbar + 2 * u * c / (1 + 2 * s), rtol=1e-13, atol=1e-13)
+    pert = res["Z"] - mean_a[:, None]
+    np.testing.assert_allclose(pert, np.stack([u, -u], 1) / np.sqrt(1 + 2 * s), rtol=1e-12, atol=1e-13)
+    np.testing.assert_allclose(np.sort(res["lam"]), [1.0, 1 + 2 * s], rtol=1e-13)
+
+
+def test_scalar_kalman_filter():
+    """n = p = 1, H = 1: mean x + P/(P+R) d, variance P R / (P + R)."""
+    rng = np.random.default_rng(1)
+    for m in (3, 10, 40):
+        x = rng.standard_normal(m) * 2.0 + 1.0
+        xbar, xp = x.mean(), x - x.mean()
+        R = 0.7
+        y = 0.3
+        P = xp @ xp / (m - 1)
+        res = domain_analysis(xp[None, :], np.array([xbar]), xp[None, :], np.array([y - xbar]),
+                              np.array([1.0 / R]))
+        za = res["Z"][0]
+        np.testing.assert_allclose(za.mean(), xbar + P / (P + R) * (y - xbar), rtol=1e-13)
+        np.testing.assert_allclose(np.var(za, ddof=1), P * R / (P + R), rtol=1e-12)
+
+
+def test_no_observations_is_identity():
+    rng = np.random.default_rng(2)
+    Xp, xbar, Yp, d, r = _rand_domain(rng, 12, 6, 9)
+    res = domain_analysis(Xp, xbar, Yp, d, np.zeros_like(r))
+    np.testing.assert_allclose(res["W"], np.eye(12), atol=1e-14)
+    np.testing.assert_allclose(res["wbar"], 0, atol=1e-15)
+    np.testing.assert_allclose(res["Z"], xbar[:, None] + Xp, atol=1e-14)
+
+
+# ---------------------------------------------------------------- library routines
+@pytest.mark.parametrize("m", [2, 3, 4, 7])
+def test_tiny_against_sqrtm_and_solve(m):
+    rng = np.random.default_rng(10 + m)
+    Xp, xbar, Yp, d, r = _rand_domain(rng, m, 3, 5)
+    res = domain_analysis(Xp, xbar, Yp, d, r)
+    A = (m - 1) * np.eye(m) + Yp.T @ np.diag(r) @ Yp           # brute force
+    np.testing.assert_allclose(res["A"], A, rtol=1e-14, atol=1e-13)
+    W = scipy.linalg.sqrtm((m - 1) * np.linalg.inv(A)).real
+    np.testing.assert_allclose(res["W"], W, rtol=1e-10, atol=1e-12)
+    np.testing.assert_allclose(res["wbar"], scipy.linalg.solve(A, Yp.T @ (r * d)), rtol=1e-11, atol=1e-13)
+    # brute-force update, element by element
+    T = W + res["wbar"][:, None]
+    Z = np.array([[xbar[i] + sum(Xp[i, k] * T[k, j] for k in range(m)) for j in range(m)]
+                  for i in range(Xp.shape[0])])
+    np.testing.assert_allclose(res["Z"], Z, rtol=1e-10, atol=1e-12)
+
+
+# ---------------------------------------------------------------- invariants
+@pytest.mark.parametrize("rho", [1.0, 1.05])
+def test_transform_invariants(rho):
+    rng = np.random.default_rng(3)
+    m = 24
+    Xp, xbar, Yp, d, r = _rand_domain(rng, m, 10, 30, scale=3.0)
+    res = domain_analysis(Xp, xbar, Yp, d, r, rho=rho)
+    W, wbar, lam = res["W"], res["wbar"], res["lam"]
+    one = np.ones(m)
+    np.testing.assert_allclose(W, W.T, atol=1e-14)
+    np.testing.assert_allclose(W @ one, one * np.sqrt(rho), rtol=1e-12)     # 1 is an eigvec, lambda = (m-1)/rho
+    assert abs(one @ wbar) < 1e-12 * np.abs(wbar).sum()
+    Pt = np.linalg.inv(res["A"])
+    np.testing.assert_allclose(W @ W, (m - 1) * Pt, rtol=1e-10, atol=1e-14)
+    assert lam.min() >= (m - 1) / rho * (1 - 1e-12)
+    pert = res["Z"] - res["Z"].mean(axis=1, keepdims=True)
+    np.testing.assert_allclose(pert.sum(axis=1), 0, atol=1e-10)
+    np.testing.assert_allclose(res["Z"].mean(axis=1), xbar + Xp @ wbar, rtol=1e-12, atol=1e-12)
+
+
+def test_member_permutation_equivariance():
+    rng = np.random.default_rng(4)
+    geom = build_geometry(6, "square")
+    D = fried_slope_matrix(geom).to_dense()
+    dm = window_domains(geom, 3, 2, 1)
+    m = 9
+    X = rng.standard_normal((geom.n, m))
+    y = rng.standard_normal(geom.p)
+    r_inv = np.full(geom.p, 4.0)
+    perm = rng.permutation(m)
+    Xa = analysis(X, y, D, dm, r_inv)
+    Xa_p = analysis(X[:, perm], y, D, dm, r_inv)
+    np.testing.assert_allclose(Xa_p, Xa[:, perm], rtol=1e-11, atol=1e-11)
+
+
+# ---------------------------------------------------------------- Kalman filter identity
+def _kf(xbar, P, H, R, y):
+    S = H @ P @ H.T + R
+    K = np.linalg.solve(S, H @ P).T      # P H^T S^-1  (S symmetric)
+    return xbar + K @ (y - H @ xbar), (np.eye(len(xbar)) - K @ H) @ P
+
+
+def _tiny_case(rng, lenslets=4, m=8):
+    geom = build_geometry(lenslets, "square")
+    D = fried_slope_matrix(geom).to_dense()
+    H = np.hstack([D, np.zeros_like(D)])
+    X = rng.standard_normal((geom.n, m)) * 2.0
+    y = rng.standard_normal(geom.p)
+    R = np.diag(rng.uniform(0.2, 1.0, geom.p))
+    return geom, D, H, X, y, R
+
+
+@pytest.mark.parametrize("m", [2, 5, 16])
+def test_global_etkf_equals_kf_with_sample_covariance(m):
+    """Woodbury: one global domain gives the KF analysis with P = X'X'^T/(m-1)."""
+    rng = np.random.default_rng(5 + m)
+    geom, D, H, X, y, R = _tiny_case(rng, 4, m)
+    xbar, Xp = ensemble_mean_perturbations(X)
+    P = Xp @ Xp.T / (m - 1)
+    mean_kf, Pa_kf = _kf(xbar, P, H, R, y)
+    Xa = analysis(X, y, D, global_domain(geom), 1.0 / np.diag(R))
+    xa, Xap = ensemble_mean_perturbations(Xa)
+    np.testing.assert_allclose(xa, mean_kf, rtol=1e-10, atol=1e-10)
+    np.testing.assert_allclose(Xap @ Xap.T / (m - 1), Pa_kf, rtol=1e-9, atol=1e-10)
+
+
+def test_etkf_exact_kf_when_ensemble_spans_covariance():
+    """An ensemble whose sample covariance is exactly P gives the exact KF."""
+    rng = np.random.default_rng(6)
+    geom, D, H, _, y, R = _tiny_case(rng, 3, 8)
+    n = geom.n
+    m = n + 5
+    L = np.linalg.cholesky(np.cov(rng.standard_normal((n, 4 * n))) + 0.1 * np.eye(n))
+    P = L @ L.T
+    # E: n orthonormal rows orthogonal to the ones vector
+    Q, _ = np.linalg.qr(np.hstack([np.ones((m, 1)), rng.standard_normal((m, n))]))
+    E = Q[:, 1:n + 1].T
+    xbar = rng.standard_normal(n)
+    X = xbar[:, None] + np.sqrt(m - 1) * L @ E
+    mean_kf, Pa_kf = _kf(xbar, P, H, R, y)
+    Xa = analysis(X, y, D, global_domain(geom), 1.0 / np.diag(R))
+    xa, Xap = ensemble_mean_perturbations(Xa)
+    np.testing.assert_allclose(xa, mean_kf, rtol=1e-10, atol=1e-10)
+    np.testing.assert_allclose(Xap @ Xap.T / (m - 1), Pa_kf, rtol=1e-9, atol=1e-10)
+
+
+def test_etkf_converges_to_kf_as_m_grows():
+    """Linear-Gaussian case: the ETKF mean error vs the exact KF decays like
+    m^-1/2 (Sec. 3.1 convergence claim), measured over seeds."""
+    rng0 = np.random.default_rng(7)
+    geom, D, H, _, y, R = _tiny_case(rng0, 3, 8)
+    n = geom.n
+    L = np.linalg.cholesky(np.cov(rng0.standard_normal((n, 4 * n))) + 0.1 * np.eye(n))
+    P = L @ L.T
+    xtrue = rng0.standard_normal(n)
+    mean_kf, _ = _kf(xtrue, P, H, R, y)
+    errs = []
+    ms = [8, 32, 128, 512]
+    for m in ms:
+        e = []
+        for s in range(12):
+            rng = np.random.default_rng(1000 * m + s)
+            X = xtrue[:, None] + L @ rng.standard_normal((n, m))
+            X += (xtrue - X.mean(axis=1))[:, None]           # exact forecast mean
+            Xa = analysis(X, y, D, global_domain(geom), 1.0 / np.diag(R))
+            e.append(np.linalg.norm(Xa.mean(axis=1) - mean_kf))
+        errs.append(np.mean(e))
+    slope = np.polyfit(np.log(ms), np.log(errs), 1)[0]
+    assert -0.8 < slope < -0.3, (errs, slope)
+    assert all(errs[i + 1] < errs[i] for i in range(len(errs) - 1)), errs
+
+
+# ---------------------------------------------------------------- localization
+def test_infinite_halo_domains_equal_global():
+    """Every domain seeing every slope without taper uses the global transform,
+    so any partition reproduces the global ETKF."""
+    rng = np.random.default_rng(8)
+    geom = build_geometry(6, "square")
+    D = fried_slope_matrix(geom).to_dense()
+    m = 10
+    X = rng.standard_normal((geom.n, m))
+    y = rng.standard_normal(geom.p)
+    r_inv = rng.uniform(1, 5, geom.p)
+    glob = analysis(X, y, D, global_domain(geom), r_inv)
+    for dm in (window_domains(geom, 3, 3, 50), window_domains(geom, 4, 2, 50)):
+        np.testing.assert_allclose(analysis(X, y, D, dm, r_inv), glob, rtol=1e-10, atol=1e-10)
+
+
+def test_merge_weights_average_overlapping_domains():
+    """Two identical copies of the global domain with weights 1/2 each give
+    the global result (merge is a weighted sum per row)."""
+    rng = np.random.default_rng(9)
+    geom = build_geometry(5, "square")
+    D = fried_slope_matrix(geom).to_dense()
+    g = global_domain(geom)
+    two = DomainMap(np.array([0, geom.n_act, 2 * geom.n_act], np.int32),
+                    np.concatenate([g.est_act, g.est_act]), np.full(2 * geom.n_act, 0.5),
+                    np.array([0, geom.n_sub, 2 * geom.n_sub], np.int32),
+                    np.concatenate([g.obs_sub, g.obs_sub]), np.ones(2 * geom.n_sub))
+    X = rng.standard_normal((geom.n, 6))
+    y = rng.standard_normal(geom.p)
+    r = np.full(geom.p, 2.0)
+    np.testing.assert_allclose(analysis(X, y, D, two, r), analysis(X, y, D, g, r), rtol=1e-12, atol=1e-12)
+
+
+def test_taper_zero_removes_observation():
+    """A zero taper weight is the same as not observing that subaperture."""
+    rng = np.random.default_rng(10)
+    geom = build_geometry(5, "square")
+    D = fried_slope_matrix(geom).to_dense()
+    g = global_domain(geom)
+    X = rng.standard_normal((geom.n, 7))
+    y = rng.standard_normal(geom.p)
+    r = np.full(geom.p, 3.0)
+    keep = np.arange(geom.n_sub) % 3 != 0
+    tap = DomainMap(g.est_ptr, g.est_act, g.est_w, g.obs_ptr, g.obs_sub, keep.astype(float))
+    sub = DomainMap(g.est_ptr, g.est_act, g.est_w, np.array([0, keep.sum()], np.int32),
+                    g.obs_sub[keep], np.ones(keep.sum()))
+    np.testing.assert_allclose(analysis(X, y, D, tap, r), analysis(X, y, D, sub, r), rtol=1e-12, atol=1e-12)
+
+
+# ---------------------------------------------------------------- slopes / forecast
+def test_slope_synthesis_tilt_and_piston():
+    geom = build_geometry(8, "circular")
+    D = fried_slope_matrix(geom).to_dense()
+    c = geom.act_rc[:, 1].astype(float)
+    m = 4
+    amp = np.array([1.0, -2.0, 0.5, 0.5])
+    X = np.vstack([np.outer(c, amp) + 3.0, np.zeros((geom.n_act, m))])   # tilts plus a common piston
+    ybar, Yp = slope_synthesis(D, X, geom.n_act)
+    np.testing.assert_allclose(ybar[:geom.n_sub], amp.mean())
+    np.testing.assert_allclose(Yp[:geom.n_sub], np.tile(amp - amp.mean(), (geom.n_sub, 1)), atol=1e-14)
+    np.testing.assert_allclose(Yp[geom.n_sub:], 0, atol=1e-14)
+
+
+def test_forecast_deterministic_ar2_closed_form():
+    """a1 = 1.6, a2 = -0.64 has a double pole at 0.8: phi_k = (c1 + c2 k) 0.8^k."""
+    n_act, m = 3, 2
+    phi0 = np.array([1.0, -2.0, 0.5])
+    phim1 = np.array([0.5, 1.0, 0.0])
+    X = np.vstack([np.tile(phi0[:, None], m), np.tile(phim1[:, None], m)])
+    a1, a2 = np.full(n_act, 1.6), np.full(n_act, -0.64)
+    c1 = phi0
+    c2 = c1 - 0.8 * phim1          # from phi_-1 = (c1 - c2) / 0.8
+    for k in range(1, 12):
+        X = forecast(X, a1, a2, 0.0, seed=0, frame=k)
+        np.testing.assert_allclose(X[:n_act, 0], (c1 + c2 * k) * 0.8 ** k, rtol=1e-12, atol=1e-14)
+        np.testing.assert_allclose(X[n_act:, 0], (c1 + c2 * (k - 1)) * 0.8 ** (k - 1), rtol=1e-12, atol=1e-14)
+
+
+def test_forecast_noise_stationary_variance():
+    """AR(2) driven by sigma_v z reaches sigma_v^2 (1-a2)/((1+a2)((1-a2)^2-a1^2))."""
+    n_act, m = 200, 64
+    a1, a2 = np.full(n_act, 1.6), np.full(n_act, -0.64)
+    X = np.zeros((2 * n_act, m))
+    acc = []
+    for k in range(600):
+        X = forecast(X, a1, a2, 1.0, seed=99, frame=k)
+        if k >= 200:
+            acc.append(np.var(X[:n_act]))
+    target = (1 - (-0.64)) / ((1 - 0.64) * ((1 + 0.64) ** 2 - 1.6 ** 2))
+    assert abs(np.mean(acc) / target - 1) < 0.06
