@@ -1,0 +1,237 @@
+/*
+ * letkf.h -- C ABI of the MI355X (gfx950) local ETKF library.
+ *
+ * The library keeps an m-member ensemble of the adaptive-optics state
+ * resident in device memory and advances it one frame at a time:
+ *
+ *   letkf_analyse   per-domain local ETKF update from one slope frame
+ *                   (paper Sec. 2.2-2.3: every estimation domain is updated
+ *                   from its own observation region, independently).
+ *   letkf_forecast  AR(1)/AR(2) prediction of every member (Sec. 2.1).
+ *   letkf_submit_frame  the same two steps driven by a serving loop that
+ *                   batches the frames of several resident instances into
+ *                   shared kernel launches.
+ *
+ * State (Sec. 2.1): x_k = [phi_k ; phi_{k-1}] on the n_act valid actuators,
+ * n = 2 n_act.  Observations (Sec. 2.1, Sec. 3): x then y slope of each
+ * of the n_sub valid subapertures, p = 2 n_sub, through the WFS matrix D
+ * (p x n_act, CSR), observing the current instant: H = [D 0].
+ *
+ * Analysis of domain l (actuators E_l, subapertures O_l; ensemble-space ETKF
+ * of the paper's refs [8]-[10], localized per ref [14]):
+ *   X' = X - xbar 1^T,  Y' = D X'_phi,  d = y - D xbar_phi,
+ *   r = taper * R^-1 on O_l,   C = Y'_O^T diag(r) Y'_O,   b = Y'_O^T diag(r) d_O,
+ *   A = (m-1)/rho I + C = U Lambda U^T,  wbar = A^-1 b,
+ *   W = U ((m-1) Lambda^-1)^(1/2) U^T  (symmetric root, ref [9]),
+ *   Z_l = xbar_E 1^T + X'_E (W + wbar 1^T);
+ * rows covered by several domains are merged with the map's weights
+ * (whole-pupil reconstruction, Sec. 3.2).
+ *
+ * Forecast: phi_{k+1} = a1 .* phi_k + a2 .* phi_{k-1} + sigma_v z, with z
+ * standard normal from Philox4x32-10 (Salmon et al., SC'11):
+ *   counter = (member, actuator, frame mod 2^32, frame div 2^32),
+ *   key = (seed mod 2^32, seed div 2^32);  outputs (x0..x3) give
+ *   u1 = ((x0 2^21 + x1 div 2^11) + 1/2) 2^-53, u2 likewise from (x2, x3),
+ *   z = sqrt(-2 ln u1) cos(2 pi u2).  frame = number of forecasts done
+ *   since create (or the value given to letkf_set_state).
+ *
+ * Conventions for every call
+ *   - Every function returns an int status: LETKF_OK (0) or a negative code.
+ *     No C++ exception crosses this interface.  letkf_last_error() returns a
+ *     thread-local message for the last failure of the calling thread.
+ *   - "host" pointers are ordinary CPU memory, "device" pointers are HIP
+ *     device memory of the handle's GPU.  All host input arrays are read
+ *     (and copied where needed) before the call returns; the caller keeps
+ *     ownership of every pointer it passes.
+ *   - Matrices are row-major.  Ensemble matrices are n x m: row = state
+ *     variable (rows 0..n_act-1 = phi_k, n_act..n-1 = phi_{k-1}), column =
+ *     member.
+ *   - stream: a hipStream_t passed as void* (NULL = the default stream).
+ *   - Limits: 2 <= m <= 128; n_act, n_sub >= 1; every domain has >= 1
+ *     actuator.  Violations return LETKF_EINVAL before any device work.
+ *   - A handle is used by one thread at a time.
+ */
+#ifndef LETKF_H
+#define LETKF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------- */
+#define LETKF_OK        0
+#define LETKF_EINVAL   (-1)  /* invalid argument, map or dimension */
+#define LETKF_ENOMEM   (-2)  /* workspace / arena too small, HBM budget exceeded */
+#define LETKF_EAGAIN   (-3)  /* no free frame slot; try again */
+#define LETKF_EDEVICE  (-4)  /* a HIP runtime call failed */
+#define LETKF_ENUMERIC (-5)  /* non-finite input, or the eigensolver did not converge */
+#define LETKF_ESTATE   (-6)  /* call not valid in the handle's state (e.g. no debug buffers) */
+
+/* ---- precision paths --------------------------------------------------
+ * LETKF_FP64: ensemble, slopes and both contractions in FP64; FP64 eigen.
+ * LETKF_FP32: FP32 ensemble; C and the update contraction on FP32 MFMA
+ *             with FP32 accumulation; FP64 eigensolve, wbar and W.
+ * LETKF_BF16: FP32 ensemble; BF16 operands for C and the update on MFMA with
+ *             FP32 accumulation; FP64 eigensolve, wbar and W.             */
+#define LETKF_FP64 0
+#define LETKF_FP32 1
+#define LETKF_BF16 2
+
+/* ---- create flags ----------------------------------------------------- */
+#define LETKF_FLAG_DEBUG 0x1u  /* keep per-domain C, lambda, T for letkf_debug_domain */
+
+typedef struct letkf_handle letkf_handle;
+typedef struct letkf_server letkf_server;
+
+typedef struct letkf_dims {
+  int32_t n_act;  /* valid actuators (state n = 2 n_act) */
+  int32_t n_sub;  /* valid subapertures (slopes p = 2 n_sub) */
+  int32_t m;      /* ensemble members, 2..128 */
+} letkf_dims;
+
+typedef struct letkf_model {
+  const double* a1;        /* host [n_act]: AR coefficient of phi_k */
+  const double* a2;        /* host [n_act]: AR coefficient of phi_{k-1} (0 gives AR(1)) */
+  double sigma_v;          /* model-noise std added to phi_{k+1}; >= 0 */
+  const double* r_inv;     /* host [p]: diagonal of R^-1 (inverse slope-noise variance); >= 0 */
+  int32_t d_nnz;           /* nonzeros of D */
+  const int32_t* d_rowptr; /* host [p+1]: CSR row pointers of D (p x n_act) */
+  const int32_t* d_col;    /* host [d_nnz]: actuator index of each nonzero */
+  const double* d_val;     /* host [d_nnz] */
+  double inflation;        /* rho > 0; 1 = no inflation */
+  uint64_t seed;           /* Philox key of the model noise */
+} letkf_model;
+
+typedef struct letkf_domain_map {
+  int32_t n_domains;
+  const int32_t* est_ptr;   /* host [n_domains+1]: CSR into est_act/est_w */
+  const int32_t* est_act;   /* host: actuators of each estimation domain (both instants updated) */
+  const double* est_w;      /* host: merge weight of each (domain, actuator); for every actuator
+                               the weights of the domains covering it sum to 1 (|sum-1| <= 1e-9) */
+  const int32_t* obs_ptr;   /* host [n_domains+1]: CSR into obs_sub/obs_taper */
+  const int32_t* obs_sub;   /* host: subapertures of each observation region (x and y slope used) */
+  const double* obs_taper;  /* host: localisation weight in [0,1], multiplies R^-1 of both slopes */
+} letkf_domain_map;
+
+/* ---- single instance -------------------------------------------------- */
+
+/* Bytes of device workspace letkf_create needs for this problem. */
+int letkf_workspace_size(const letkf_dims* dims, const letkf_model* model,
+                         const letkf_domain_map* map, int precision, uint32_t flags,
+                         size_t* bytes);
+
+/* Validates everything, lays the problem out in the caller's device
+ * workspace (>= letkf_workspace_size bytes, 256-byte aligned; owned by the
+ * caller and never freed by the library), uploads D, the map, the model and
+ * the initial ensemble X0 (host, n x m FP64, converted to the path's
+ * storage precision) on `stream`, and returns a handle.  Frame counter = 0. */
+int letkf_create(const letkf_dims* dims, const letkf_model* model, const letkf_domain_map* map,
+                 int precision, uint32_t flags, const double* X0, void* workspace,
+                 size_t workspace_bytes, void* stream, letkf_handle** out);
+
+/* Releases host-side state (pinned staging, tables).  Waits for the
+ * handle's outstanding work.  The workspace stays the caller's. */
+int letkf_destroy(letkf_handle* h);
+
+/* Analysis of the resident forecast ensemble with slopes y (p values, FP64;
+ * host pointer if y_on_device == 0, else device).  Host y is copied before
+ * return.  If mean_out (host [n_act]) is non-NULL the analysis mean of
+ * phi_k is written there and the call waits for the stream; otherwise the
+ * call is asynchronous on `stream`.  Non-finite host slopes: LETKF_ENUMERIC. */
+int letkf_analyse(letkf_handle* h, const double* y, int y_on_device, double* mean_out, void* stream);
+
+/* AR forecast of the resident ensemble to the next frame (asynchronous on
+ * `stream`); advances the frame counter. */
+int letkf_forecast(letkf_handle* h, void* stream);
+
+/* One frame of the plain path: analyse(y) then forecast.  If pred_out (host
+ * [n_act]) is non-NULL it receives the prediction mean of phi_{k+1} and the
+ * call waits for completion. */
+int letkf_step(letkf_handle* h, const double* y, int y_on_device, double* pred_out, void* stream);
+
+/* Copies the ensemble (host [n x m] FP64, rows [phi_k; phi_{k-1}]) and the
+ * frame counter out (frame_out may be NULL); waits for the stream. */
+int letkf_get_state(letkf_handle* h, double* X_out, uint64_t* frame_out, void* stream);
+
+/* Replaces the ensemble (host [n x m] FP64) and the frame counter. */
+int letkf_set_state(letkf_handle* h, const double* X, uint64_t frame, void* stream);
+
+/* Per-domain intermediates of the last analysis (needs LETKF_FLAG_DEBUG):
+ * C_out [m x m] (C = Y'^T diag(r) Y', no (m-1)/rho I), lam_out [m]
+ * (ascending eigenvalues of A), T_out [m x m] (W + wbar 1^T), sweeps_out
+ * (Jacobi sweeps used).  Any output may be NULL.  Waits for the stream. */
+int letkf_debug_domain(letkf_handle* h, int32_t domain, double* C_out, double* lam_out,
+                       double* T_out, int32_t* sweeps_out, void* stream);
+
+/* Number of domains whose eigensolver hit the sweep cap in the last analysis
+ * (0 when all converged); waits for the stream. */
+int letkf_unconverged_domains(letkf_handle* h, int32_t* count, void* stream);
+
+/* Kernel timing of the plain path: while enabled, analyse/forecast/step
+ * record HIP events on their stream around each kernel.  enable = 1 clears
+ * and starts, 0 stops.  ms_out (nullable, [3]) receives the accumulated
+ * milliseconds of {slope synthesis, domain analysis, merge/forecast} and
+ * frames_out (nullable) the number of timed frames; reading waits for the
+ * recorded events.  At most 65536 frames are timed per enable. */
+int letkf_kernel_times(letkf_handle* h, int enable, double* ms_out, uint64_t* frames_out);
+
+/* Totals since create (or set_state): Jacobi sweeps over all domain solves,
+ * and the number of domain solves.  Waits for the stream. */
+int letkf_sweep_stats(letkf_handle* h, uint64_t* sweeps, uint64_t* domain_solves, void* stream);
+
+/* ---- serving: many resident instances, batched frames ----------------- */
+
+/* Completion callback: called once per submitted frame from the server's
+ * completion thread, after pred_out has been written.  status is LETKF_OK
+ * or a negative code.  Must not call back into the server. */
+typedef void (*letkf_done_fn)(void* user, uint64_t frame_id, int status);
+
+/* A server sub-allocates instance workspaces from the caller's device arena
+ * (arena_bytes = the HBM budget) and runs one scheduler thread that gathers
+ * the pending frames of all instances (at most one per instance per batch,
+ * at most max_batch frames) into one batched launch sequence on its own
+ * stream.  Frames arriving while a batch runs join the next batch.
+ * flags: reserved, 0. */
+int letkf_server_create(void* arena, size_t arena_bytes, int32_t max_batch, uint32_t flags,
+                        letkf_server** out);
+
+/* Admits one instance (same arguments as letkf_create).  LETKF_ENOMEM when
+ * the remaining arena cannot hold its workspace. */
+int letkf_server_add(letkf_server* s, const letkf_dims* dims, const letkf_model* model,
+                     const letkf_domain_map* map, int precision, uint32_t flags, const double* X0,
+                     letkf_handle** out);
+
+/* Removes an idle instance (no frame in flight) and returns its workspace to
+ * the arena.  LETKF_EAGAIN while it still has frames in flight. */
+int letkf_server_remove(letkf_server* s, letkf_handle* h);
+
+/* Queues one frame of instance h: y (host [p] FP64) is copied before return;
+ * the frame is analyse(y) then forecast, and pred_out (host [n_act], owned by
+ * the caller, valid until cb fires) receives the prediction mean of phi_{k+1}.
+ * Frames of one instance run in submission order.  LETKF_EAGAIN when the
+ * instance's queue (64 frames) is full. */
+int letkf_submit_frame(letkf_handle* h, const double* y, uint64_t frame_id, double* pred_out,
+                       letkf_done_fn cb, void* user);
+
+/* Blocks until every submitted frame has completed. */
+int letkf_server_drain(letkf_server* s);
+
+/* Counters since create: frames completed, batches launched, sum of batch
+ * sizes (any pointer may be NULL). */
+int letkf_server_stats(letkf_server* s, uint64_t* frames, uint64_t* batches, uint64_t* batched_frames);
+
+/* Drains, stops the scheduler and frees host state; instance handles of the
+ * server become invalid.  The arena stays the caller's. */
+int letkf_server_destroy(letkf_server* s);
+
+/* ---- errors ------------------------------------------------------------ */
+const char* letkf_strerror(int status);
+const char* letkf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LETKF_H */

@@ -1,0 +1,85 @@
+// Device-resident descriptors shared by the runtime and the kernels.
+//
+// An instance is one resident AO filter (its ensemble, D, domain map and
+// scratch live in one workspace).  A batch is a list of instances that have
+// one frame each in the current launch sequence; kernels are launched once
+// per (padded ensemble size, storage precision) class and walk the class's
+// entries, so the frames of several instances share every launch.
+#pragma once
+#include <cstdint>
+
+namespace letkf {
+
+constexpr int kMaxBatch = 64;   // frames per batch
+constexpr int kNumClasses = 12; // 4 padded sizes (16, 32, 64, 128) x 3 precisions
+
+struct InstState {           // mutated on the device by the forecast kernel
+  int32_t cur;               // ring slot holding phi_k (the other holds phi_{k-1})
+  int32_t unconverged;       // domains that hit the Jacobi sweep cap in the last analysis
+  uint64_t frame;            // forecasts done so far (Philox counter word 2..3)
+  unsigned long long sweeps; // Jacobi sweeps summed over every domain solve
+  unsigned long long solves; // domain solves
+};
+
+struct InstDesc {
+  int32_t n_act, n_sub, m, n_dom;
+  int32_t prec, flags, zrows, nnz;
+  double sigma_v;
+  double a_diag;             // (m-1)/rho
+  uint64_t seed;
+  void* ens;                 // [2][n_act][m]   storage type (double for FP64, float otherwise)
+  void* Yp;                  // [p][m]          slope perturbations D X'_phi
+  double* d;                 // [p]             innovation y - D xbar_phi
+  void* Z;                   // [zrows][m]      per-domain analysis rows before the merge
+  const double* a1;          // [n_act]
+  const double* a2;          // [n_act]
+  const int32_t* d_rowptr;   // [p+1]
+  const int32_t* d_col;      // [nnz]
+  const double* d_val;       // [nnz]
+  const int32_t* dom;        // [n_dom][4]: est_off, e, obs_off, s  (Z rows of l start at 2*est_off)
+  const int32_t* order;      // [n_dom] domains by decreasing estimated cost
+  const int32_t* est_act;    // [sum e]
+  const int32_t* obs_row;    // [2 sum s]: slope row of each observation (x rows then y rows per domain)
+  const double* obs_r;       // [2 sum s]: taper * R^-1 of each observation
+  const int32_t* mptr;       // [n_act+1] merge CSR: covering (domain, position) entries per actuator
+  const int32_t* mrow;       // [2*entries]: Z row of the phi_k copy and of the phi_{k-1} copy
+  const double* mw;          // [entries]: merge weight
+  double* dbg;               // [n_dom][2*m*m + m] C, lambda, T (NULL unless debug)
+  int32_t* dbg_sweeps;       // [n_dom]
+  InstState* st;
+};
+
+// Entries of one class in a batch.  Prefix arrays index the flattened work of
+// the class: actuator rows, slope rows and domains of every entry.
+struct ClassBatch {
+  int32_t n;
+  int32_t inst[kMaxBatch];        // index into the instance table
+  int32_t ent[kMaxBatch];         // batch entry (position of y / outputs)
+  int32_t act_off[kMaxBatch + 1];
+  int32_t slope_off[kMaxBatch + 1];
+  int32_t dom_off[kMaxBatch + 1];
+  uint32_t done;                  // completion counter of the forecast launch (self-resetting)
+  uint32_t pad;
+};
+
+struct BatchHdr {
+  const double* y;                // slopes of every entry, entry e at y_off[e]
+  double* amean;                  // analysis means (phi_k), entry e at out_off[e]
+  double* pmean;                  // prediction means (phi_{k+1}), entry e at out_off[e]
+  int32_t y_off[kMaxBatch];
+  int32_t out_off[kMaxBatch];
+  ClassBatch cls[kNumClasses];
+};
+
+inline int class_of(int padded_m, int prec) {
+  int s = padded_m <= 16 ? 0 : padded_m <= 32 ? 1 : padded_m <= 64 ? 2 : 3;
+  return prec * 4 + s;
+}
+
+inline int padded_members(int m) {
+  int p = 16;
+  while (p < m) p *= 2;
+  return p;
+}
+
+}  // namespace letkf

@@ -1,0 +1,84 @@
+// Host-side internals shared by the runtime (runtime.cpp) and the serving
+// scheduler (server.cpp).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/letkf.h"
+#include "desc.hpp"
+
+namespace letkf {
+
+void set_error(const std::string& msg);
+int fail(int code, const std::string& msg);
+int hip_fail(hipError_t e, const char* what);
+
+#define LETKF_HIP(call)                                     \
+  do {                                                      \
+    hipError_t e_ = (call);                                 \
+    if (e_ != hipSuccess) return ::letkf::hip_fail(e_, #call); \
+  } while (0)
+
+// Byte offsets of every region of one instance workspace.
+struct Layout {
+  size_t desc, state, hdr, ens, Yp, d, Z, y, amean, pmean;
+  size_t a1, a2, rowptr, col, val, dom, order, est, obs_row, obs_r, mptr, mrow, mw;
+  size_t dbg, dbg_sweeps;
+  size_t static_begin, static_end;  // [a1, end of tables) uploaded at create
+  size_t total;
+};
+
+struct Problem {  // validated, host-side copy of the create arguments
+  int n_act = 0, n_sub = 0, m = 0, prec = 0, n_dom = 0, nnz = 0;
+  uint32_t flags = 0;
+  double sigma_v = 0, inflation = 1;
+  uint64_t seed = 0;
+  std::vector<double> a1, a2, r_inv, d_val;
+  std::vector<int32_t> d_rowptr, d_col;
+  std::vector<int32_t> est_ptr, est_act, obs_ptr, obs_sub;
+  std::vector<double> est_w, obs_taper;
+  int p() const { return 2 * n_sub; }
+  int sum_e() const { return est_ptr.back(); }
+  int sum_s() const { return obs_ptr.back(); }
+  int zrows() const { return 2 * sum_e(); }
+  size_t esize() const { return prec == LETKF_FP64 ? 8 : 4; }
+};
+
+int validate(const letkf_dims* dims, const letkf_model* model, const letkf_domain_map* map,
+             int precision, uint32_t flags, Problem& out);
+Layout make_layout(const Problem& P);
+
+// Writes the instance into `ws` (device) on `stream` and waits.  `X0` is
+// host n x m FP64.  Fills `desc` (host copy of the device descriptor).
+int upload_instance(const Problem& P, const Layout& L, char* ws, const double* X0, hipStream_t stream,
+                    InstDesc& desc);
+
+}  // namespace letkf
+
+struct letkf_handle {
+  letkf::Problem P;
+  letkf::Layout L;
+  letkf::InstDesc desc{};      // host mirror of the device descriptor
+  char* ws = nullptr;          // device workspace (caller- or arena-owned)
+  int device = 0;
+  int mpad = 16;
+  int cls = 0;
+  double* h_y = nullptr;       // pinned staging
+  double* h_out = nullptr;     // pinned staging of the output means
+  hipEvent_t y_free = nullptr; // last H2D of h_y completed
+  bool y_pending = false;
+  // kernel timing (letkf_kernel_times): 4 events per recorded call
+  bool timing = false;
+  std::vector<hipEvent_t> ev;
+  size_t ev_used = 0;              // quads recorded since the last flush
+  double ms_acc[3] = {0, 0, 0};
+  uint64_t timed_calls = 0;
+  // serving
+  letkf_server* server = nullptr;
+  int slot = -1;               // index in the server's instance table
+  size_t arena_off = 0;
+};

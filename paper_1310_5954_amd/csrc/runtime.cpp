@@ -1,0 +1,573 @@
+// C ABI of the single-instance path: validation, workspace layout, upload,
+// and the per-frame launch sequence (slopes -> analysis -> merge/forecast).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+#include "launch.hpp"
+
+namespace letkf {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+int hip_fail(hipError_t e, const char* what) {
+  g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+  return LETKF_EDEVICE;
+}
+
+static bool finite_all(const double* p, size_t n) {
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(p[i])) return false;
+  return true;
+}
+
+int validate(const letkf_dims* dims, const letkf_model* model, const letkf_domain_map* map,
+             int precision, uint32_t flags, Problem& P) {
+  if (!dims || !model || !map) return fail(LETKF_EINVAL, "null dims/model/map");
+  if (dims->n_act < 1 || dims->n_sub < 1) return fail(LETKF_EINVAL, "n_act and n_sub must be >= 1");
+  if (dims->m < 2 || dims->m > 128) return fail(LETKF_EINVAL, "m must be in [2, 128]");
+  if (precision != LETKF_FP64 && precision != LETKF_FP32 && precision != LETKF_BF16)
+    return fail(LETKF_EINVAL, "unknown precision");
+  if (flags & ~LETKF_FLAG_DEBUG) return fail(LETKF_EINVAL, "unknown flags");
+  P.n_act = dims->n_act;
+  P.n_sub = dims->n_sub;
+  P.m = dims->m;
+  P.prec = precision;
+  P.flags = flags;
+  const int n_act = P.n_act, p = 2 * P.n_sub;
+  if (!model->a1 || !model->a2 || !model->r_inv || !model->d_rowptr ||
+      (model->d_nnz > 0 && (!model->d_col || !model->d_val)))
+    return fail(LETKF_EINVAL, "null model array");
+  if (!finite_all(model->a1, n_act) || !finite_all(model->a2, n_act))
+    return fail(LETKF_EINVAL, "non-finite AR coefficients");
+  if (!std::isfinite(model->sigma_v) || model->sigma_v < 0) return fail(LETKF_EINVAL, "sigma_v must be finite and >= 0");
+  if (!std::isfinite(model->inflation) || model->inflation <= 0) return fail(LETKF_EINVAL, "inflation must be > 0");
+  for (int i = 0; i < p; ++i)
+    if (!std::isfinite(model->r_inv[i]) || model->r_inv[i] < 0) return fail(LETKF_EINVAL, "r_inv must be finite and >= 0");
+  if (model->d_nnz < 0) return fail(LETKF_EINVAL, "d_nnz < 0");
+  if (model->d_rowptr[0] != 0 || model->d_rowptr[p] != model->d_nnz)
+    return fail(LETKF_EINVAL, "D rowptr must start at 0 and end at d_nnz");
+  for (int i = 0; i < p; ++i)
+    if (model->d_rowptr[i + 1] < model->d_rowptr[i]) return fail(LETKF_EINVAL, "D rowptr not monotone");
+  for (int k = 0; k < model->d_nnz; ++k) {
+    if (model->d_col[k] < 0 || model->d_col[k] >= n_act) return fail(LETKF_EINVAL, "D column out of range");
+    if (!std::isfinite(model->d_val[k])) return fail(LETKF_EINVAL, "non-finite D value");
+  }
+  P.sigma_v = model->sigma_v;
+  P.inflation = model->inflation;
+  P.seed = model->seed;
+  P.nnz = model->d_nnz;
+  P.a1.assign(model->a1, model->a1 + n_act);
+  P.a2.assign(model->a2, model->a2 + n_act);
+  P.r_inv.assign(model->r_inv, model->r_inv + p);
+  P.d_rowptr.assign(model->d_rowptr, model->d_rowptr + p + 1);
+  P.d_col.assign(model->d_col, model->d_col + P.nnz);
+  P.d_val.assign(model->d_val, model->d_val + P.nnz);
+
+  const int L = map->n_domains;
+  if (L < 1) return fail(LETKF_EINVAL, "n_domains must be >= 1");
+  if (!map->est_ptr || !map->est_act || !map->est_w || !map->obs_ptr ||
+      (map->obs_ptr && map->obs_ptr[L] > 0 && (!map->obs_sub || !map->obs_taper)))
+    return fail(LETKF_EINVAL, "null domain-map array");
+  if (map->est_ptr[0] != 0 || map->obs_ptr[0] != 0) return fail(LETKF_EINVAL, "map CSR must start at 0");
+  std::vector<double> wsum(n_act, 0.0);
+  for (int l = 0; l < L; ++l) {
+    const int e = map->est_ptr[l + 1] - map->est_ptr[l];
+    const int s = map->obs_ptr[l + 1] - map->obs_ptr[l];
+    if (e < 1) return fail(LETKF_EINVAL, "domain " + std::to_string(l) + " has no actuator");
+    if (s < 0) return fail(LETKF_EINVAL, "obs_ptr not monotone");
+    for (int q = map->est_ptr[l]; q < map->est_ptr[l + 1]; ++q) {
+      const int a = map->est_act[q];
+      if (a < 0 || a >= n_act) return fail(LETKF_EINVAL, "est_act out of range");
+      if (!std::isfinite(map->est_w[q]) || map->est_w[q] < 0) return fail(LETKF_EINVAL, "bad merge weight");
+      wsum[a] += map->est_w[q];
+    }
+    for (int q = map->obs_ptr[l]; q < map->obs_ptr[l + 1]; ++q) {
+      if (map->obs_sub[q] < 0 || map->obs_sub[q] >= P.n_sub) return fail(LETKF_EINVAL, "obs_sub out of range");
+      const double t = map->obs_taper[q];
+      if (!(t >= 0.0 && t <= 1.0)) return fail(LETKF_EINVAL, "taper must be in [0, 1]");
+    }
+  }
+  for (int a = 0; a < n_act; ++a)
+    if (std::fabs(wsum[a] - 1.0) > 1e-9)
+      return fail(LETKF_EINVAL, "merge weights of actuator " + std::to_string(a) + " do not sum to 1");
+  P.n_dom = L;
+  P.est_ptr.assign(map->est_ptr, map->est_ptr + L + 1);
+  P.obs_ptr.assign(map->obs_ptr, map->obs_ptr + L + 1);
+  P.est_act.assign(map->est_act, map->est_act + P.est_ptr[L]);
+  P.est_w.assign(map->est_w, map->est_w + P.est_ptr[L]);
+  P.obs_sub.assign(map->obs_sub, map->obs_sub + P.obs_ptr[L]);
+  P.obs_taper.assign(map->obs_taper, map->obs_taper + P.obs_ptr[L]);
+  return LETKF_OK;
+}
+
+Layout make_layout(const Problem& P) {
+  Layout L{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    off = (off + 255) & ~size_t(255);
+    const size_t o = off;
+    off += bytes;
+    return o;
+  };
+  const size_t es = P.esize();
+  const size_t m = P.m, n_act = P.n_act, p = P.p();
+  L.desc = take(sizeof(InstDesc));
+  L.state = take(sizeof(InstState));
+  L.hdr = take(sizeof(BatchHdr));
+  L.ens = take(2 * n_act * m * es);
+  L.Yp = take(p * m * es);
+  L.d = take(p * 8);
+  L.Z = take((size_t)P.zrows() * m * es);
+  L.y = take(p * 8);
+  L.amean = take(n_act * 8);
+  L.pmean = take(n_act * 8);
+  L.static_begin = off = (off + 255) & ~size_t(255);
+  L.a1 = take(n_act * 8);
+  L.a2 = take(n_act * 8);
+  L.rowptr = take((p + 1) * 4);
+  L.col = take((size_t)P.nnz * 4);
+  L.val = take((size_t)P.nnz * 8);
+  L.dom = take((size_t)P.n_dom * 16);
+  L.order = take((size_t)P.n_dom * 4);
+  L.est = take((size_t)P.sum_e() * 4);
+  L.obs_row = take((size_t)2 * P.sum_s() * 4);
+  L.obs_r = take((size_t)2 * P.sum_s() * 8);
+  L.mptr = take((n_act + 1) * 4);
+  L.mrow = take((size_t)2 * P.sum_e() * 4);
+  L.mw = take((size_t)P.sum_e() * 8);
+  L.static_end = off;
+  if (P.flags & LETKF_FLAG_DEBUG) {
+    L.dbg = take((size_t)P.n_dom * (2 * m * m + m) * 8);
+    L.dbg_sweeps = take((size_t)P.n_dom * 4);
+  } else {
+    L.dbg = L.dbg_sweeps = 0;
+  }
+  L.total = (off + 255) & ~size_t(255);
+  return L;
+}
+
+template <typename T>
+static void put(std::vector<char>& blob, size_t base, size_t off, const T* src, size_t n) {
+  if (n) std::memcpy(blob.data() + (off - base), src, n * sizeof(T));
+}
+
+int upload_instance(const Problem& P, const Layout& L, char* ws, const double* X0, hipStream_t stream,
+                    InstDesc& D) {
+  const int n_act = P.n_act, m = P.m, p = P.p();
+  const size_t es = P.esize();
+  // ---- static tables
+  std::vector<char> blob(L.static_end - L.static_begin, 0);
+  const size_t B = L.static_begin;
+  put(blob, B, L.a1, P.a1.data(), n_act);
+  put(blob, B, L.a2, P.a2.data(), n_act);
+  put(blob, B, L.rowptr, P.d_rowptr.data(), p + 1);
+  put(blob, B, L.col, P.d_col.data(), P.nnz);
+  put(blob, B, L.val, P.d_val.data(), P.nnz);
+  std::vector<int32_t> dom(4 * P.n_dom), order(P.n_dom);
+  for (int l = 0; l < P.n_dom; ++l) {
+    dom[4 * l] = P.est_ptr[l];
+    dom[4 * l + 1] = P.est_ptr[l + 1] - P.est_ptr[l];
+    dom[4 * l + 2] = P.obs_ptr[l];
+    dom[4 * l + 3] = P.obs_ptr[l + 1] - P.obs_ptr[l];
+  }
+  // largest work first: with one workgroup per domain the dispatcher then packs the tail
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    return dom[4 * a + 1] + dom[4 * a + 3] > dom[4 * b + 1] + dom[4 * b + 3];
+  });
+  put(blob, B, L.dom, dom.data(), dom.size());
+  put(blob, B, L.order, order.data(), order.size());
+  put(blob, B, L.est, P.est_act.data(), P.est_act.size());
+  std::vector<int32_t> obs_row(2 * P.sum_s());
+  std::vector<double> obs_r(2 * P.sum_s());
+  for (int l = 0; l < P.n_dom; ++l) {
+    const int o0 = P.obs_ptr[l], s = P.obs_ptr[l + 1] - o0;
+    for (int q = 0; q < s; ++q) {
+      const int sub = P.obs_sub[o0 + q];
+      const double t = P.obs_taper[o0 + q];
+      obs_row[2 * o0 + q] = sub;
+      obs_row[2 * o0 + s + q] = P.n_sub + sub;
+      obs_r[2 * o0 + q] = t * P.r_inv[sub];
+      obs_r[2 * o0 + s + q] = t * P.r_inv[P.n_sub + sub];
+    }
+  }
+  put(blob, B, L.obs_row, obs_row.data(), obs_row.size());
+  put(blob, B, L.obs_r, obs_r.data(), obs_r.size());
+  // merge CSR: for each actuator, the (Z row of phi_k, Z row of phi_{k-1}, weight) of every covering domain
+  std::vector<int32_t> mptr(n_act + 1, 0);
+  for (int q = 0; q < P.sum_e(); ++q) mptr[P.est_act[q] + 1]++;
+  for (int a = 0; a < n_act; ++a) mptr[a + 1] += mptr[a];
+  std::vector<int32_t> fill(mptr.begin(), mptr.end() - 1), mrow(2 * P.sum_e());
+  std::vector<double> mw(P.sum_e());
+  for (int l = 0; l < P.n_dom; ++l) {
+    const int e0 = P.est_ptr[l], e = P.est_ptr[l + 1] - e0;
+    for (int q = 0; q < e; ++q) {
+      const int a = P.est_act[e0 + q];
+      const int k = fill[a]++;
+      mrow[2 * k] = 2 * e0 + q;
+      mrow[2 * k + 1] = 2 * e0 + e + q;
+      mw[k] = P.est_w[e0 + q];
+    }
+  }
+  put(blob, B, L.mptr, mptr.data(), mptr.size());
+  put(blob, B, L.mrow, mrow.data(), mrow.size());
+  put(blob, B, L.mw, mw.data(), mw.size());
+
+  // ---- descriptor
+  std::memset(&D, 0, sizeof(D));
+  D.n_act = n_act; D.n_sub = P.n_sub; D.m = m; D.n_dom = P.n_dom;
+  D.prec = P.prec; D.flags = (int32_t)P.flags; D.zrows = P.zrows(); D.nnz = P.nnz;
+  D.sigma_v = P.sigma_v;
+  D.a_diag = (double)(m - 1) / P.inflation;
+  D.seed = P.seed;
+  D.ens = ws + L.ens; D.Yp = ws + L.Yp; D.d = (double*)(ws + L.d); D.Z = ws + L.Z;
+  D.a1 = (const double*)(ws + L.a1); D.a2 = (const double*)(ws + L.a2);
+  D.d_rowptr = (const int32_t*)(ws + L.rowptr); D.d_col = (const int32_t*)(ws + L.col);
+  D.d_val = (const double*)(ws + L.val);
+  D.dom = (const int32_t*)(ws + L.dom); D.order = (const int32_t*)(ws + L.order);
+  D.est_act = (const int32_t*)(ws + L.est);
+  D.obs_row = (const int32_t*)(ws + L.obs_row); D.obs_r = (const double*)(ws + L.obs_r);
+  D.mptr = (const int32_t*)(ws + L.mptr); D.mrow = (const int32_t*)(ws + L.mrow);
+  D.mw = (const double*)(ws + L.mw);
+  D.dbg = L.dbg ? (double*)(ws + L.dbg) : nullptr;
+  D.dbg_sweeps = L.dbg_sweeps ? (int32_t*)(ws + L.dbg_sweeps) : nullptr;
+  D.st = (InstState*)(ws + L.state);
+
+  InstState S{};
+  S.cur = 0;
+  S.frame = 0;
+  // single-entry batch header of the plain path
+  BatchHdr H;
+  std::memset(&H, 0, sizeof(H));
+  H.y = (const double*)(ws + L.y);
+  H.amean = (double*)(ws + L.amean);
+  H.pmean = (double*)(ws + L.pmean);
+  const int cls = class_of(padded_members(m), P.prec);
+  ClassBatch& cb = H.cls[cls];
+  cb.n = 1;
+  cb.inst[0] = 0;
+  cb.ent[0] = 0;
+  cb.act_off[1] = n_act;
+  cb.slope_off[1] = p;
+  cb.dom_off[1] = P.n_dom;
+
+  // ensemble: slot 0 = phi_k (rows 0..n_act-1 of X0), slot 1 = phi_{k-1}
+  std::vector<char> ens(2 * (size_t)n_act * m * es);
+  if (es == 8) std::memcpy(ens.data(), X0, ens.size());
+  else {
+    float* f = (float*)ens.data();
+    for (size_t i = 0; i < 2 * (size_t)n_act * m; ++i) f[i] = (float)X0[i];
+  }
+  LETKF_HIP(hipMemcpyAsync(ws + L.static_begin, blob.data(), blob.size(), hipMemcpyHostToDevice, stream));
+  LETKF_HIP(hipMemcpyAsync(ws + L.desc, &D, sizeof(D), hipMemcpyHostToDevice, stream));
+  LETKF_HIP(hipMemcpyAsync(ws + L.state, &S, sizeof(S), hipMemcpyHostToDevice, stream));
+  LETKF_HIP(hipMemcpyAsync(ws + L.hdr, &H, sizeof(H), hipMemcpyHostToDevice, stream));
+  LETKF_HIP(hipMemcpyAsync(ws + L.ens, ens.data(), ens.size(), hipMemcpyHostToDevice, stream));
+  if (L.dbg) LETKF_HIP(hipMemsetAsync(ws + L.dbg, 0, L.total - L.dbg, stream));
+  LETKF_HIP(hipStreamSynchronize(stream));
+  return LETKF_OK;
+}
+
+}  // namespace letkf
+
+using namespace letkf;
+
+static int check_handle(letkf_handle* h) {
+  if (!h) return fail(LETKF_EINVAL, "null handle");
+  if (hipSetDevice(h->device) != hipSuccess) return fail(LETKF_EDEVICE, "hipSetDevice failed");
+  return LETKF_OK;
+}
+
+static InstDesc* dev_desc(letkf_handle* h) { return (InstDesc*)(h->ws + h->L.desc); }
+
+static constexpr size_t kTimerQuads = 1024;
+
+static int flush_timer(letkf_handle* h) {
+  for (size_t q = 0; q < h->ev_used; ++q) {
+    hipEvent_t* e = &h->ev[4 * q];
+    LETKF_HIP(hipEventSynchronize(e[3]));
+    for (int k = 0; k < 3; ++k) {
+      float ms = 0.f;
+      LETKF_HIP(hipEventElapsedTime(&ms, e[k], e[k + 1]));
+      h->ms_acc[k] += ms;
+    }
+  }
+  h->ev_used = 0;
+  return LETKF_OK;
+}
+
+// Records event `k` (0..3) of the current timed call on stream s.
+static int mark(letkf_handle* h, int k, hipStream_t s) {
+  if (!h->timing) return LETKF_OK;
+  if (k == 0 && h->ev_used == kTimerQuads) {
+    int rc = flush_timer(h);
+    if (rc) return rc;
+  }
+  LETKF_HIP(hipEventRecord(h->ev[4 * h->ev_used + k], s));
+  if (k == 3) {
+    ++h->ev_used;
+    ++h->timed_calls;
+  }
+  return LETKF_OK;
+}
+static BatchHdr* dev_hdr(letkf_handle* h) { return (BatchHdr*)(h->ws + h->L.hdr); }
+
+extern "C" {
+
+int letkf_workspace_size(const letkf_dims* dims, const letkf_model* model, const letkf_domain_map* map,
+                         int precision, uint32_t flags, size_t* bytes) {
+  if (!bytes) return fail(LETKF_EINVAL, "null bytes");
+  Problem P;
+  int rc = validate(dims, model, map, precision, flags, P);
+  if (rc) return rc;
+  *bytes = make_layout(P).total;
+  return LETKF_OK;
+}
+
+int letkf_create(const letkf_dims* dims, const letkf_model* model, const letkf_domain_map* map,
+                 int precision, uint32_t flags, const double* X0, void* workspace, size_t workspace_bytes,
+                 void* stream, letkf_handle** out) {
+  if (!out) return fail(LETKF_EINVAL, "null out");
+  *out = nullptr;
+  auto* h = new letkf_handle();
+  int rc = validate(dims, model, map, precision, flags, h->P);
+  if (rc) { delete h; return rc; }
+  if (!X0) { delete h; return fail(LETKF_EINVAL, "null X0"); }
+  if (!finite_all(X0, 2 * (size_t)h->P.n_act * h->P.m)) { delete h; return fail(LETKF_ENUMERIC, "non-finite X0"); }
+  h->L = make_layout(h->P);
+  if (!workspace) { delete h; return fail(LETKF_EINVAL, "null workspace"); }
+  if (((uintptr_t)workspace & 255) != 0) { delete h; return fail(LETKF_EINVAL, "workspace must be 256-byte aligned"); }
+  if (workspace_bytes < h->L.total) {
+    delete h;
+    return fail(LETKF_ENOMEM, "workspace too small: need " + std::to_string(make_layout(h->P).total) + " bytes");
+  }
+  if (hipGetDevice(&h->device) != hipSuccess) { delete h; return fail(LETKF_EDEVICE, "hipGetDevice failed"); }
+  h->ws = (char*)workspace;
+  h->mpad = padded_members(h->P.m);
+  h->cls = class_of(h->mpad, h->P.prec);
+  rc = upload_instance(h->P, h->L, h->ws, X0, (hipStream_t)stream, h->desc);
+  if (!rc && hipHostMalloc((void**)&h->h_y, sizeof(double) * h->P.p()) != hipSuccess) rc = fail(LETKF_EDEVICE, "hipHostMalloc");
+  if (!rc && hipHostMalloc((void**)&h->h_out, sizeof(double) * h->P.n_act) != hipSuccess) rc = fail(LETKF_EDEVICE, "hipHostMalloc");
+  if (!rc && hipEventCreateWithFlags(&h->y_free, hipEventDisableTiming) != hipSuccess) rc = fail(LETKF_EDEVICE, "hipEventCreate");
+  if (rc) { letkf_destroy(h); return rc; }
+  *out = h;
+  return LETKF_OK;
+}
+
+int letkf_destroy(letkf_handle* h) {
+  if (!h) return LETKF_OK;
+  if (h->y_free) { hipEventSynchronize(h->y_free); hipEventDestroy(h->y_free); }
+  for (hipEvent_t e : h->ev) hipEventDestroy(e);
+  if (h->h_y) hipHostFree(h->h_y);
+  if (h->h_out) hipHostFree(h->h_out);
+  delete h;
+  return LETKF_OK;
+}
+
+// Stage y into the device y buffer of the handle (plain path).
+static int stage_y(letkf_handle* h, const double* y, int y_on_device, hipStream_t s) {
+  const size_t bytes = sizeof(double) * h->P.p();
+  double* dy = (double*)(h->ws + h->L.y);
+  if (!y) return fail(LETKF_EINVAL, "null y");
+  if (y_on_device) {
+    LETKF_HIP(hipMemcpyAsync(dy, y, bytes, hipMemcpyDeviceToDevice, s));
+    return LETKF_OK;
+  }
+  if (!finite_all(y, h->P.p())) return fail(LETKF_ENUMERIC, "non-finite slopes");
+  if (h->y_pending) LETKF_HIP(hipEventSynchronize(h->y_free));
+  std::memcpy(h->h_y, y, bytes);
+  LETKF_HIP(hipMemcpyAsync(dy, h->h_y, bytes, hipMemcpyHostToDevice, s));
+  LETKF_HIP(hipEventRecord(h->y_free, s));
+  h->y_pending = true;
+  return LETKF_OK;
+}
+
+static int read_means(letkf_handle* h, size_t off, double* out, hipStream_t s) {
+  LETKF_HIP(hipMemcpyAsync(h->h_out, h->ws + off, sizeof(double) * h->P.n_act, hipMemcpyDeviceToHost, s));
+  LETKF_HIP(hipStreamSynchronize(s));
+  std::memcpy(out, h->h_out, sizeof(double) * h->P.n_act);
+  return LETKF_OK;
+}
+
+int letkf_analyse(letkf_handle* h, const double* y, int y_on_device, double* mean_out, void* stream) {
+  int rc = check_handle(h);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  if ((rc = stage_y(h, y, y_on_device, s))) return rc;
+  if ((rc = mark(h, 0, s))) return rc;
+  launch_slopes(h->cls, h->P.p(), dev_desc(h), dev_hdr(h), s);
+  if ((rc = mark(h, 1, s))) return rc;
+  launch_analysis(h->cls, h->P.n_dom, dev_desc(h), dev_hdr(h), s);
+  if ((rc = mark(h, 2, s))) return rc;
+  launch_rows(h->cls, 0, h->P.n_act, dev_desc(h), dev_hdr(h), s);
+  if ((rc = mark(h, 3, s))) return rc;
+  LETKF_HIP(hipGetLastError());
+  if (mean_out) return read_means(h, h->L.amean, mean_out, s);
+  return LETKF_OK;
+}
+
+int letkf_forecast(letkf_handle* h, void* stream) {
+  int rc = check_handle(h);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  for (int k = 0; k < 3; ++k)
+    if ((rc = mark(h, k, s))) return rc;
+  launch_rows(h->cls, 1, h->P.n_act, dev_desc(h), dev_hdr(h), s);
+  if ((rc = mark(h, 3, s))) return rc;
+  LETKF_HIP(hipGetLastError());
+  return LETKF_OK;
+}
+
+int letkf_step(letkf_handle* h, const double* y, int y_on_device, double* pred_out, void* stream) {
+  int rc = check_handle(h);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  if ((rc = stage_y(h, y, y_on_device, s))) return rc;
+  if ((rc = mark(h, 0, s))) return rc;
+  launch_slopes(h->cls, h->P.p(), dev_desc(h), dev_hdr(h), s);
+  if ((rc = mark(h, 1, s))) return rc;
+  launch_analysis(h->cls, h->P.n_dom, dev_desc(h), dev_hdr(h), s);
+  if ((rc = mark(h, 2, s))) return rc;
+  launch_rows(h->cls, 2, h->P.n_act, dev_desc(h), dev_hdr(h), s);
+  if ((rc = mark(h, 3, s))) return rc;
+  LETKF_HIP(hipGetLastError());
+  if (pred_out) return read_means(h, h->L.pmean, pred_out, s);
+  return LETKF_OK;
+}
+
+int letkf_get_state(letkf_handle* h, double* X_out, uint64_t* frame_out, void* stream) {
+  int rc = check_handle(h);
+  if (rc) return rc;
+  if (!X_out) return fail(LETKF_EINVAL, "null X_out");
+  hipStream_t s = (hipStream_t)stream;
+  const size_t n = 2 * (size_t)h->P.n_act * h->P.m, es = h->P.esize();
+  std::vector<char> buf(n * es);
+  InstState S;
+  LETKF_HIP(hipMemcpyAsync(buf.data(), h->ws + h->L.ens, buf.size(), hipMemcpyDeviceToHost, s));
+  LETKF_HIP(hipMemcpyAsync(&S, h->ws + h->L.state, sizeof(S), hipMemcpyDeviceToHost, s));
+  LETKF_HIP(hipStreamSynchronize(s));
+  const size_t slot = (size_t)h->P.n_act * h->P.m;
+  for (int part = 0; part < 2; ++part) {
+    const size_t src = (size_t)(part == 0 ? S.cur : (S.cur ^ 1)) * slot;
+    for (size_t i = 0; i < slot; ++i)
+      X_out[part * slot + i] = es == 8 ? ((double*)buf.data())[src + i] : (double)((float*)buf.data())[src + i];
+  }
+  if (frame_out) *frame_out = S.frame;
+  return LETKF_OK;
+}
+
+int letkf_set_state(letkf_handle* h, const double* X, uint64_t frame, void* stream) {
+  int rc = check_handle(h);
+  if (rc) return rc;
+  if (!X) return fail(LETKF_EINVAL, "null X");
+  const size_t n = 2 * (size_t)h->P.n_act * h->P.m, es = h->P.esize();
+  if (!finite_all(X, n)) return fail(LETKF_ENUMERIC, "non-finite state");
+  hipStream_t s = (hipStream_t)stream;
+  std::vector<char> buf(n * es);
+  if (es == 8) std::memcpy(buf.data(), X, buf.size());
+  else for (size_t i = 0; i < n; ++i) ((float*)buf.data())[i] = (float)X[i];
+  InstState S{};
+  S.cur = 0;
+  S.frame = frame;
+  LETKF_HIP(hipMemcpyAsync(h->ws + h->L.ens, buf.data(), buf.size(), hipMemcpyHostToDevice, s));
+  LETKF_HIP(hipMemcpyAsync(h->ws + h->L.state, &S, sizeof(S), hipMemcpyHostToDevice, s));
+  LETKF_HIP(hipStreamSynchronize(s));
+  return LETKF_OK;
+}
+
+int letkf_debug_domain(letkf_handle* h, int32_t domain, double* C_out, double* lam_out, double* T_out,
+                       int32_t* sweeps_out, void* stream) {
+  int rc = check_handle(h);
+  if (rc) return rc;
+  if (!(h->P.flags & LETKF_FLAG_DEBUG)) return fail(LETKF_ESTATE, "handle created without LETKF_FLAG_DEBUG");
+  if (domain < 0 || domain >= h->P.n_dom) return fail(LETKF_EINVAL, "domain out of range");
+  hipStream_t s = (hipStream_t)stream;
+  const size_t m = h->P.m, per = 2 * m * m + m;
+  std::vector<double> buf(per);
+  int32_t sw = 0;
+  LETKF_HIP(hipMemcpyAsync(buf.data(), h->ws + h->L.dbg + domain * per * 8, per * 8, hipMemcpyDeviceToHost, s));
+  LETKF_HIP(hipMemcpyAsync(&sw, h->ws + h->L.dbg_sweeps + domain * 4, 4, hipMemcpyDeviceToHost, s));
+  LETKF_HIP(hipStreamSynchronize(s));
+  if (C_out) std::memcpy(C_out, buf.data(), m * m * 8);
+  if (lam_out) {
+    std::vector<double> lam(buf.begin() + m * m, buf.begin() + m * m + m);
+    std::sort(lam.begin(), lam.end());
+    std::memcpy(lam_out, lam.data(), m * 8);
+  }
+  if (T_out) std::memcpy(T_out, buf.data() + m * m + m, m * m * 8);
+  if (sweeps_out) *sweeps_out = sw;
+  return LETKF_OK;
+}
+
+int letkf_unconverged_domains(letkf_handle* h, int32_t* count, void* stream) {
+  int rc = check_handle(h);
+  if (rc) return rc;
+  if (!count) return fail(LETKF_EINVAL, "null count");
+  InstState S;
+  hipStream_t s = (hipStream_t)stream;
+  LETKF_HIP(hipMemcpyAsync(&S, h->ws + h->L.state, sizeof(S), hipMemcpyDeviceToHost, s));
+  LETKF_HIP(hipStreamSynchronize(s));
+  *count = S.unconverged;
+  return LETKF_OK;
+}
+
+int letkf_kernel_times(letkf_handle* h, int enable, double* ms_out, uint64_t* frames_out) {
+  int rc = check_handle(h);
+  if (rc) return rc;
+  if (h->timing && (rc = flush_timer(h))) return rc;
+  if (ms_out)
+    for (int k = 0; k < 3; ++k) ms_out[k] = h->ms_acc[k];
+  if (frames_out) *frames_out = h->timed_calls;
+  if (enable) {
+    if (h->ev.empty()) {
+      h->ev.resize(4 * kTimerQuads, nullptr);
+      for (auto& e : h->ev) LETKF_HIP(hipEventCreate(&e));
+    }
+    h->ms_acc[0] = h->ms_acc[1] = h->ms_acc[2] = 0.0;
+    h->timed_calls = 0;
+    h->ev_used = 0;
+  }
+  h->timing = enable != 0;
+  return LETKF_OK;
+}
+
+int letkf_sweep_stats(letkf_handle* h, uint64_t* sweeps, uint64_t* domain_solves, void* stream) {
+  int rc = check_handle(h);
+  if (rc) return rc;
+  InstState S;
+  hipStream_t s = (hipStream_t)stream;
+  LETKF_HIP(hipMemcpyAsync(&S, h->ws + h->L.state, sizeof(S), hipMemcpyDeviceToHost, s));
+  LETKF_HIP(hipStreamSynchronize(s));
+  if (sweeps) *sweeps = S.sweeps;
+  if (domain_solves) *domain_solves = S.solves;
+  return LETKF_OK;
+}
+
+const char* letkf_strerror(int status) {
+  switch (status) {
+    case LETKF_OK: return "ok";
+    case LETKF_EINVAL: return "invalid argument";
+    case LETKF_ENOMEM: return "not enough workspace / HBM budget";
+    case LETKF_EAGAIN: return "no free slot, try again";
+    case LETKF_EDEVICE: return "HIP runtime error";
+    case LETKF_ENUMERIC: return "non-finite input or eigensolver failure";
+    case LETKF_ESTATE: return "call not valid in this state";
+    default: return "unknown status";
+  }
+}
+
+const char* letkf_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

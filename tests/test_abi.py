@@ -1,0 +1,110 @@
+"""The C ABI library loads, exports every declared symbol, and validates its
+arguments on the host before any device work (CPU only)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1310_5954_amd import _lib as L
+from paper_1310_5954_amd.api import Problem
+from workload.configs import build_case
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "letkf.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(letkf_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = L.lib()
+    names = _declared()
+    assert "letkf_create" in names and "letkf_submit_frame" in names
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def _problem(**over):
+    case = build_case(1)
+    kw = dict(n_act=case.n_act, n_sub=case.n_sub, m=case.m, a1=case.a1, a2=case.a2, sigma_v=case.sigma_v,
+              r_inv=case.r_inv, d_rowptr=case.D.rowptr, d_col=case.D.col, d_val=case.D.val,
+              est_ptr=case.dmap.est_ptr, est_act=case.dmap.est_act, est_w=case.dmap.est_w,
+              obs_ptr=case.dmap.obs_ptr, obs_sub=case.dmap.obs_sub, obs_taper=case.dmap.obs_taper)
+    kw.update(over)
+    return Problem(**kw)
+
+
+def test_workspace_size_grows_with_precision_and_debug():
+    pr = _problem()
+    s64 = pr.workspace_size(L.FP64)
+    s32 = pr.workspace_size(L.FP32)
+    sdbg = pr.workspace_size(L.FP64, L.FLAG_DEBUG)
+    assert 0 < s32 < s64 < sdbg
+    assert s64 % 256 == 0
+
+
+@pytest.mark.parametrize("over,needle", [
+    (dict(m=1), "m must be"),
+    (dict(m=129), "m must be"),
+    (dict(n_act=0), "n_act"),
+    (dict(sigma_v=-1.0), "sigma_v"),
+    (dict(inflation=0.0), "inflation"),
+])
+def test_invalid_dims_and_model_rejected(over, needle):
+    pr = _problem(**over)
+    b = C.c_size_t()
+    rc = L.lib().letkf_workspace_size(C.byref(pr.dims), C.byref(pr.model), C.byref(pr.map), L.FP64, 0, C.byref(b))
+    assert rc == L.EINVAL
+    assert needle in L.lib().letkf_last_error().decode()
+
+
+def test_invalid_map_rejected():
+    case = build_case(1)
+    w = case.dmap.est_w.copy()
+    w[0] = 0.5                      # weights of actuator no longer sum to 1
+    pr = _problem(est_w=w)
+    b = C.c_size_t()
+    assert L.lib().letkf_workspace_size(C.byref(pr.dims), C.byref(pr.model), C.byref(pr.map), L.FP64, 0,
+                                        C.byref(b)) == L.EINVAL
+    sub = case.dmap.obs_sub.copy()
+    sub[3] = case.n_sub + 5         # out of range
+    pr = _problem(obs_sub=sub)
+    assert L.lib().letkf_workspace_size(C.byref(pr.dims), C.byref(pr.model), C.byref(pr.map), L.FP64, 0,
+                                        C.byref(b)) == L.EINVAL
+    col = case.D.col.copy()
+    col[0] = -1
+    pr = _problem(d_col=col)
+    assert L.lib().letkf_workspace_size(C.byref(pr.dims), C.byref(pr.model), C.byref(pr.map), L.FP64, 0,
+                                        C.byref(b)) == L.EINVAL
+
+
+def test_bad_precision_and_flags_rejected():
+    pr = _problem()
+    b = C.c_size_t()
+    assert L.lib().letkf_workspace_size(C.byref(pr.dims), C.byref(pr.model), C.byref(pr.map), 7, 0,
+                                        C.byref(b)) == L.EINVAL
+    assert L.lib().letkf_workspace_size(C.byref(pr.dims), C.byref(pr.model), C.byref(pr.map), 0, 0x80,
+                                        C.byref(b)) == L.EINVAL
+
+
+def test_create_rejects_small_workspace_before_device_work():
+    pr = _problem()
+    h = C.c_void_p()
+    X0 = np.zeros((pr.n, pr.m))
+    rc = L.lib().letkf_create(C.byref(pr.dims), C.byref(pr.model), C.byref(pr.map), L.FP64, 0,
+                              X0.ctypes.data_as(C.POINTER(C.c_double)), C.c_void_p(256), 1024, None, C.byref(h))
+    assert rc == L.ENOMEM and not h.value
+    X0[0, 0] = np.nan
+    rc = L.lib().letkf_create(C.byref(pr.dims), C.byref(pr.model), C.byref(pr.map), L.FP64, 0,
+                              X0.ctypes.data_as(C.POINTER(C.c_double)), C.c_void_p(256), 1 << 40, None, C.byref(h))
+    assert rc == L.ENUMERIC
+
+
+def test_strerror_covers_codes():
+    for code in (L.OK, L.EINVAL, L.ENOMEM, L.EAGAIN, L.EDEVICE, L.ENUMERIC, L.ESTATE):
+        assert L.lib().letkf_strerror(code)

@@ -1,0 +1,175 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Single-step protocol: the oracle is fed the GPU's own input ensemble, slopes
+and frame counter, so rounding never compounds; errors are normwise relative
+per result (analysis mean, analysis perturbations, forecast ensemble, and
+per domain C, lambda, T).  Bounds: FP64 1e-10, FP32 1e-4.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1310_5954_amd import FP32, FP64, Filter, LetkfError, Problem
+from workload.configs import build_case
+from workload.geometry import (DomainMap, build_geometry, fried_slope_matrix, global_domain, window_domains)
+
+from _helpers import oracle_spin_up, rel, result_errors, sparse_D
+
+pytestmark = pytest.mark.gpu
+
+TOL = {FP64: 1e-10, FP32: 1e-4}
+
+
+def _check_step(case, X, k, precision, debug=False, dmap=None, check_domains=None):
+    """Load X at frame k, analyse y_k, compare; forecast, compare."""
+    dm = dmap if dmap is not None else case.dmap
+    f = Filter(Problem.from_case(case, dmap=dm), X, precision=precision, debug=debug)
+    f.set_state(X, frame=k)
+    Xg, fr = f.get_state()
+    assert fr == k
+    y = case.slopes(k)
+    D = sparse_D(case)
+    mean = f.analyse(y, mean=True)
+    Xa_g, _ = f.get_state()
+    Xa_o, doms = oracle.analysis(Xg, y, D, dm, case.r_inv, case.inflation, keep_domains=True)
+    f.forecast()
+    Xf_g, fr2 = f.get_state()
+    assert fr2 == k + 1
+    Xf_o = oracle.forecast(Xa_g, case.a1, case.a2, case.sigma_v, case.philox_seed, k)
+    err = result_errors(Xa_g, Xa_o, Xf_g, Xf_o)
+    err["amean_out"] = rel(mean, Xa_o[:case.n_act].mean(axis=1))
+    tol = TOL[precision]
+    assert max(err.values()) < tol, err
+    assert f.unconverged() == 0
+    if debug:
+        worst = dict(C=0.0, lam=0.0, T=0.0)
+        for l in (check_domains if check_domains is not None else range(dm.n_domains)):
+            g = f.debug_domain(l)
+            o = doms[l]
+            worst["C"] = max(worst["C"], rel(g["C"], o["C"]))
+            worst["lam"] = max(worst["lam"], rel(g["lam"], o["lam"]))
+            worst["T"] = max(worst["T"], rel(g["T"], o["T"]))
+            assert 1 <= g["sweeps"] < 40
+        assert max(worst.values()) < tol, worst
+    f.close()
+    return err
+
+
+def test_cfg1_fp64_single_step_and_intermediates():
+    case = build_case(1)
+    X, k = oracle_spin_up(case, 4)
+    _check_step(case, X, k, FP64, debug=True)
+
+
+def test_cfg1_fp64_first_frame_from_X0():
+    case = build_case(1)
+    _check_step(case, case.X0, 0, FP64, debug=True)
+
+
+def test_cfg1_fp64_trajectory_single_step_parity():
+    """20 frames of the plain path (letkf_step); each frame checked against the
+    oracle fed the GPU's input state."""
+    case = build_case(1)
+    D = sparse_D(case)
+    f = Filter(Problem.from_case(case), case.X0, precision=FP64)
+    worst = {}
+    for k in range(20):
+        Xin, fr = f.get_state()
+        assert fr == k
+        y = case.slopes(k)
+        pred = f.step(y, pred=True)
+        Xout, _ = f.get_state()
+        Xa_o = oracle.analysis(Xin, y, D, case.dmap, case.r_inv)
+        Xf_o = oracle.forecast(Xa_o, case.a1, case.a2, case.sigma_v, case.philox_seed, k)
+        e = dict(forecast=rel(Xout, Xf_o), pred=rel(pred, Xf_o[:case.n_act].mean(axis=1)))
+        for kk, v in e.items():
+            worst[kk] = max(worst.get(kk, 0.0), v)
+    assert max(worst.values()) < 1e-10, worst
+
+
+@pytest.mark.parametrize("m", [2, 5, 16, 33, 100, 128])
+def test_ensemble_sizes_and_padding_fp64(m):
+    """Non-power-of-two m is padded to 16/32/64/128 inside the kernel."""
+    case = build_case(1, m=m)
+    X, k = oracle_spin_up(case, 2)
+    _check_step(case, X, k, FP64, debug=True)
+
+
+def test_global_domain_many_chunks_fp64():
+    """One domain holding the whole 15x15 pupil: 450 observation rows and
+    512 state rows stream through the LDS chunks."""
+    case = build_case(1, global_map=True)
+    X, k = oracle_spin_up(case, 2)
+    _check_step(case, X, k, FP64, debug=True)
+
+
+def test_domain_without_observations_is_identity():
+    """A domain whose observation region is empty keeps its forecast rows."""
+    case = build_case(1)
+    dm = case.dmap
+    s = np.diff(dm.obs_ptr).copy()
+    s[5] = 0                                  # drop the observations of domain 5
+    keep = np.concatenate([dm.obs(l) if l != 5 else np.zeros(0, np.int32) for l in range(dm.n_domains)])
+    tap = np.concatenate([dm.taper(l) if l != 5 else np.zeros(0) for l in range(dm.n_domains)])
+    dm2 = DomainMap(dm.est_ptr, dm.est_act, dm.est_w, np.concatenate([[0], np.cumsum(s)]).astype(np.int32),
+                    keep.astype(np.int32), tap)
+    X, k = oracle_spin_up(case, 2)
+    _check_step(case, X, k, FP64, debug=True, dmap=dm2)
+
+
+def test_ragged_overlapping_map_fp64():
+    """Circular pupil, overlapping windows clipped at the edge (1..25
+    actuators), Gaspari-Cohn taper, weighted merge."""
+    cfg = dict(build_case(2).cfg)
+    cfg.update(lenslets=16)
+    case = build_case(cfg)
+    X, k = oracle_spin_up(case, 2)
+    _check_step(case, X, k, FP64, debug=True)
+
+
+def test_cfg2_fp32_single_step():
+    case = build_case(2)
+    X, k = oracle_spin_up(case, 3)
+    _check_step(case, X, k, FP32)
+
+
+def test_cfg3_full_size_fp64():
+    """84x84 pupil, m = 64, 375 domains: every domain and row compared."""
+    case = build_case(3)
+    X, k = oracle_spin_up(case, 2)
+    _check_step(case, X, k, FP64, debug=True, check_domains=range(0, case.dmap.n_domains, 7))
+
+
+def test_cfg3_full_size_fp32():
+    case = build_case(3)
+    X, k = oracle_spin_up(case, 2)
+    _check_step(case, X, k, FP32)
+
+
+def test_deterministic_and_device_y():
+    """Same input twice gives bit-identical results; device and host y agree."""
+    import torch
+    case = build_case(1)
+    X, k = oracle_spin_up(case, 2)
+    y = case.slopes(k)
+    f = Filter(Problem.from_case(case), X, precision=FP64)
+    outs = []
+    for use_dev in (False, False, True):
+        f.set_state(X, frame=k)
+        yy = torch.tensor(y, dtype=torch.float64, device="cuda:0") if use_dev else y
+        f.step(yy, pred=False)
+        outs.append(f.get_state()[0])
+    assert np.array_equal(outs[0], outs[1])
+    assert np.array_equal(outs[0], outs[2])
+
+
+def test_nonfinite_slopes_rejected():
+    case = build_case(1)
+    f = Filter(Problem.from_case(case), case.X0, precision=FP64)
+    y = case.slopes(0)
+    y[3] = np.nan
+    with pytest.raises(LetkfError) as ei:
+        f.analyse(y)
+    assert ei.value.status == -5
+    # the filter is still usable afterwards
+    f.analyse(case.slopes(0))
