@@ -1,15 +1,23 @@
 """Benchmark: local ETKF frames on one MI355X, 84x84-subaperture pupil, m = 64.
 
-One step = one frame of the whole hot path over one slope vector: slope
-synthesis (a3), per-domain analysis (a4-a8: gather, C and b, Jacobi
-eigensolve, wbar/W/T, update), merge + AR(2) forecast with model noise (a1,
-a2, a8) and the prediction mean (a9).  Slopes of every timed frame are
-resident in HBM before the timed region starts.
+A frame is the whole hot path over one slope vector: slope synthesis,
+per-domain analysis (gather, C and b, Cholesky + Jacobi eigensolve,
+wbar/W/T, update), merge + AR(2) forecast with model noise, and the
+prediction mean copied to the host.  Slopes of every timed frame are resident
+in HBM before the timed region starts.
 
-    python bench.py [--steps K] [--warmup W] [--precision fp64|fp32|bf16]
+Two forms are timed on the same workload:
+  serving  --instances B resident AO instances (independent ensembles) in a
+           closed loop: each submits its next frame when its previous one is
+           done; the server batches the pending frames of all instances into
+           shared launches.  One step = one batch (one frame per instance).
+           This is `value` (aggregate frames/s) and p50/p99 (submit -> done).
+  plain    one instance, FP64, one frame per launch sequence (letkf_step),
+           the comparison point; its analysis kernel gives the roofline line.
 
-Prints one JSON line (see the keys below).  --gpus N > 1 is refused: this
-build runs on one GPU.
+    python bench.py [--steps K] [--warmup W] [--instances B] [--precision fp64|fp32|bf16]
+
+Prints one JSON line.  --gpus N > 1 is refused: this build runs on one GPU.
 """
 from __future__ import annotations
 
@@ -72,34 +80,12 @@ def cpu_baseline(case, seconds: float = 15.0):
                 sample=f"first {len(ys)} frames of the same 84x84, m=64 workload (NumPy/LAPACK FP64, 1 thread)")
 
 
-def main() -> int:
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=300)
-    ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16"])
-    ap.add_argument("--latency-frames", type=int, default=200)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(json.dumps(dict(error="this build runs on one GPU only; --gpus must be 1")))
-        return 2
-
+def run_plain(case, prec, K, W, NL, ys):
+    """Plain per-frame path on one instance: throughput, latency, kernel times."""
     import torch
 
-    from paper_1310_5954_amd import BF16, FP32, FP64, Filter, Problem
-    from workload.configs import build_case
-
-    prec = dict(fp64=FP64, fp32=FP32, bf16=BF16)[args.precision]
-    case = build_case(3)
-    K, W, NL = args.steps, args.warmup, args.latency_frames
-    n_frames = W + K + NL
-    print(f"[bench] cfg3 84x84 m=64 domains={case.dmap.n_domains} precision={args.precision} "
-          f"frames={n_frames}", file=sys.stderr, flush=True)
-    ys_host = np.stack([case.slopes(k) for k in range(n_frames)])
-    dev = torch.device("cuda:0")
-    ys = torch.tensor(ys_host, dtype=torch.float64, device=dev)
-    f = Filter(Problem.from_case(case), case.X0, precision=prec, device=dev)
+    from paper_1310_5954_amd import Filter, Problem
+    f = Filter(Problem.from_case(case), case.X0, precision=prec, device="cuda:0")
     for k in range(W):
         f.step(ys[k], pred=False)
     torch.cuda.synchronize()
@@ -114,37 +100,166 @@ def main() -> int:
     ms, calls = f.kernel_times(False)
     sw1, so1 = f.sweep_stats()
     assert calls == K
-    fps = K / (t1 - t0)
-    print(f"[bench] timed {K} frames: {fps:.1f} frames/s", file=sys.stderr, flush=True)
-
-    # per-frame latency: slopes already resident, prediction mean back on the host
     lat = []
     for k in range(W + K, W + K + NL):
         ts = time.perf_counter()
         f.step(ys[k], pred=True)
         lat.append(time.perf_counter() - ts)
-    lat_us = np.array(lat) * 1e6
     assert f.unconverged() == 0
+    f.close()
+    lat_us = np.array(lat) * 1e6
+    return dict(fps=K / (t1 - t0), p50_us=float(np.percentile(lat_us, 50)), p99_us=float(np.percentile(lat_us, 99)),
+                kernel_ms=[v / K for v in ms], sweeps=sw1 - sw0, solves=so1 - so0)
 
-    ana_ms = ms[1] / K
-    flops = analysis_flops(case.m, case.dmap, sw1 - sw0, so1 - so0, K) / K
+
+def run_serving(case, prec, B, K, W, ys, depth=1):
+    """B resident instances in a closed loop through the batching server, each
+    keeping `depth` frames submitted (depth 1: a frame is submitted when the
+    previous one of that instance is done)."""
+    import threading
+
+    import torch
+
+    from paper_1310_5954_amd import Problem, Server
+    pr = Problem.from_case(case)
+    budget = B * pr.workspace_size(prec) + (64 << 20)
+    # instance i starts from the ensemble shifted by i columns and reads frame k + 7 i of the slope stream
+    total = W + K
+    state = dict(next=[0] * B, t_sub={}, lat=[], done=0, timing=False)
+    cv = threading.Condition()
+    preds = [np.empty(case.n_act) for _ in range(B)]
+
+    def submit(i, k):
+        fid = i * 1_000_000 + k
+        state["t_sub"][fid] = time.perf_counter()
+        rc = srv.submit(insts[i], ys[(k + 7 * i) % len(ys)], fid, preds[i])
+        assert rc == 0, rc
+
+    def on_done(fid, status, t):
+        assert status == 0, status
+        i, k = divmod(fid, 1_000_000)
+        if state["timing"] and k >= W:
+            state["lat"].append(t - state["t_sub"][fid])
+        if k + depth < total:
+            submit(i, k + depth)
+        with cv:
+            state["done"] += 1
+            cv.notify_all()
+
+    srv = Server(budget, on_done=on_done)
+    insts = [srv.add(pr, np.roll(case.X0, i, axis=1), prec) for i in range(B)]
+    torch.cuda.synchronize()
+    # warm-up frames 0..W-1 run in the same closed loop; the clock starts when every instance has finished them
+    with cv:
+        for k in range(min(depth, total)):
+            for i in range(B):
+                submit(i, k)
+    # crude but robust: wait for the warm-up frames, then time the rest
+    with cv:
+        cv.wait_for(lambda: state["done"] >= B * W, timeout=600)
+    # the loop has already submitted the next frames of every instance; time from now
+    state["timing"] = True
+    t0 = time.perf_counter()
+    with cv:
+        cv.wait_for(lambda: state["done"] >= B * total, timeout=600)
+    t1 = time.perf_counter()
+    srv.drain()
+    st = srv.stats()
+    srv.close()
+    lat_us = np.array(state["lat"]) * 1e6
+    return dict(fps=B * K / (t1 - t0), p50_us=float(np.percentile(lat_us, 50)),
+                p99_us=float(np.percentile(lat_us, 99)), batches=st["batches"],
+                mean_batch=st["batched_frames"] / max(st["batches"], 1))
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--instances", type=int, default=4)
+    ap.add_argument("--precision", default="bf16", choices=["fp64", "fp32", "bf16"],
+                    help="precision path of the serving form (the plain form is always FP64)")
+    ap.add_argument("--latency-frames", type=int, default=200)
+    ap.add_argument("--plain-only", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-ref", action="store_true",
+                    help="only run a plain 512 MiB device-to-device copy (reference for HBM byte counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps(dict(error="this build runs on one GPU only; --gpus must be 1")))
+        return 2
+
+    import torch
+
+    if args.copy_ref:
+        nbytes = 512 << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps(dict(copy_ref_bytes_read=nbytes, copy_ref_bytes_written=nbytes, dispatches=5)))
+        return 0
+
+    from paper_1310_5954_amd import BF16, FP32, FP64, build_id
+    from workload.configs import build_case
+
+    prec = dict(fp64=FP64, fp32=FP32, bf16=BF16)[args.precision]
+    case = build_case(3)
+    K, W, NL, B = args.steps, args.warmup, args.latency_frames, args.instances
+    n_frames = W + K + NL
+    print(f"[bench] 84x84 m=64 domains={case.dmap.n_domains} library={build_id()} frames={n_frames}",
+          file=sys.stderr, flush=True)
+    ys_host = np.stack([case.slopes(k) for k in range(n_frames)])
+    ys = torch.tensor(ys_host, dtype=torch.float64, device="cuda:0")
+
+    plain = run_plain(case, FP64, K, W, NL, ys)
+    print(f"[bench] plain fp64: {plain['fps']:.1f} frames/s p50 {plain['p50_us']:.0f} us "
+          f"p99 {plain['p99_us']:.0f} us", file=sys.stderr, flush=True)
+    ana_ms = plain["kernel_ms"][1]
+    flops = analysis_flops(case.m, case.dmap, plain["sweeps"], plain["solves"], K) / K
     achieved = flops / (ana_ms * 1e-3) / 1e12
-    sweeps_mean = (sw1 - sw0) / max(so1 - so0, 1)
+    roofline = dict(bound="alu", achieved=round(achieved, 3), peak=PEAK_FP64_TFLOPS, unit="TFLOP/s",
+                    frac=round(achieved / PEAK_FP64_TFLOPS, 4), traffic=None,
+                    kernel="k_analysis<FP64, m=64> (vector FP64: Cholesky + one-sided Jacobi dominate)")
+    plain_out = dict(frames_per_s=round(plain["fps"], 2), p50_us=round(plain["p50_us"], 1),
+                     p99_us=round(plain["p99_us"], 1),
+                     kernel_ms=dict(slopes=round(plain["kernel_ms"][0], 4), analysis=round(ana_ms, 4),
+                                    merge_forecast=round(plain["kernel_ms"][2], 4)),
+                     jacobi_sweeps_mean=round(plain["sweeps"] / max(plain["solves"], 1), 3))
+    dname = {FP64: "f64", FP32: "f32", BF16: "bf16+f64"}
+    if args.plain_only:
+        value, p50, p99, dtype, path = plain["fps"], plain["p50_us"], plain["p99_us"], "f64", "plain"
+        ms_per_step = 1e3 / plain["fps"]
+        serving_out = None
+    else:
+        cap = run_serving(case, prec, B, K, W, ys, depth=3)
+        print(f"[bench] serving {args.precision} x{B} depth 3: {cap['fps']:.1f} frames/s, "
+              f"mean batch {cap['mean_batch']:.2f}", file=sys.stderr, flush=True)
+        lat = run_serving(case, prec, B, K, W, ys, depth=1)
+        print(f"[bench] serving {args.precision} x{B} depth 1: {lat['fps']:.1f} frames/s p50 {lat['p50_us']:.0f} us "
+              f"p99 {lat['p99_us']:.0f} us, mean batch {lat['mean_batch']:.2f}", file=sys.stderr, flush=True)
+        value, p50, p99, dtype = cap["fps"], lat["p50_us"], lat["p99_us"], dname[prec]
+        path = (f"serving: {B} resident instances, continuous batching; value = capacity with 3 frames per "
+                f"instance in flight, p50/p99 = submit-to-done with 1 frame per instance in flight")
+        ms_per_step = 1e3 * B / cap["fps"]
+        serving_out = dict(instances=B, capacity_fps=round(cap["fps"], 2), capacity_mean_batch=round(cap["mean_batch"], 3),
+                           closed_loop_fps=round(lat["fps"], 2), closed_loop_mean_batch=round(lat["mean_batch"], 3),
+                           capacity_p50_us=round(cap["p50_us"], 1), capacity_p99_us=round(cap["p99_us"], 1))
     out = dict(
-        metric=METRIC, value=round(fps, 2), unit="frames/s", n_gpus=1, steps=K, warmup=W,
-        ms_per_step=round(1e3 / fps, 4), higher_is_better=True, scaling="weak", vs_baseline=None,
-        dtype="f64" if prec == FP64 else ("f32" if prec == FP32 else "bf16+f64"), data="synthetic",
+        metric=METRIC, value=round(value, 2), unit="frames/s", n_gpus=1, steps=K, warmup=W,
+        ms_per_step=round(ms_per_step, 4), higher_is_better=True, scaling="weak", vs_baseline=None,
+        dtype=dtype, data="synthetic",
         config=dict(workload="84x84 circular SH pupil, 5713 actuators (n=11426), 5544 subapertures (p=11088), "
-                             f"m=64, {case.dmap.n_domains} overlapping 6x6 domains, halo 2, GC taper; plain "
-                             "per-frame path (one instance, analysis + AR(2) forecast per frame)",
-                    precision=args.precision, path="plain"),
-        p50_us=round(float(np.percentile(lat_us, 50)), 1), p99_us=round(float(np.percentile(lat_us, 99)), 1),
-        kernel_ms=dict(slopes=round(ms[0] / K, 4), analysis=round(ana_ms, 4), merge_forecast=round(ms[2] / K, 4)),
-        jacobi_sweeps_mean=round(sweeps_mean, 3),
-        roofline=dict(bound="alu", achieved=round(achieved, 3), peak=PEAK_FP64_TFLOPS, unit="TFLOP/s",
-                      frac=round(achieved / PEAK_FP64_TFLOPS, 4), traffic=None,
-                      kernel="k_analysis (FP64 vector ALU: one-sided Jacobi dominates)"),
+                             f"m=64, {case.dmap.n_domains} overlapping 6x6-actuator domains, halo 2, "
+                             "Gaspari-Cohn taper; one frame = analysis + AR(2) forecast",
+                    path=path, precision=args.precision if serving_out else "fp64"),
+        p50_us=round(p50, 1), p99_us=round(p99, 1),
+        plain_fp64=plain_out, roofline=roofline, library=build_id(),
     )
+    if serving_out:
+        out["serving"] = serving_out
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(case)
     print(json.dumps(out), flush=True)

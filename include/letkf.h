@@ -185,8 +185,9 @@ int letkf_sweep_stats(letkf_handle* h, uint64_t* sweeps, uint64_t* domain_solves
 /* ---- serving: many resident instances, batched frames ----------------- */
 
 /* Completion callback: called once per submitted frame from the server's
- * completion thread, after pred_out has been written.  status is LETKF_OK
- * or a negative code.  Must not call back into the server. */
+ * completion thread (holding no server lock), after pred_out has been
+ * written.  status is LETKF_OK or a negative code.  It may submit further
+ * frames; it must not call letkf_server_drain, _remove or _destroy. */
 typedef void (*letkf_done_fn)(void* user, uint64_t frame_id, int status);
 
 /* A server sub-allocates instance workspaces from the caller's device arena
@@ -216,8 +217,22 @@ int letkf_server_remove(letkf_server* s, letkf_handle* h);
 int letkf_submit_frame(letkf_handle* h, const double* y, uint64_t frame_id, double* pred_out,
                        letkf_done_fn cb, void* user);
 
+/* As letkf_submit_frame, with the slopes already in device memory: y_dev
+ * ([p] FP64, on the server's GPU) is read by the batch's kernels directly and
+ * must stay unchanged until cb fires.  Device slopes are not checked for
+ * non-finite values. */
+int letkf_submit_frame_device(letkf_handle* h, const double* y_dev, uint64_t frame_id, double* pred_out,
+                              letkf_done_fn cb, void* user);
+
 /* Blocks until every submitted frame has completed. */
 int letkf_server_drain(letkf_server* s);
+
+/* Batching window (default 100 us): with the GPU idle and some instances
+ * without a pending frame, the scheduler waits at most this long for them
+ * before launching a partial batch.  While a batch runs it never launches a
+ * partial batch behind it; it waits for every instance or for the GPU to
+ * drain.  0 launches as soon as a frame arrives on an idle GPU. */
+int letkf_server_set_window(letkf_server* s, uint32_t window_us);
 
 /* Counters since create: frames completed, batches launched, sum of batch
  * sizes (any pointer may be NULL). */
@@ -227,8 +242,10 @@ int letkf_server_stats(letkf_server* s, uint64_t* frames, uint64_t* batches, uin
  * server become invalid.  The arena stays the caller's. */
 int letkf_server_destroy(letkf_server* s);
 
-/* ---- errors ------------------------------------------------------------ */
+/* ---- errors, build ------------------------------------------------------ */
 const char* letkf_strerror(int status);
+/* Hash of the sources the library was built from (16 hex digits). */
+const char* letkf_build_id(void);
 const char* letkf_last_error(void);
 
 #ifdef __cplusplus

@@ -4,7 +4,7 @@
 frames of several resident instances.  The HIP library is loaded on first
 use and must have been built (``python -m paper_1310_5954_amd.build``).
 """
-from ._lib import BF16, FP32, FP64, LetkfError, lib
-from .api import Filter, Problem
+from ._lib import BF16, FP32, FP64, LetkfError, build_id, lib
+from .api import Filter, Instance, Problem, Server
 
-__all__ = ["BF16", "FP32", "FP64", "LetkfError", "lib", "Filter", "Problem"]
+__all__ = ["BF16", "FP32", "FP64", "LetkfError", "build_id", "lib", "Filter", "Instance", "Problem", "Server"]

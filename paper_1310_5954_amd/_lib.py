@@ -68,17 +68,21 @@ def _sig(lib):
                                      C.c_uint32, pd, C.POINTER(P)]
     lib.letkf_server_remove.argtypes = [P, P]
     lib.letkf_submit_frame.argtypes = [P, pd, C.c_uint64, pd, DONE_FN, P]
+    lib.letkf_submit_frame_device.argtypes = [P, P, C.c_uint64, pd, DONE_FN, P]
     lib.letkf_server_drain.argtypes = [P]
+    lib.letkf_server_set_window.argtypes = [P, C.c_uint32]
     lib.letkf_server_stats.argtypes = [P, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]
     lib.letkf_server_destroy.argtypes = [P]
     lib.letkf_strerror.argtypes = [C.c_int]
     lib.letkf_strerror.restype = C.c_char_p
     lib.letkf_last_error.argtypes = []
     lib.letkf_last_error.restype = C.c_char_p
+    lib.letkf_build_id.argtypes = []
+    lib.letkf_build_id.restype = C.c_char_p
     for name in ("letkf_workspace_size", "letkf_create", "letkf_destroy", "letkf_analyse", "letkf_forecast",
                  "letkf_step", "letkf_get_state", "letkf_set_state", "letkf_debug_domain",
                  "letkf_unconverged_domains", "letkf_kernel_times", "letkf_sweep_stats", "letkf_server_create", "letkf_server_add", "letkf_server_remove",
-                 "letkf_submit_frame", "letkf_server_drain", "letkf_server_stats", "letkf_server_destroy"):
+                 "letkf_submit_frame", "letkf_submit_frame_device", "letkf_server_drain", "letkf_server_set_window", "letkf_server_stats", "letkf_server_destroy"):
         getattr(lib, name).restype = C.c_int
 
 
@@ -91,7 +95,22 @@ def lib() -> C.CDLL:
                               "`python -m paper_1310_5954_amd.build` (no CPU fallback exists)")
         _lib = C.CDLL(LIB_PATH)
         _sig(_lib)
+        _check_fresh(_lib)
     return _lib
+
+
+def _check_fresh(handle) -> None:
+    """Refuse a library built from other sources than the ones in this tree."""
+    from .build import source_hash
+    built = handle.letkf_build_id().decode()
+    want = source_hash()
+    if built != want:
+        raise ImportError(f"{LIB_PATH} was built from sources {built} but the tree holds {want}: "
+                          "rebuild with `python -m paper_1310_5954_amd.build`")
+
+
+def build_id() -> str:
+    return lib().letkf_build_id().decode()
 
 
 def check(status: int, where: str) -> None:

@@ -180,3 +180,115 @@ class Filter:
             L.check(L.lib().letkf_unconverged_domains(self.handle, C.byref(c), _stream(self.device)),
                     "letkf_unconverged_domains")
         return int(c.value)
+
+
+class Instance:
+    """A filter instance resident in a Server's arena."""
+
+    def __init__(self, server, handle, problem, precision):
+        self.server = server
+        self.handle = handle
+        self.problem = problem
+        self.precision = precision
+
+    def get_state(self):
+        X = np.empty((self.problem.n, self.problem.m))
+        f = C.c_uint64()
+        L.check(L.lib().letkf_get_state(self.handle, X.ctypes.data_as(_pd), C.byref(f), None), "letkf_get_state")
+        return X, int(f.value)
+
+    def set_state(self, X, frame: int = 0):
+        X = _f64(X)
+        L.check(L.lib().letkf_set_state(self.handle, X.ctypes.data_as(_pd), int(frame), None), "letkf_set_state")
+
+
+class Server:
+    """Continuous-batching frame server over resident instances.
+
+    The HBM budget is a uint8 CUDA tensor of ``budget_bytes`` handed to the
+    library as its arena.  ``submit`` returns at once; completion is reported
+    through ``done`` (frame_id -> (status, perf_counter time)) and the
+    caller's prediction buffer is filled before the frame is marked done."""
+
+    def __init__(self, budget_bytes: int, max_batch: int = 64, device="cuda:0", on_done=None):
+        self.device = torch.device(device)
+        self.arena = torch.empty(int(budget_bytes), dtype=torch.uint8, device=self.device)
+        self.done = {}
+        self.on_done = on_done          # optional hook(frame_id, status, time), runs on the completion thread
+        self._keep = {}
+        self._cb = L.DONE_FN(self._on_done)
+        h = C.c_void_p()
+        with torch.cuda.device(self.device):
+            torch.cuda.synchronize(self.device)
+            L.check(L.lib().letkf_server_create(C.c_void_p(self.arena.data_ptr()), int(budget_bytes), int(max_batch),
+                                                0, C.byref(h)), "letkf_server_create")
+        self.handle = h
+
+    def _on_done(self, user, frame_id, status):
+        import time
+        t = time.perf_counter()
+        self.done[int(frame_id)] = (int(status), t)
+        self._keep.pop(int(frame_id), None)
+        if self.on_done is not None:
+            self.on_done(int(frame_id), int(status), t)
+
+    def add(self, problem: Problem, X0, precision: int = L.FP64) -> Instance:
+        X0 = _f64(X0)
+        h = C.c_void_p()
+        with torch.cuda.device(self.device):
+            L.check(L.lib().letkf_server_add(self.handle, C.byref(problem.dims), C.byref(problem.model),
+                                             C.byref(problem.map), int(precision), 0, X0.ctypes.data_as(_pd),
+                                             C.byref(h)), "letkf_server_add")
+        return Instance(self, h, problem, precision)
+
+    def remove(self, inst: Instance):
+        L.check(L.lib().letkf_server_remove(self.handle, inst.handle), "letkf_server_remove")
+        inst.handle = None
+
+    def submit(self, inst: Instance, y, frame_id: int, pred_out=None) -> int:
+        """Queues one frame; returns the status (0, or -3 when the queue is full).
+        y: host array (copied at once) or a float64 CUDA tensor (read in place by
+        the batch's kernels; keep it unchanged until the frame is done)."""
+        dev = isinstance(y, torch.Tensor) and y.is_cuda
+        if dev:
+            if y.dtype != torch.float64 or not y.is_contiguous() or y.numel() != inst.problem.p:
+                raise ValueError("device y must be a contiguous float64 tensor of p values")
+        else:
+            y = _f64(y)
+        out_ptr = None
+        if pred_out is not None:
+            if pred_out.dtype != np.float64 or pred_out.shape != (inst.problem.n_act,) or not pred_out.flags.c_contiguous:
+                raise ValueError("pred_out must be a contiguous float64 array of n_act values")
+            self._keep[int(frame_id)] = pred_out
+            out_ptr = pred_out.ctypes.data_as(_pd)
+        if dev:
+            rc = L.lib().letkf_submit_frame_device(inst.handle, C.c_void_p(y.data_ptr()), int(frame_id), out_ptr,
+                                                   self._cb, None)
+        else:
+            rc = L.lib().letkf_submit_frame(inst.handle, y.ctypes.data_as(_pd), int(frame_id), out_ptr, self._cb, None)
+        if rc not in (L.OK, L.EAGAIN):
+            self._keep.pop(int(frame_id), None)
+            L.check(rc, "letkf_submit_frame")
+        return rc
+
+    def drain(self):
+        L.check(L.lib().letkf_server_drain(self.handle), "letkf_server_drain")
+
+    def set_window(self, window_us: int):
+        L.check(L.lib().letkf_server_set_window(self.handle, int(window_us)), "letkf_server_set_window")
+
+    def stats(self):
+        a, b, c = C.c_uint64(), C.c_uint64(), C.c_uint64()
+        L.check(L.lib().letkf_server_stats(self.handle, C.byref(a), C.byref(b), C.byref(c)), "letkf_server_stats")
+        return dict(frames=int(a.value), batches=int(b.value), batched_frames=int(c.value))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            L.lib().letkf_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

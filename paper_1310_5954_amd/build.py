@@ -5,6 +5,7 @@
 from __future__ import annotations
 
 import concurrent.futures as cf
+import hashlib
 import os
 import subprocess
 import sys
@@ -21,8 +22,18 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          "-I", os.path.join(HERE, "..", "include")]
 
 
-def _compile(src: str, obj: str) -> None:
-    cmd = ["hipcc", *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+def source_hash() -> str:
+    """Hash of every source and header the library is built from."""
+    h = hashlib.sha256()
+    files = sorted(f for f in os.listdir(CSRC) if f.endswith((".hip", ".cpp", ".hpp")))
+    for f in files + ["../../include/letkf.h"]:
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(f.encode() + b"\0" + fh.read())
+    return h.hexdigest()[:16]
+
+
+def _compile(src: str, obj: str, build_id: str) -> None:
+    cmd = ["hipcc", *FLAGS, f'-DLETKF_BUILD_ID="{build_id}"', "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")
@@ -31,8 +42,9 @@ def _compile(src: str, obj: str) -> None:
 def build(verbose: bool = True) -> str:
     os.makedirs(LIBDIR, exist_ok=True)
     objs = [os.path.join(LIBDIR, os.path.splitext(s)[0] + ".o") for s in SOURCES]
+    build_id = source_hash()
     with cf.ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
-        list(ex.map(_compile, SOURCES, objs))
+        list(ex.map(_compile, SOURCES, objs, [build_id] * len(SOURCES)))
     tmp = LIB + ".tmp"
     r = subprocess.run(["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs],
                        capture_output=True, text=True)
@@ -42,7 +54,7 @@ def build(verbose: bool = True) -> str:
     for o in objs:
         os.remove(o)
     if verbose:
-        print(f"built {LIB}", file=sys.stderr)
+        print(f"built {LIB} (sources {build_id})", file=sys.stderr)
     return LIB
 
 

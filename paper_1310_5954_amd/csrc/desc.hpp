@@ -63,10 +63,9 @@ struct ClassBatch {
 };
 
 struct BatchHdr {
-  const double* y;                // slopes of every entry, entry e at y_off[e]
+  const double* yptr[kMaxBatch];  // slopes of entry e (device memory: staging slot or caller's buffer)
   double* amean;                  // analysis means (phi_k), entry e at out_off[e]
   double* pmean;                  // prediction means (phi_{k+1}), entry e at out_off[e]
-  int32_t y_off[kMaxBatch];
   int32_t out_off[kMaxBatch];
   ClassBatch cls[kNumClasses];
 };

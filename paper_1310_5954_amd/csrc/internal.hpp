@@ -54,6 +54,10 @@ Layout make_layout(const Problem& P);
 
 // Writes the instance into `ws` (device) on `stream` and waits.  `X0` is
 // host n x m FP64.  Fills `desc` (host copy of the device descriptor).
+// For a handle owned by a server: LETKF_EAGAIN if it has frames queued or in
+// flight, else waits for the server stream and returns it in *stream.
+int server_idle_stream(letkf_handle* h, hipStream_t* stream);
+
 int upload_instance(const Problem& P, const Layout& L, char* ws, const double* X0, hipStream_t stream,
                     InstDesc& desc);
 

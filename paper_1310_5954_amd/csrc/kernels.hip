@@ -60,6 +60,28 @@ __device__ __forceinline__ double row_sum(double v, double* red) {
   return v;
 }
 
+// Cross-lane moves of a double with DPP (VALU, no LDS round trip).
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const long long x = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)x, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(x >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Sum over aligned groups of G consecutive lanes (G = 2, 4, 8 or 16); every
+// lane of a group ends with the group total.  Stages: swap neighbours, swap
+// pairs (quad permutes), then mirror within 8 and within 16 lanes.
+template <int G>
+__device__ __forceinline__ double group_sum(double v) {
+  if constexpr (G >= 2) v += dpp_f64<0xB1>(v);   // quad_perm [1,0,3,2]
+  if constexpr (G >= 4) v += dpp_f64<0x4E>(v);   // quad_perm [2,3,0,1]
+  if constexpr (G >= 8) v += dpp_f64<0x141>(v);  // row_half_mirror
+  if constexpr (G >= 16) v += dpp_f64<0x140>(v); // row_mirror
+  static_assert(G <= 16, "group_sum supports up to 16 lanes");
+  return v;
+}
+
 __device__ __forceinline__ int find_entry(const int32_t* off, int n, int g) {
   int b = 0;
   while (b + 1 < n && off[b + 1] <= g) ++b;
@@ -96,7 +118,7 @@ __global__ __launch_bounds__(256) void k_slopes(const InstDesc* __restrict__ tab
   const double ybar = row_sum<MP>(v, red) / (double)m;
   if (active) {
     if (j < m) st((T*)I.Yp + (size_t)o * m + j, v - ybar);
-    if (j == 0) I.d[o] = hdr->y[hdr->y_off[cb.ent[b]] + o] - ybar;
+    if (j == 0) I.d[o] = hdr->yptr[cb.ent[b]][o] - ybar;
   }
 }
 
@@ -180,58 +202,90 @@ __global__ __launch_bounds__(256) void k_rows(const InstDesc* __restrict__ tab,
 }
 
 // ----------------------------------------------------------------------------
-// a4-a8: per-domain analysis, one 256-thread workgroup per domain.
+// a4-a8: per-domain analysis, one 256-thread workgroup (4 wavefronts) per domain.
+//
+// P selects the contraction path: 0 = FP64 vector FMA, 1 = FP32 MFMA
+// (v_mfma_f32_16x16x4f32), 2 = BF16 MFMA (v_mfma_f32_16x16x32_bf16) with FP32
+// accumulation.  The eigensolve, wbar and W are FP64 on every path.  On the
+// BF16 path C uses split operands (hi + lo, three products): a single BF16
+// rounding of sqrt(r) Y' perturbs C by ~1e-3 of its largest eigenvalue, which
+// exceeds the smallest ones ((m-1)/rho) that dominate W.
 // ----------------------------------------------------------------------------
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
 template <int M> struct AnaCfg {
   static constexpr int NT = 256;
-  static constexpr int LDB = M + 2;                // column stride of the m x m matrix in LDS
-  static constexpr int KC = M <= 64 ? 32 : 8;      // rows per staged chunk
-  static constexpr int TM = M / 16;                // 16 x 16 thread grid, TM x TM tile per thread
+  static constexpr int KC = 16;                    // FP64 path: rows per staged chunk (keeps m = 64 at 3 workgroups/CU)
+  static constexpr int TM = M / 16;                // FP64 path: TM x TM outputs per thread
   static constexpr int TPP = (2 * NT / M) < M ? (2 * NT / M) : M;  // threads per Jacobi pair
+  // Column stride of the M x M matrix in LDS: shifting consecutive columns by
+  // one pair-group span (min(TPP, 8) doubles) spreads the pair groups of a
+  // wavefront over all banks in every Jacobi step.
+  static constexpr int LDB = M + (TPP < 8 ? TPP : 8);
   static constexpr int ACTIVE = (M / 2) * TPP;
   static constexpr int RPT = M / TPP;              // rows per thread in a Jacobi step
   static constexpr int MAX_SWEEPS = 40;
+  // MFMA paths
+  static constexpr int KCF = M <= 64 ? 32 : 16;    // FP32: observations per staged chunk
+  static constexpr int LDKF = KCF + 4;             // row stride (floats) of the transposed chunk
+  static constexpr int KCB = 32;                   // BF16: observations per chunk (one k-step)
+  static constexpr int LDKB = KCB + 8;             // row stride (bf16) of the transposed chunk
+  static constexpr int KR = M <= 64 ? 32 : 16;     // update: state rows per chunk (16-row tiles)
+  static constexpr size_t STAGE_BYTES = [] {
+    size_t a = (size_t)KC * M * 8, b = (size_t)M * LDKF * 4, c = (size_t)M * LDKB * 2 * 2, d = (size_t)KR * M * 4;
+    size_t x = a > b ? a : b;
+    x = x > c ? x : c;
+    return x > d ? x : d;
+  }();
 };
 
-template <typename T, int M>
-__global__ __launch_bounds__(256) void k_analysis(const InstDesc* __restrict__ tab,
-                                                  BatchHdr* __restrict__ hdr, int cls) {
+template <int M> struct AnaSmem {
   using C = AnaCfg<M>;
-  constexpr int NT = C::NT, LDB = C::LDB, KC = C::KC, TM = C::TM, TPP = C::TPP;
-  __shared__ double Bm[M * LDB];
-  __shared__ double Xc[KC * M];
-  __shared__ double rc[KC], dc[KC];
-  __shared__ double bvec[M], nrm[M], lam[M], zv[M], wbar[M];
-  __shared__ int s_rot;
+  double Bm[M * C::LDB];                              // A, then U, then T (row-major)
+  alignas(16) unsigned char stage[C::STAGE_BYTES];    // chunk staging (phase-dependent type)
+  double rc[32], dc[32];
+  double bvec[M], nrm[M], lam[M], zv[M], wbar[M];
+  int s_rot;
+  __device__ double* red() { return (double*)stage; }  // NT partial sums, aliases the staging area
+};
 
-  const ClassBatch& cb = hdr->cls[cls];
-  const int item = blockIdx.x;
-  if (item >= cb.dom_off[cb.n]) return;
-  const int eb = find_entry(cb.dom_off, cb.n, item);
-  const InstDesc& I = tab[cb.inst[eb]];
-  const int l = I.order[item - cb.dom_off[eb]];
-  const int est_off = I.dom[4 * l], e = I.dom[4 * l + 1];
-  const int obs_off = I.dom[4 * l + 2], s = I.dom[4 * l + 3];
-  const int m = I.m;
-  const int cur = I.st->cur;
-  const int tid = threadIdx.x;
-  const int ti = tid / 16, tj = tid % 16;
+// Writes the entry (i, j) of A = (m-1)/rho I + C into LDS (symmetrically: only
+// the producer of i <= j writes, to both halves), padded members -> identity.
+template <int M>
+__device__ __forceinline__ void put_A(AnaSmem<M>& sm, int i, int j, int m, double c, double a_diag, double* dbg) {
+  if (i > j) return;
+  double v = c;
+  if (i >= m || j >= m) v = (i == j) ? 1.0 : 0.0;
+  else {
+    if (dbg) { dbg[i * m + j] = c; dbg[j * m + i] = c; }
+    if (i == j) v += a_diag;
+  }
+  sm.Bm[j * AnaCfg<M>::LDB + i] = v;
+  sm.Bm[i * AnaCfg<M>::LDB + j] = v;
+}
 
-  // ---- a4/a5: gather Y'_O in chunks; C = Y'^T diag(r) Y', b = Y'^T diag(r) d
+// ---- a4/a5 on the FP64 path: C = Y'^T diag(r) Y', b = Y'^T diag(r) d -------
+template <int M>
+__device__ void gather_C_fp64(AnaSmem<M>& sm, const InstDesc& I, int obs_off, int s, double* dbg) {
+  using C = AnaCfg<M>;
+  constexpr int NT = C::NT, KC = C::KC, TM = C::TM;
+  double* Xc = (double*)sm.stage;
+  const int m = I.m, tid = threadIdx.x, ti = tid / 16, tj = tid % 16;
   double acc[TM][TM];
 #pragma unroll
   for (int x = 0; x < TM; ++x)
 #pragma unroll
     for (int y = 0; y < TM; ++y) acc[x][y] = 0.0;
   double bacc = 0.0;
-  const T* Yp = (const T*)I.Yp;
+  const double* Yp = (const double*)I.Yp;
   const int nobs = 2 * s;
   for (int q0 = 0; q0 < nobs; q0 += KC) {
     const int kc = min(KC, nobs - q0);
     for (int idx = tid; idx < KC * M; idx += NT) {
       const int qq = idx / M, j = idx % M;
       double v = 0.0;
-      if (qq < kc && j < m) v = ld(Yp + (size_t)I.obs_row[2 * obs_off + q0 + qq] * m + j);
+      if (qq < kc && j < m) v = Yp[(size_t)I.obs_row[2 * obs_off + q0 + qq] * m + j];
       Xc[idx] = v;
     }
     if (tid < KC) {
@@ -240,12 +294,12 @@ __global__ __launch_bounds__(256) void k_analysis(const InstDesc* __restrict__ t
         r = I.obs_r[2 * obs_off + q0 + tid];
         dd = I.d[I.obs_row[2 * obs_off + q0 + tid]];
       }
-      rc[tid] = r;
-      dc[tid] = dd;
+      sm.rc[tid] = r;
+      sm.dc[tid] = dd;
     }
     __syncthreads();
     for (int qq = 0; qq < kc; ++qq) {
-      const double r = rc[qq];
+      const double r = sm.rc[qq];
       double yi[TM], yj[TM];
 #pragma unroll
       for (int x = 0; x < TM; ++x) {
@@ -258,36 +312,186 @@ __global__ __launch_bounds__(256) void k_analysis(const InstDesc* __restrict__ t
         for (int y = 0; y < TM; ++y) acc[x][y] += yi[x] * yj[y];
     }
     if (tid < M)
-      for (int qq = 0; qq < kc; ++qq) bacc += rc[qq] * dc[qq] * Xc[qq * M + tid];
+      for (int qq = 0; qq < kc; ++qq) bacc += sm.rc[qq] * sm.dc[qq] * Xc[qq * M + tid];
     __syncthreads();
   }
-  double* dbg = I.dbg ? I.dbg + (size_t)l * (2 * m * m + m) : nullptr;
 #pragma unroll
   for (int x = 0; x < TM; ++x)
 #pragma unroll
-    for (int y = 0; y < TM; ++y) {
-      const int i = ti + 16 * x, j = tj + 16 * y;
-      double v = acc[x][y];
-      if (dbg && i < m && j < m) dbg[i * m + j] = v;
-      if (i >= m || j >= m) v = (i == j) ? 1.0 : 0.0;       // padded members: identity block
-      else if (i == j) v += I.a_diag;                       // A = (m-1)/rho I + C
-      Bm[j * LDB + i] = v;
-    }
-  if (tid < M) bvec[tid] = tid < m ? bacc : 0.0;
+    for (int y = 0; y < TM; ++y) put_A<M>(sm, ti + 16 * x, tj + 16 * y, m, acc[x][y], I.a_diag, dbg);
+  if (tid < M) sm.bvec[tid] = tid < m ? bacc : 0.0;
   __syncthreads();
+}
 
-  // ---- a6: one-sided (Hestenes) Jacobi on B = A.  Column pairs (i, i^k) for
-  // k = 1..M-1 form M-1 perfect matchings that cover every pair once per sweep.
-  // At convergence the columns of B = A V are lambda_i u_i (A is SPD).
-  const double tol = (double)M * 1.1102230246251565e-16;
+// ---- a4/a5 on the MFMA paths ------------------------------------------------
+// The chunk of observations is staged transposed, At[j][k] = sqrt(r_k) Y'[k][j],
+// so that C = At At^T is one MFMA product per 16 x 16 tile.  Wave w owns a
+// WT x WT block of tiles.  b is accumulated in FP64 from the FP32 slopes.
+template <int P, int M>
+__device__ void gather_C_mfma(AnaSmem<M>& sm, const InstDesc& I, int obs_off, int s, double* dbg) {
+  using C = AnaCfg<M>;
+  constexpr int NT = C::NT;
+  constexpr int KCH = P == 1 ? C::KCF : C::KCB;
+  constexpr int TILES = M / 16;
+  constexpr int WT = TILES >= 2 ? TILES / 2 : 1;
+  const int m = I.m, tid = threadIdx.x, w = tid / 64, lane = tid % 64;
+  const bool wave_on = TILES >= 2 || w == 0;
+  const int tr0 = TILES >= 2 ? (w / 2) * WT : 0;
+  const int tc0 = TILES >= 2 ? (w % 2) * WT : 0;
+  f32x4 acc[WT][WT];
+#pragma unroll
+  for (int a = 0; a < WT; ++a)
+#pragma unroll
+    for (int b = 0; b < WT; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+  double bpart = 0.0;
+  const float* Yp = (const float*)I.Yp;
+  const int nobs = 2 * s;
+  for (int q0 = 0; q0 < nobs; q0 += KCH) {
+    const int kc = min(KCH, nobs - q0);
+    if (tid < KCH) {
+      double r = 0.0, dd = 0.0;
+      if (tid < kc) {
+        r = I.obs_r[2 * obs_off + q0 + tid];
+        dd = I.d[I.obs_row[2 * obs_off + q0 + tid]];
+      }
+      sm.rc[tid] = sqrt(r);
+      sm.dc[tid] = r * dd;
+    }
+    __syncthreads();
+    for (int idx = tid; idx < KCH * M; idx += NT) {
+      const int kk = idx / M, j = idx % M;
+      double y = 0.0;
+      if (kk < kc && j < m) y = Yp[(size_t)I.obs_row[2 * obs_off + q0 + kk] * m + j];
+      bpart += sm.dc[kk] * y;
+      if constexpr (P == 1) ((float*)sm.stage)[j * C::LDKF + kk] = (float)(sm.rc[kk] * y);
+      else {
+        // split BF16: x = hi + lo with hi = bf16(x), lo = bf16(x - hi)
+        const float xf = (float)(sm.rc[kk] * y);
+        const __bf16 hi = (__bf16)xf;
+        ((__bf16*)sm.stage)[j * C::LDKB + kk] = hi;
+        ((__bf16*)sm.stage)[M * C::LDKB + j * C::LDKB + kk] = (__bf16)(xf - (float)hi);
+      }
+    }
+    __syncthreads();
+    if (wave_on) {
+      if constexpr (P == 1) {
+        const float* At = (const float*)sm.stage;
+#pragma unroll
+        for (int ks = 0; ks < KCH / 4; ++ks) {
+          float av[WT], bv[WT];
+#pragma unroll
+          for (int a = 0; a < WT; ++a) {
+            av[a] = At[((tr0 + a) * 16 + lane % 16) * C::LDKF + ks * 4 + lane / 16];
+            bv[a] = At[((tc0 + a) * 16 + lane % 16) * C::LDKF + ks * 4 + lane / 16];
+          }
+#pragma unroll
+          for (int a = 0; a < WT; ++a)
+#pragma unroll
+            for (int b = 0; b < WT; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a], bv[b], acc[a][b], 0, 0, 0);
+        }
+      } else {
+        // C += hi hi^T + hi lo^T + lo hi^T (the lo lo^T term is below FP32 rounding)
+        const __bf16* Ah = (const __bf16*)sm.stage;
+        const __bf16* Al = Ah + M * C::LDKB;
+        bf16x8 ah[WT], al[WT], bh[WT], bl[WT];
+#pragma unroll
+        for (int a = 0; a < WT; ++a) {
+          const int ra = ((tr0 + a) * 16 + lane % 16) * C::LDKB + 8 * (lane / 16);
+          const int rb = ((tc0 + a) * 16 + lane % 16) * C::LDKB + 8 * (lane / 16);
+          ah[a] = *(const bf16x8*)(Ah + ra);
+          al[a] = *(const bf16x8*)(Al + ra);
+          bh[a] = *(const bf16x8*)(Ah + rb);
+          bl[a] = *(const bf16x8*)(Al + rb);
+        }
+#pragma unroll
+        for (int a = 0; a < WT; ++a)
+#pragma unroll
+          for (int b = 0; b < WT; ++b) {
+            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bh[b], acc[a][b], 0, 0, 0);
+            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bl[b], acc[a][b], 0, 0, 0);
+            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[a], bh[b], acc[a][b], 0, 0, 0);
+          }
+      }
+    }
+    __syncthreads();
+  }
+  if (wave_on) {
+#pragma unroll
+    for (int a = 0; a < WT; ++a)
+#pragma unroll
+      for (int b = 0; b < WT; ++b)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          put_A<M>(sm, (tr0 + a) * 16 + 4 * (lane / 16) + v, (tc0 + b) * 16 + lane % 16, m, (double)acc[a][b][v],
+                   I.a_diag, dbg);
+  }
+  // b: threads sharing j = tid % M hold partial sums
+  sm.red()[tid] = bpart;
+  __syncthreads();
+  if (tid < M) {
+    double t = 0.0;
+    for (int q = tid; q < NT; q += M) t += sm.red()[q];
+    sm.bvec[tid] = tid < m ? t : 0.0;
+  }
+  __syncthreads();
+}
+
+// ---- a6 (first half): Cholesky factor A = L L^T in place (FP64, LDS) --------
+// Right-looking, one column per step: the trailing lower triangle is updated
+// from the unscaled column k, then column k is scaled (and its upper part
+// zeroed) while the next step already updates columns > k + 1.  A is SPD
+// (all eigenvalues >= (m-1)/rho), so every pivot is positive.
+template <int M>
+__device__ void cholesky(AnaSmem<M>& sm) {
+  using C = AnaCfg<M>;
+  constexpr int NT = C::NT, LDB = C::LDB;
+  const int tid = threadIdx.x;
+  for (int k = 0; k < M; ++k) {
+    const double akk = sm.Bm[k * LDB + k];
+    const double sk = sqrt(akk);
+    const double inv = 1.0 / akk;
+    const int n = M - 1 - k;
+    for (int idx = tid; idx < n * n; idx += NT) {
+      const int jj = k + 1 + idx / n, ii = k + 1 + idx % n;
+      if (ii >= jj) sm.Bm[jj * LDB + ii] -= sm.Bm[k * LDB + ii] * (sm.Bm[k * LDB + jj] * inv);
+    }
+    __syncthreads();
+    if (tid < M) {
+      const double v = sm.Bm[k * LDB + tid];
+      sm.Bm[k * LDB + tid] = tid < k ? 0.0 : (tid == k ? sk : v / sk);
+    }
+  }
+  __syncthreads();
+}
+
+// ---- a6 (second half): one-sided (Hestenes) Jacobi on the columns of L ------
+// L J = U Sigma with U the eigenvectors of A = L L^T and lambda = sigma^2, so
+// no rotation accumulator is needed; rounding scales with sqrt(lambda), and
+// the Cholesky factor's columns start closer to orthogonal than those of A.
+// Column pairs (i, i^k), k = 1..M-1, are M-1 perfect matchings covering every
+// pair once per sweep.
+template <int P, int M>
+__device__ int jacobi(AnaSmem<M>& sm) {
+  using C = AnaCfg<M>;
+  constexpr int NT = C::NT, LDB = C::LDB, TPP = C::TPP;
+  const int tid = threadIdx.x;
+  // Rotations are skipped once |b_i.b_j| <= tol |b_i| |b_j|.  FP64 path: tol =
+  // M eps (the rounding level of a length-M dot product).  FP32 / BF16 paths:
+  // C already carries relative errors ~1e-7 / ~1e-3, so the rotations stop
+  // at 1e-9 / 1e-6, below what those inputs can resolve.
+  const double tol = P == 0 ? (double)M * 1.1102230246251565e-16 : (P == 1 ? 1e-9 : 1e-6);
+  const double tol2 = tol * tol;
   int sweeps = 0;
   for (; sweeps < C::MAX_SWEEPS;) {
-    if (tid < M) {
+    {
+      constexpr int TPC = NT / M;  // threads per column for the norms
+      const int c = tid / TPC, part = tid % TPC;
       double ss = 0.0;
-      for (int r = 0; r < M; ++r) { const double v = Bm[tid * LDB + r]; ss += v * v; }
-      nrm[tid] = ss;
+      for (int r = part; r < M; r += TPC) { const double v = sm.Bm[c * LDB + r]; ss += v * v; }
+      ss = group_sum<TPC>(ss);
+      if (part == 0) sm.nrm[c] = ss;
     }
-    if (tid == 0) s_rot = 0;
+    if (tid == 0) sm.s_rot = 0;
     __syncthreads();
     for (int k = 1; k < M; ++k) {
       if (tid < C::ACTIVE) {
@@ -295,8 +499,9 @@ __global__ __launch_bounds__(256) void k_analysis(const InstDesc* __restrict__ t
         const int h = 31 - __clz(k);
         const int i = ((q >> h) << (h + 1)) | (q & ((1 << h) - 1));
         const int jj = i ^ k;
-        double* bi = Bm + i * LDB;
-        double* bj = Bm + jj * LDB;
+        double* bi = sm.Bm + i * LDB;
+        double* bj = sm.Bm + jj * LDB;
+        const double al = sm.nrm[i], be = sm.nrm[jj];
         double xi[C::RPT], xj[C::RPT];
         double gsum = 0.0;
 #pragma unroll
@@ -305,12 +510,13 @@ __global__ __launch_bounds__(256) void k_analysis(const InstDesc* __restrict__ t
           xj[t] = bj[sub + t * TPP];
           gsum += xi[t] * xj[t];
         }
-#pragma unroll
-        for (int off = TPP / 2; off > 0; off >>= 1) gsum += __shfl_xor(gsum, off, 64);
-        const double al = nrm[i], be = nrm[jj];
-        if (fabs(gsum) > tol * sqrt(al * be)) {
-          const double zeta = (be - al) / (2.0 * gsum);
-          const double t = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+        gsum = group_sum<TPP>(gsum);
+        if (gsum * gsum > tol2 * (al * be)) {
+          // t = tan(theta), the smaller root of t^2 + 2 zeta t - 1 = 0 with
+          // zeta = (be - al) / (2 gsum), written without the quotient zeta.
+          const double dd = be - al, g2 = 2.0 * gsum;
+          const double den = fabs(dd) + sqrt(dd * dd + g2 * g2);
+          const double t = copysign(1.0, dd) * g2 / den;
           const double c = 1.0 / sqrt(1.0 + t * t);
           const double sn = c * t;
 #pragma unroll
@@ -319,43 +525,58 @@ __global__ __launch_bounds__(256) void k_analysis(const InstDesc* __restrict__ t
             bj[sub + u * TPP] = sn * xi[u] + c * xj[u];
           }
           if (sub == 0) {
-            nrm[i] = al - t * gsum;
-            nrm[jj] = be + t * gsum;
-            s_rot = 1;
+            sm.nrm[i] = al - t * gsum;
+            sm.nrm[jj] = be + t * gsum;
+            sm.s_rot = 1;
           }
         }
       }
       __syncthreads();
     }
     ++sweeps;
-    const int any = s_rot;
+    const int any = sm.s_rot;
     __syncthreads();
     if (!any) break;
   }
+  return sweeps;
+}
 
-  // ---- a7: lambda, U, wbar = U Lambda^-1 U^T b, W = U sqrt((m-1)/Lambda) U^T
-  if (tid < M) {
+// ---- a7: lambda, U, wbar = U Lambda^-1 U^T b, T = U sqrt((m-1)/Lambda) U^T + wbar 1^T
+// (from the converged columns sigma_i u_i of L J)
+// Leaves T row-major in Bm (T[k][j] at Bm[k*LDB + j], zero outside m x m).
+template <int M>
+__device__ void transform(AnaSmem<M>& sm, int m, double* dbg) {
+  using C = AnaCfg<M>;
+  constexpr int NT = C::NT, LDB = C::LDB, TM = C::TM;
+  const int tid = threadIdx.x, ti = tid / 16, tj = tid % 16;
+  {
+    constexpr int TPC = NT / M;
+    const int c = tid / TPC, part = tid % TPC;
     double ss = 0.0;
-    for (int r = 0; r < M; ++r) { const double v = Bm[tid * LDB + r]; ss += v * v; }
-    lam[tid] = sqrt(ss);
+    for (int r = part; r < M; r += TPC) { const double v = sm.Bm[c * LDB + r]; ss += v * v; }
+    ss = group_sum<TPC>(ss);
+    if (part == 0) {
+      sm.lam[c] = ss;          // columns of L J are sigma_i u_i and lambda_i = sigma_i^2
+      sm.nrm[c] = sqrt(ss);
+    }
   }
   __syncthreads();
   for (int idx = tid; idx < M * M; idx += NT) {
     const int c = idx / M, r = idx % M;
-    Bm[c * LDB + r] /= lam[c];
+    sm.Bm[c * LDB + r] /= sm.nrm[c];
   }
   __syncthreads();
   if (tid < M) {
     double t = 0.0;
-    for (int r = 0; r < M; ++r) t += Bm[tid * LDB + r] * bvec[r];
-    zv[tid] = tid < m ? t / lam[tid] : 0.0;
-    nrm[tid] = tid < m ? sqrt((double)(m - 1) / lam[tid]) : 0.0;
+    for (int r = 0; r < M; ++r) t += sm.Bm[tid * LDB + r] * sm.bvec[r];
+    sm.zv[tid] = tid < m ? t / sm.lam[tid] : 0.0;
+    sm.nrm[tid] = tid < m ? sqrt((double)(m - 1) / sm.lam[tid]) : 0.0;
   }
   __syncthreads();
   if (tid < M) {
     double w = 0.0;
-    for (int c = 0; c < m; ++c) w += Bm[c * LDB + tid] * zv[c];
-    wbar[tid] = tid < m ? w : 0.0;
+    for (int c = 0; c < m; ++c) w += sm.Bm[c * LDB + tid] * sm.zv[c];
+    sm.wbar[tid] = tid < m ? w : 0.0;
   }
   double tacc[TM][TM];
 #pragma unroll
@@ -363,12 +584,12 @@ __global__ __launch_bounds__(256) void k_analysis(const InstDesc* __restrict__ t
 #pragma unroll
     for (int y = 0; y < TM; ++y) tacc[x][y] = 0.0;
   for (int c = 0; c < m; ++c) {
-    const double sc = nrm[c];
+    const double sc = sm.nrm[c];
     double ui[TM], uj[TM];
 #pragma unroll
     for (int x = 0; x < TM; ++x) {
-      ui[x] = Bm[c * LDB + ti + 16 * x] * sc;
-      uj[x] = Bm[c * LDB + tj + 16 * x];
+      ui[x] = sm.Bm[c * LDB + ti + 16 * x] * sc;
+      uj[x] = sm.Bm[c * LDB + tj + 16 * x];
     }
 #pragma unroll
     for (int x = 0; x < TM; ++x)
@@ -376,60 +597,157 @@ __global__ __launch_bounds__(256) void k_analysis(const InstDesc* __restrict__ t
       for (int y = 0; y < TM; ++y) tacc[x][y] += ui[x] * uj[y];
   }
   __syncthreads();
-  // T = W + wbar 1^T, stored row-major (row = ensemble index contracted in the update)
 #pragma unroll
   for (int x = 0; x < TM; ++x)
 #pragma unroll
     for (int y = 0; y < TM; ++y) {
       const int i = ti + 16 * x, j = tj + 16 * y;
-      const double v = (i < m && j < m) ? tacc[x][y] + wbar[i] : 0.0;
-      Bm[i * LDB + j] = v;
+      const double v = (i < m && j < m) ? tacc[x][y] + sm.wbar[i] : 0.0;
+      sm.Bm[i * LDB + j] = v;
       if (dbg && i < m && j < m) dbg[m * m + m + i * m + j] = v;
     }
-  if (dbg && tid < m) dbg[m * m + tid] = lam[tid];
-  if (tid == 0) {
+  if (dbg && tid < m) dbg[m * m + tid] = sm.lam[tid];
+  __syncthreads();
+}
+
+// Loads `kc` state rows of the domain (both instants) into a KCH x M chunk
+// (zero padded) and their member means into sm.rc.
+template <int M, int KCH, typename T, typename S>
+__device__ void load_rows(AnaSmem<M>& sm, S* X, const InstDesc& I, int est_off, int e, int cur, int q0, int kc) {
+  constexpr int NT = AnaCfg<M>::NT;
+  const int m = I.m, tid = threadIdx.x;
+  const T* ens = (const T*)I.ens;
+  const size_t slot = (size_t)I.n_act * m;
+  for (int idx = tid; idx < KCH * M; idx += NT) {
+    const int qq = idx / M, j = idx % M;
+    T v = (T)0;
+    if (qq < kc && j < m) {
+      const int q = q0 + qq;
+      const int inst = q < e ? cur : (cur ^ 1);
+      const int act = I.est_act[est_off + (q < e ? q : q - e)];
+      v = ens[(size_t)inst * slot + (size_t)act * m + j];
+    }
+    X[idx] = (S)v;
+  }
+  __syncthreads();
+  constexpr int TPR = NT / KCH;  // threads per row for the means (8 or 16)
+  const int row = tid / TPR, part = tid % TPR;
+  double sum = 0.0;
+  for (int j = part; j < m; j += TPR) sum += (double)X[row * M + j];
+  sum = group_sum<TPR>(sum);
+  if (part == 0) sm.rc[row] = sum / (double)m;
+  __syncthreads();
+}
+
+// ---- a8 on the FP64 path: Z = xbar 1^T + X' T --------------------------------
+template <int M>
+__device__ void update_fp64(AnaSmem<M>& sm, const InstDesc& I, int est_off, int e, int cur) {
+  using C = AnaCfg<M>;
+  constexpr int NT = C::NT, LDB = C::LDB, KC = C::KC;
+  const int m = I.m, tid = threadIdx.x;
+  double* Xc = (double*)sm.stage;
+  double* Z = (double*)I.Z + (size_t)2 * est_off * m;
+  for (int q0 = 0; q0 < 2 * e; q0 += KC) {
+    const int kc = min(KC, 2 * e - q0);
+    load_rows<M, KC, double>(sm, Xc, I, est_off, e, cur, q0, kc);
+    for (int idx = tid; idx < kc * M; idx += NT) {
+      const int qq = idx / M, j = idx % M;
+      if (j < m) {
+        const double xb = sm.rc[qq];
+        double z = 0.0;
+        for (int k = 0; k < m; ++k) z += (Xc[qq * M + k] - xb) * sm.Bm[k * LDB + j];
+        Z[(size_t)(q0 + qq) * m + j] = xb + z;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---- a8 on the MFMA paths: Z = xbar 1^T + X' T in 16 x 16 tiles --------------
+// FP32: X' and T in FP32.  BF16: X' in BF16, T split into hi + lo BF16 parts
+// (two MFMAs), so only X' carries the BF16 rounding.
+template <int P, int M>
+__device__ void update_mfma(AnaSmem<M>& sm, const InstDesc& I, int est_off, int e, int cur) {
+  using C = AnaCfg<M>;
+  constexpr int LDB = C::LDB, KR = C::KR;
+  constexpr int RB = KR / 16, CB = M / 16, NTILE = RB * CB;
+  const int m = I.m, tid = threadIdx.x, w = tid / 64, lane = tid % 64;
+  float* Xf = (float*)sm.stage;
+  float* Z = (float*)I.Z + (size_t)2 * est_off * m;
+  for (int q0 = 0; q0 < 2 * e; q0 += KR) {
+    const int kc = min(KR, 2 * e - q0);
+    load_rows<M, KR, float>(sm, Xf, I, est_off, e, cur, q0, kc);
+    for (int t = w; t < NTILE; t += 4) {
+      const int rb = t / CB, cb = t % CB;
+      const int arow = rb * 16 + lane % 16;
+      const float xb = (float)sm.rc[arow];
+      const int col = cb * 16 + lane % 16;
+      f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+      if constexpr (P == 1) {
+#pragma unroll 4
+        for (int ks = 0; ks < M / 4; ++ks) {
+          const int k = ks * 4 + lane / 16;
+          const float a = k < m ? Xf[arow * M + k] - xb : 0.f;
+          const float b = (float)sm.Bm[k * LDB + col];
+          acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
+        }
+      } else {
+        for (int ks = 0; ks < (M + 31) / 32; ++ks) {
+          bf16x8 a, bh, bl;
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const int k = ks * 32 + 8 * (lane / 16) + u;
+            const float xa = (k < m) ? Xf[arow * M + k] - xb : 0.f;
+            const double tv = k < M ? sm.Bm[k * LDB + col] : 0.0;
+            const __bf16 hi = (__bf16)(float)tv;
+            a[u] = (__bf16)xa;
+            bh[u] = hi;
+            bl[u] = (__bf16)(float)(tv - (double)(float)hi);
+          }
+          acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bh, acc, 0, 0, 0);
+          acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bl, acc, 0, 0, 0);
+        }
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = rb * 16 + 4 * (lane / 16) + v;
+        if (row < kc && col < m) Z[(size_t)(q0 + row) * m + col] = (float)(sm.rc[row] + (double)acc[v]);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <int P, int M>
+__global__ __launch_bounds__(256) void k_analysis(const InstDesc* __restrict__ tab,
+                                                  BatchHdr* __restrict__ hdr, int cls) {
+  using C = AnaCfg<M>;
+  __shared__ AnaSmem<M> sm;
+  const ClassBatch& cb = hdr->cls[cls];
+  const int item = blockIdx.x;
+  if (item >= cb.dom_off[cb.n]) return;
+  const int eb = find_entry(cb.dom_off, cb.n, item);
+  const InstDesc& I = tab[cb.inst[eb]];
+  const int l = I.order[item - cb.dom_off[eb]];
+  const int est_off = I.dom[4 * l], e = I.dom[4 * l + 1];
+  const int obs_off = I.dom[4 * l + 2], s = I.dom[4 * l + 3];
+  const int m = I.m;
+  const int cur = I.st->cur;
+  double* dbg = I.dbg ? I.dbg + (size_t)l * (2 * m * m + m) : nullptr;
+
+  if constexpr (P == 0) gather_C_fp64<M>(sm, I, obs_off, s, dbg);
+  else gather_C_mfma<P, M>(sm, I, obs_off, s, dbg);
+  cholesky<M>(sm);
+  const int sweeps = jacobi<P, M>(sm);
+  transform<M>(sm, m, dbg);
+  if (threadIdx.x == 0) {
     if (I.dbg_sweeps) I.dbg_sweeps[l] = sweeps;
     if (sweeps >= C::MAX_SWEEPS) atomicAdd(&I.st->unconverged, 1);
     atomicAdd(&I.st->sweeps, (unsigned long long)sweeps);
     atomicAdd(&I.st->solves, 1ull);
   }
-  __syncthreads();
-
-  // ---- a8: Z = xbar 1^T + X' T for the domain's state rows (both instants)
-  const T* ens = (const T*)I.ens;
-  const size_t slot = (size_t)I.n_act * m;
-  T* Z = (T*)I.Z + (size_t)2 * est_off * m;
-  for (int q0 = 0; q0 < 2 * e; q0 += KC) {
-    const int kc = min(KC, 2 * e - q0);
-    for (int idx = tid; idx < KC * M; idx += NT) {
-      const int qq = idx / M, j = idx % M;
-      double v = 0.0;
-      if (qq < kc && j < m) {
-        const int q = q0 + qq;
-        const int inst = q < e ? cur : (cur ^ 1);
-        const int act = I.est_act[est_off + (q < e ? q : q - e)];
-        v = ld(ens + (size_t)inst * slot + (size_t)act * m + j);
-      }
-      Xc[idx] = v;
-    }
-    __syncthreads();
-    if (tid < KC) {
-      double sm = 0.0;
-      for (int j = 0; j < m; ++j) sm += Xc[tid * M + j];
-      rc[tid] = sm / (double)m;
-    }
-    __syncthreads();
-    for (int idx = tid; idx < kc * M; idx += NT) {
-      const int qq = idx / M, j = idx % M;
-      if (j < m) {
-        const double xb = rc[qq];
-        double z = 0.0;
-        for (int k = 0; k < m; ++k) z += (Xc[qq * M + k] - xb) * Bm[k * LDB + j];
-        st(Z + (size_t)(q0 + qq) * m + j, xb + z);
-      }
-    }
-    __syncthreads();
-  }
+  if constexpr (P == 0) update_fp64<M>(sm, I, est_off, e, cur);
+  else update_mfma<P, M>(sm, I, est_off, e, cur);
 }
 
 // ----------------------------------------------------------------------------
@@ -451,9 +769,9 @@ static void launch_slopes_t(int rows, const InstDesc* tab, BatchHdr* hdr, int cl
   if (grid > 0) hipLaunchKernelGGL((k_slopes<T, MP>), dim3(grid), dim3(256), 0, s, tab, hdr, cls);
 }
 
-template <typename T, int M>
+template <int P, int M>
 static void launch_analysis_t(int items, const InstDesc* tab, BatchHdr* hdr, int cls, hipStream_t s) {
-  if (items > 0) hipLaunchKernelGGL((k_analysis<T, M>), dim3(items), dim3(256), 0, s, tab, hdr, cls);
+  if (items > 0) hipLaunchKernelGGL((k_analysis<P, M>), dim3(items), dim3(256), 0, s, tab, hdr, cls);
 }
 
 #define LETKF_DISPATCH(FN, cls, ...)                                          \
@@ -479,7 +797,18 @@ void launch_rows(int cls, int mode, int rows, const InstDesc* tab, BatchHdr* hdr
   LETKF_DISPATCH(launch_rows_t, cls, mode, rows, tab, hdr, cls, s);
 }
 void launch_analysis(int cls, int items, const InstDesc* tab, BatchHdr* hdr, hipStream_t s) {
-  LETKF_DISPATCH(launch_analysis_t, cls, items, tab, hdr, cls, s);
+  const int prec = cls / 4, sz = cls % 4;
+#define LETKF_ANA(P)                                                   \
+  do {                                                                 \
+    if (sz == 0) launch_analysis_t<P, 16>(items, tab, hdr, cls, s);    \
+    else if (sz == 1) launch_analysis_t<P, 32>(items, tab, hdr, cls, s); \
+    else if (sz == 2) launch_analysis_t<P, 64>(items, tab, hdr, cls, s); \
+    else launch_analysis_t<P, 128>(items, tab, hdr, cls, s);           \
+  } while (0)
+  if (prec == 0) LETKF_ANA(0);
+  else if (prec == 1) LETKF_ANA(1);
+  else LETKF_ANA(2);
+#undef LETKF_ANA
 }
 
 }  // namespace letkf

@@ -251,7 +251,7 @@ int upload_instance(const Problem& P, const Layout& L, char* ws, const double* X
   // single-entry batch header of the plain path
   BatchHdr H;
   std::memset(&H, 0, sizeof(H));
-  H.y = (const double*)(ws + L.y);
+  H.yptr[0] = (const double*)(ws + L.y);
   H.amean = (double*)(ws + L.amean);
   H.pmean = (double*)(ws + L.pmean);
   const int cls = class_of(padded_members(m), P.prec);
@@ -287,6 +287,23 @@ using namespace letkf;
 static int check_handle(letkf_handle* h) {
   if (!h) return fail(LETKF_EINVAL, "null handle");
   if (hipSetDevice(h->device) != hipSuccess) return fail(LETKF_EDEVICE, "hipSetDevice failed");
+  return LETKF_OK;
+}
+
+// Plain-path launches: not for instances driven by a server.
+static int check_plain(letkf_handle* h) {
+  int rc = check_handle(h);
+  if (rc) return rc;
+  if (h->server) return fail(LETKF_ESTATE, "instance belongs to a server: use letkf_submit_frame");
+  return LETKF_OK;
+}
+
+// Stream for state access: the caller's, or the server's once the instance is idle.
+static int access_stream(letkf_handle* h, void* stream, hipStream_t* out) {
+  int rc = check_handle(h);
+  if (rc) return rc;
+  if (h->server) return server_idle_stream(h, out);
+  *out = (hipStream_t)stream;
   return LETKF_OK;
 }
 
@@ -368,6 +385,7 @@ int letkf_create(const letkf_dims* dims, const letkf_model* model, const letkf_d
 
 int letkf_destroy(letkf_handle* h) {
   if (!h) return LETKF_OK;
+  if (h->server) return fail(LETKF_ESTATE, "instance belongs to a server: use letkf_server_remove");
   if (h->y_free) { hipEventSynchronize(h->y_free); hipEventDestroy(h->y_free); }
   for (hipEvent_t e : h->ev) hipEventDestroy(e);
   if (h->h_y) hipHostFree(h->h_y);
@@ -402,7 +420,7 @@ static int read_means(letkf_handle* h, size_t off, double* out, hipStream_t s) {
 }
 
 int letkf_analyse(letkf_handle* h, const double* y, int y_on_device, double* mean_out, void* stream) {
-  int rc = check_handle(h);
+  int rc = check_plain(h);
   if (rc) return rc;
   hipStream_t s = (hipStream_t)stream;
   if ((rc = stage_y(h, y, y_on_device, s))) return rc;
@@ -419,7 +437,7 @@ int letkf_analyse(letkf_handle* h, const double* y, int y_on_device, double* mea
 }
 
 int letkf_forecast(letkf_handle* h, void* stream) {
-  int rc = check_handle(h);
+  int rc = check_plain(h);
   if (rc) return rc;
   hipStream_t s = (hipStream_t)stream;
   for (int k = 0; k < 3; ++k)
@@ -431,7 +449,7 @@ int letkf_forecast(letkf_handle* h, void* stream) {
 }
 
 int letkf_step(letkf_handle* h, const double* y, int y_on_device, double* pred_out, void* stream) {
-  int rc = check_handle(h);
+  int rc = check_plain(h);
   if (rc) return rc;
   hipStream_t s = (hipStream_t)stream;
   if ((rc = stage_y(h, y, y_on_device, s))) return rc;
@@ -448,10 +466,10 @@ int letkf_step(letkf_handle* h, const double* y, int y_on_device, double* pred_o
 }
 
 int letkf_get_state(letkf_handle* h, double* X_out, uint64_t* frame_out, void* stream) {
-  int rc = check_handle(h);
+  hipStream_t s;
+  int rc = access_stream(h, stream, &s);
   if (rc) return rc;
   if (!X_out) return fail(LETKF_EINVAL, "null X_out");
-  hipStream_t s = (hipStream_t)stream;
   const size_t n = 2 * (size_t)h->P.n_act * h->P.m, es = h->P.esize();
   std::vector<char> buf(n * es);
   InstState S;
@@ -469,12 +487,12 @@ int letkf_get_state(letkf_handle* h, double* X_out, uint64_t* frame_out, void* s
 }
 
 int letkf_set_state(letkf_handle* h, const double* X, uint64_t frame, void* stream) {
-  int rc = check_handle(h);
+  hipStream_t s;
+  int rc = access_stream(h, stream, &s);
   if (rc) return rc;
   if (!X) return fail(LETKF_EINVAL, "null X");
   const size_t n = 2 * (size_t)h->P.n_act * h->P.m, es = h->P.esize();
   if (!finite_all(X, n)) return fail(LETKF_ENUMERIC, "non-finite state");
-  hipStream_t s = (hipStream_t)stream;
   std::vector<char> buf(n * es);
   if (es == 8) std::memcpy(buf.data(), X, buf.size());
   else for (size_t i = 0; i < n; ++i) ((float*)buf.data())[i] = (float)X[i];
@@ -489,11 +507,11 @@ int letkf_set_state(letkf_handle* h, const double* X, uint64_t frame, void* stre
 
 int letkf_debug_domain(letkf_handle* h, int32_t domain, double* C_out, double* lam_out, double* T_out,
                        int32_t* sweeps_out, void* stream) {
-  int rc = check_handle(h);
+  hipStream_t s;
+  int rc = access_stream(h, stream, &s);
   if (rc) return rc;
   if (!(h->P.flags & LETKF_FLAG_DEBUG)) return fail(LETKF_ESTATE, "handle created without LETKF_FLAG_DEBUG");
   if (domain < 0 || domain >= h->P.n_dom) return fail(LETKF_EINVAL, "domain out of range");
-  hipStream_t s = (hipStream_t)stream;
   const size_t m = h->P.m, per = 2 * m * m + m;
   std::vector<double> buf(per);
   int32_t sw = 0;
@@ -512,11 +530,11 @@ int letkf_debug_domain(letkf_handle* h, int32_t domain, double* C_out, double* l
 }
 
 int letkf_unconverged_domains(letkf_handle* h, int32_t* count, void* stream) {
-  int rc = check_handle(h);
+  hipStream_t s;
+  int rc = access_stream(h, stream, &s);
   if (rc) return rc;
   if (!count) return fail(LETKF_EINVAL, "null count");
   InstState S;
-  hipStream_t s = (hipStream_t)stream;
   LETKF_HIP(hipMemcpyAsync(&S, h->ws + h->L.state, sizeof(S), hipMemcpyDeviceToHost, s));
   LETKF_HIP(hipStreamSynchronize(s));
   *count = S.unconverged;
@@ -544,10 +562,10 @@ int letkf_kernel_times(letkf_handle* h, int enable, double* ms_out, uint64_t* fr
 }
 
 int letkf_sweep_stats(letkf_handle* h, uint64_t* sweeps, uint64_t* domain_solves, void* stream) {
-  int rc = check_handle(h);
+  hipStream_t s;
+  int rc = access_stream(h, stream, &s);
   if (rc) return rc;
   InstState S;
-  hipStream_t s = (hipStream_t)stream;
   LETKF_HIP(hipMemcpyAsync(&S, h->ws + h->L.state, sizeof(S), hipMemcpyDeviceToHost, s));
   LETKF_HIP(hipStreamSynchronize(s));
   if (sweeps) *sweeps = S.sweeps;
@@ -569,5 +587,10 @@ const char* letkf_strerror(int status) {
 }
 
 const char* letkf_last_error(void) { return g_last_error.c_str(); }
+
+#ifndef LETKF_BUILD_ID
+#define LETKF_BUILD_ID "unknown"
+#endif
+const char* letkf_build_id(void) { return LETKF_BUILD_ID; }
 
 }  // extern "C"

@@ -3,13 +3,15 @@
 Single-step protocol: the oracle is fed the GPU's own input ensemble, slopes
 and frame counter, so rounding never compounds; errors are normwise relative
 per result (analysis mean, analysis perturbations, forecast ensemble, and
-per domain C, lambda, T).  Bounds: FP64 1e-10, FP32 1e-4.
+per domain C, lambda, T).  Bounds: FP64 1e-10 and FP32 1e-4 on every result;
+BF16 1e-2 on the analysis mean, with the other results bounded as stated in
+BF16_TOL (BF16 operands carry 2^-9 relative rounding).
 """
 import numpy as np
 import pytest
 
 import oracle
-from paper_1310_5954_amd import FP32, FP64, Filter, LetkfError, Problem
+from paper_1310_5954_amd import BF16, FP32, FP64, Filter, LetkfError, Problem
 from workload.configs import build_case
 from workload.geometry import (DomainMap, build_geometry, fried_slope_matrix, global_domain, window_domains)
 
@@ -17,7 +19,21 @@ from _helpers import oracle_spin_up, rel, result_errors, sparse_D
 
 pytestmark = pytest.mark.gpu
 
-TOL = {FP64: 1e-10, FP32: 1e-4}
+# Per precision and result.  Results: analysis mean, analysis perturbations,
+# forecast ensemble, analysis-mean output.  Intermediates: C, lambda, T.
+# T = [(m-1)A^-1]^(1/2) + wbar 1^T amplifies the relative rounding of C by up
+# to the conditioning of A (~1e4 here): FP32 C (~1e-7) gives T to ~1e-3 while
+# the results stay within 1e-4.
+RESULTS = ("mean", "pert", "forecast", "amean_out")
+TOLS = {
+    FP64: dict.fromkeys(RESULTS + ("C", "lam", "T"), 1e-10),
+    FP32: dict(dict.fromkeys(RESULTS, 1e-4), C=1e-6, lam=1e-6, T=2e-3),
+    BF16: dict(mean=1e-2, amean_out=1e-2, pert=5e-2, forecast=5e-2, C=1e-4, lam=1e-4, T=5e-2),
+}
+
+
+def _tol(precision, key):
+    return TOLS[precision][key]
 
 
 def _check_step(case, X, k, precision, debug=False, dmap=None, check_domains=None):
@@ -38,8 +54,8 @@ def _check_step(case, X, k, precision, debug=False, dmap=None, check_domains=Non
     Xf_o = oracle.forecast(Xa_g, case.a1, case.a2, case.sigma_v, case.philox_seed, k)
     err = result_errors(Xa_g, Xa_o, Xf_g, Xf_o)
     err["amean_out"] = rel(mean, Xa_o[:case.n_act].mean(axis=1))
-    tol = TOL[precision]
-    assert max(err.values()) < tol, err
+    for key, v in err.items():
+        assert v < _tol(precision, key), err
     assert f.unconverged() == 0
     if debug:
         worst = dict(C=0.0, lam=0.0, T=0.0)
@@ -50,7 +66,9 @@ def _check_step(case, X, k, precision, debug=False, dmap=None, check_domains=Non
             worst["lam"] = max(worst["lam"], rel(g["lam"], o["lam"]))
             worst["T"] = max(worst["T"], rel(g["T"], o["T"]))
             assert 1 <= g["sweeps"] < 40
-        assert max(worst.values()) < tol, worst
+        for key, v in worst.items():
+            assert v < _tol(precision, key), worst
+        err.update({"dom_" + k: v for k, v in worst.items()})
     f.close()
     return err
 
@@ -143,7 +161,55 @@ def test_cfg3_full_size_fp64():
 def test_cfg3_full_size_fp32():
     case = build_case(3)
     X, k = oracle_spin_up(case, 2)
-    _check_step(case, X, k, FP32)
+    _check_step(case, X, k, FP32, debug=True, check_domains=range(0, case.dmap.n_domains, 11))
+
+
+def test_cfg3_full_size_bf16():
+    """BF16 MFMA contractions, FP64 eigensolve: per-result errors."""
+    case = build_case(3)
+    X, k = oracle_spin_up(case, 2)
+    err = _check_step(case, X, k, BF16, debug=True, check_domains=range(0, case.dmap.n_domains, 11))
+    print("bf16 per-result errors:", {kk: f"{v:.2e}" for kk, v in err.items()})
+
+
+@pytest.mark.parametrize("precision", [FP32, BF16])
+@pytest.mark.parametrize("m", [5, 16, 33, 100, 128])
+def test_ensemble_sizes_mfma_paths(precision, m):
+    """MFMA tiles with padded members (m -> 16/32/64/128) on both low-precision paths."""
+    case = build_case(1, m=m)
+    X, k = oracle_spin_up(case, 2)
+    _check_step(case, X, k, precision, debug=True)
+
+
+def test_cfg2_fp32_ragged_with_intermediates():
+    case = build_case(2)
+    X, k = oracle_spin_up(case, 3)
+    _check_step(case, X, k, FP32, debug=True, check_domains=range(0, case.dmap.n_domains, 5))
+
+
+def _residual_variance(case, precision, frames, burn):
+    """Piston-removed residual phase variance of the analysis mean against the
+    truth, averaged over frames burn..frames-1."""
+    f = Filter(Problem.from_case(case), case.X0, precision=precision)
+    acc = []
+    for k in range(frames):
+        mean = f.analyse(case.slopes(k), mean=True)
+        f.forecast()
+        if k >= burn:
+            r = case.truth_phase(k) - mean
+            acc.append(np.var(r))
+    f.close()
+    return float(np.mean(acc))
+
+
+def test_cfg3_bf16_residual_variance_within_1pct_of_fp64():
+    case = build_case(3)
+    v64 = _residual_variance(case, FP64, 60, 20)
+    v16 = _residual_variance(case, BF16, 60, 20)
+    v32 = _residual_variance(case, FP32, 60, 20)
+    print(f"residual variance fp64 {v64:.5f} fp32 {v32:.5f} bf16 {v16:.5f}")
+    assert abs(v32 / v64 - 1) < 1e-3
+    assert abs(v16 / v64 - 1) < 1e-2
 
 
 def test_deterministic_and_device_y():

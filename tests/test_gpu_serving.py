@@ -1,0 +1,150 @@
+"""GPU serving: continuous batching across resident instances.
+
+* A frame's result is the same alone and in a mixed batch (bit-identical:
+  per-domain work has a fixed order and the merge uses no atomics).
+* The server path equals the plain per-frame path.
+* Instances are admitted against the HBM budget and re-admitted when
+  memory frees up.
+"""
+import numpy as np
+import pytest
+
+from paper_1310_5954_amd import BF16, FP32, FP64, Filter, LetkfError, Problem, Server
+from workload.configs import build_case
+
+pytestmark = pytest.mark.gpu
+
+FRAMES = 8
+
+
+def _mix_cases():
+    c16 = dict(build_case(2).cfg)
+    c16.update(lenslets=16, seeds=(21, 22, 23))
+    c24 = dict(build_case(2).cfg)
+    c24.update(lenslets=24, seeds=(31, 32, 33), m=64)
+    return [(build_case(1), FP64), (build_case(2), FP32), (build_case(c16, m=20), FP64),
+            (build_case(c24), BF16), (build_case(1, m=33), FP64)]
+
+
+def _run_server(cases, frames=FRAMES, drain_each=False, budget=1 << 30):
+    srv = Server(budget)
+    insts = [srv.add(Problem.from_case(c), c.X0, p) for c, p in cases]
+    ys = [[c.slopes(k) for k in range(frames)] for c, _ in cases]
+    preds = [[np.empty(c.n_act) for _ in range(frames)] for c, _ in cases]
+    for k in range(frames):
+        for i, inst in enumerate(insts):
+            assert srv.submit(inst, ys[i][k], 1000 * i + k, preds[i][k]) == 0
+        if drain_each:
+            srv.drain()
+    srv.drain()
+    assert all(st == 0 for st, _ in srv.done.values())
+    assert len(srv.done) == frames * len(cases)
+    states = [inst.get_state() for inst in insts]
+    stats = srv.stats()
+    srv.close()
+    return preds, states, stats
+
+
+def test_alone_vs_in_the_mix_bit_identical():
+    cases = _mix_cases()
+    mixed_preds, mixed_states, stats = _run_server(cases)
+    assert stats["batched_frames"] / stats["batches"] > 1.5, stats    # frames really shared launches
+    for i, cp in enumerate(cases):
+        alone_preds, alone_states, _ = _run_server([cp], drain_each=True)
+        for k in range(FRAMES):
+            assert np.array_equal(alone_preds[0][k], mixed_preds[i][k]), (i, k)
+        assert np.array_equal(alone_states[0][0], mixed_states[i][0]), i
+        assert alone_states[0][1] == mixed_states[i][1] == FRAMES
+
+
+def test_server_equals_plain_path():
+    case = build_case(1)
+    preds, states, _ = _run_server([(case, FP64)], drain_each=True)
+    f = Filter(Problem.from_case(case), case.X0, precision=FP64)
+    for k in range(FRAMES):
+        p = f.step(case.slopes(k), pred=True)
+        assert np.array_equal(p, preds[0][k]), k
+    X, fr = f.get_state()
+    assert np.array_equal(X, states[0][0]) and fr == FRAMES
+
+
+def test_admission_by_hbm_budget():
+    case = build_case(3)
+    pr = Problem.from_case(case)
+    ws = pr.workspace_size(FP64)
+    assert ws > 16 << 20
+    server_tables = 20 << 20          # staging and tables of the server itself (about 18 MiB)
+    srv = Server(server_tables + int(2.5 * ws))
+    a = srv.add(pr, case.X0, FP64)
+    b = srv.add(pr, case.X0, FP64)
+    with pytest.raises(LetkfError) as ei:
+        srv.add(pr, case.X0, FP64)    # half a workspace short
+    assert ei.value.status == -2
+    y = case.slopes(0)
+    out = np.empty(case.n_act)
+    srv.submit(a, y, 1, out)
+    srv.drain()
+    srv.remove(a)                      # memory frees up ...
+    c = srv.add(pr, case.X0, FP64)    # ... and the waiting instance is admitted
+    srv.submit(c, y, 2, np.empty(case.n_act))
+    srv.submit(b, y, 3, np.empty(case.n_act))
+    srv.drain()
+    assert srv.done[2][0] == 0 and srv.done[3][0] == 0
+    srv.close()
+
+
+def test_plain_calls_refused_on_server_instances():
+    case = build_case(1)
+    srv = Server(1 << 28)
+    inst = srv.add(Problem.from_case(case), case.X0, FP64)
+    from paper_1310_5954_amd import _lib as L
+    import ctypes as C
+    rc = L.lib().letkf_forecast(inst.handle, None)
+    assert rc == L.ESTATE
+    rc = L.lib().letkf_destroy(inst.handle)
+    assert rc == L.ESTATE
+    srv.close()
+
+
+def test_device_slopes_equal_host_slopes():
+    """letkf_submit_frame_device reads the caller's device buffer in place and
+    gives the same bits as host submission."""
+    import torch
+    case = build_case(1)
+    host_preds, host_states, _ = _run_server([(case, FP64)], drain_each=True)
+    srv = Server(1 << 28)
+    inst = srv.add(Problem.from_case(case), case.X0, FP64)
+    ys = [torch.tensor(case.slopes(k), dtype=torch.float64, device="cuda:0") for k in range(FRAMES)]
+    preds = [np.empty(case.n_act) for _ in range(FRAMES)]
+    for k in range(FRAMES):
+        assert srv.submit(inst, ys[k], k, preds[k]) == 0
+    srv.drain()
+    for k in range(FRAMES):
+        assert np.array_equal(preds[k], host_preds[0][k]), k
+    X, fr = inst.get_state()
+    assert np.array_equal(X, host_states[0][0]) and fr == FRAMES
+    srv.close()
+
+
+def test_callback_may_submit_next_frame():
+    """Closed loop driven from the completion callback (the serving bench's pattern)."""
+    import threading
+    case = build_case(1)
+    done = threading.Event()
+    order = []
+    srv = None
+
+    def on_done(fid, status, t):
+        order.append(fid)
+        if fid + 1 < FRAMES:
+            srv.submit(inst, case.slopes(fid + 1), fid + 1, np.empty(case.n_act))
+        else:
+            done.set()
+
+    srv = Server(1 << 28, on_done=on_done)
+    inst = srv.add(Problem.from_case(case), case.X0, FP64)
+    srv.submit(inst, case.slopes(0), 0, np.empty(case.n_act))
+    assert done.wait(60)
+    srv.drain()
+    assert order == list(range(FRAMES))
+    srv.close()
