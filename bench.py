@@ -36,6 +36,20 @@ PEAK_FP64_TFLOPS = 78.6   # MI355X vector FP64 (256 CU x 2.4 GHz x 128 flop/clk)
 PEAK_HBM_GBS = 8000.0
 
 METRIC = "frames/s + p50/p99 frame latency (µs), LETKF 84×84 subaps m=64"
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_analysis_fp64_84x84_m64_traffic.txt")
+
+
+def measured_traffic(library: str):
+    """HBM bytes per k_analysis launch from the committed rocprofv3 counter
+    summary (FETCH_SIZE x fetch scale + WRITE_SIZE x write scale), or None when
+    the summary was taken on another build of the kernels."""
+    try:
+        kv = dict(line.split(":", 1) for line in open(TRAFFIC_FILE) if ":" in line and not line.startswith("#"))
+    except OSError:
+        return None
+    if kv.get("library", "").strip() != library:
+        return None
+    return float(kv["traffic_bytes_per_launch"])
 
 
 def analysis_flops(m: int, dmap, sweeps_total: int, solves: int, frames: int) -> float:
@@ -221,7 +235,7 @@ def main() -> int:
     flops = analysis_flops(case.m, case.dmap, plain["sweeps"], plain["solves"], K) / K
     achieved = flops / (ana_ms * 1e-3) / 1e12
     roofline = dict(bound="alu", achieved=round(achieved, 3), peak=PEAK_FP64_TFLOPS, unit="TFLOP/s",
-                    frac=round(achieved / PEAK_FP64_TFLOPS, 4), traffic=None,
+                    frac=round(achieved / PEAK_FP64_TFLOPS, 4), traffic=measured_traffic(build_id()),
                     kernel="k_analysis<FP64, m=64> (vector FP64: Cholesky + one-sided Jacobi dominate)")
     plain_out = dict(frames_per_s=round(plain["fps"], 2), p50_us=round(plain["p50_us"], 1),
                      p99_us=round(plain["p99_us"], 1),

@@ -162,9 +162,11 @@ int letkf_set_state(letkf_handle* h, const double* X, uint64_t frame, void* stre
 /* Per-domain intermediates of the last analysis (needs LETKF_FLAG_DEBUG):
  * C_out [m x m] (C = Y'^T diag(r) Y', no (m-1)/rho I), lam_out [m]
  * (ascending eigenvalues of A), T_out [m x m] (W + wbar 1^T), sweeps_out
- * (Jacobi sweeps used).  Any output may be NULL.  Waits for the stream. */
+ * (Jacobi sweeps used), cycles_out [5] (shader-clock cycles spent by the
+ * domain's workgroup in: gather + C/b, Cholesky, Jacobi, wbar/W/T, update).
+ * Any output may be NULL.  Waits for the stream. */
 int letkf_debug_domain(letkf_handle* h, int32_t domain, double* C_out, double* lam_out,
-                       double* T_out, int32_t* sweeps_out, void* stream);
+                       double* T_out, int32_t* sweeps_out, double* cycles_out, void* stream);
 
 /* Number of domains whose eigensolver hit the sweep cap in the last analysis
  * (0 when all converged); waits for the stream. */

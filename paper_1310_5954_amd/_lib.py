@@ -59,7 +59,7 @@ def _sig(lib):
     lib.letkf_step.argtypes = [P, P, C.c_int, pd, P]
     lib.letkf_get_state.argtypes = [P, pd, C.POINTER(C.c_uint64), P]
     lib.letkf_set_state.argtypes = [P, pd, C.c_uint64, P]
-    lib.letkf_debug_domain.argtypes = [P, C.c_int32, pd, pd, pd, C.POINTER(C.c_int32), P]
+    lib.letkf_debug_domain.argtypes = [P, C.c_int32, pd, pd, pd, C.POINTER(C.c_int32), pd, P]
     lib.letkf_unconverged_domains.argtypes = [P, C.POINTER(C.c_int32), P]
     lib.letkf_kernel_times.argtypes = [P, C.c_int, pd, C.POINTER(C.c_uint64)]
     lib.letkf_sweep_stats.argtypes = [P, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64), P]

@@ -151,13 +151,14 @@ class Filter:
 
     def debug_domain(self, l: int):
         m = self.problem.m
-        Cm, lam, T = np.empty((m, m)), np.empty(m), np.empty((m, m))
+        Cm, lam, T, cyc = np.empty((m, m)), np.empty(m), np.empty((m, m)), np.empty(5)
         sw = C.c_int32()
         with torch.cuda.device(self.device):
             L.check(L.lib().letkf_debug_domain(self.handle, int(l), Cm.ctypes.data_as(_pd), lam.ctypes.data_as(_pd),
-                                               T.ctypes.data_as(_pd), C.byref(sw), _stream(self.device)),
-                    "letkf_debug_domain")
-        return dict(C=Cm, lam=lam, T=T, sweeps=int(sw.value))
+                                               T.ctypes.data_as(_pd), C.byref(sw), cyc.ctypes.data_as(_pd),
+                                               _stream(self.device)), "letkf_debug_domain")
+        return dict(C=Cm, lam=lam, T=T, sweeps=int(sw.value),
+                    cycles=dict(zip(("gather_C", "cholesky", "jacobi", "transform", "update"), cyc.tolist())))
 
     def kernel_times(self, enable: bool):
         """Accumulated kernel milliseconds {slopes, analysis, merge/forecast} and

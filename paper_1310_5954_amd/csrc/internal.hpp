@@ -8,7 +8,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/letkf.h"
+#include "letkf.h"
 #include "desc.hpp"
 
 namespace letkf {

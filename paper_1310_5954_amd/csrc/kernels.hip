@@ -246,6 +246,7 @@ template <int M> struct AnaSmem {
   alignas(16) unsigned char stage[C::STAGE_BYTES];    // chunk staging (phase-dependent type)
   double rc[32], dc[32];
   double bvec[M], nrm[M], lam[M], zv[M], wbar[M];
+  double pcol[2][M];                                  // Cholesky pivot column (double buffer)
   int s_rot;
   __device__ double* red() { return (double*)stage; }  // NT partial sums, aliases the staging area
 };
@@ -436,13 +437,72 @@ __device__ void gather_C_mfma(AnaSmem<M>& sm, const InstDesc& I, int obs_off, in
   __syncthreads();
 }
 
-// ---- a6 (first half): Cholesky factor A = L L^T in place (FP64, LDS) --------
-// Right-looking, one column per step: the trailing lower triangle is updated
-// from the unscaled column k, then column k is scaled (and its upper part
-// zeroed) while the next step already updates columns > k + 1.  A is SPD
-// (all eigenvalues >= (m-1)/rho), so every pivot is positive.
+// ---- a6 (first half): Cholesky factor A = L L^T (FP64) ----------------------
+// Each thread keeps its TM x TM entries of A (rows ti + 16x, columns tj + 16y)
+// in registers; only the pivot column travels through LDS, in a double
+// buffer, so every column step costs one barrier: read the pivot column,
+// update the trailing entries, finalise the entries of column k, and (owners
+// of column k+1) publish the updated next pivot column.  A is SPD (all
+// eigenvalues >= (m-1)/rho), so every pivot is positive.  L (zero above the
+// diagonal) is written back to Bm for the Jacobi phase.
 template <int M>
 __device__ void cholesky(AnaSmem<M>& sm) {
+  using C = AnaCfg<M>;
+  constexpr int LDB = C::LDB, TM = C::TM;
+  const int tid = threadIdx.x, ti = tid / 16, tj = tid % 16;
+  double a[TM][TM];
+#pragma unroll
+  for (int x = 0; x < TM; ++x)
+#pragma unroll
+    for (int y = 0; y < TM; ++y) a[x][y] = sm.Bm[(tj + 16 * y) * LDB + ti + 16 * x];
+  // column 0 is the first pivot column
+  if (tj == 0)
+#pragma unroll
+    for (int x = 0; x < TM; ++x) sm.pcol[0][ti + 16 * x] = a[x][0];
+  __syncthreads();
+  for (int k = 0; k < M; ++k) {
+    const double* pc = sm.pcol[k & 1];
+    const double akk = pc[k];
+    const double sk = sqrt(akk);
+    const double inv = 1.0 / akk;
+    double li[TM], lj[TM];
+#pragma unroll
+    for (int x = 0; x < TM; ++x) {
+      li[x] = pc[ti + 16 * x];
+      lj[x] = pc[tj + 16 * x];
+    }
+#pragma unroll
+    for (int x = 0; x < TM; ++x) {
+      const int i = ti + 16 * x;
+#pragma unroll
+      for (int y = 0; y < TM; ++y) {
+        const int j = tj + 16 * y;
+        if (i > k && j > k) a[x][y] -= li[x] * (lj[y] * inv);
+        else if (j == k) a[x][y] = i > k ? li[x] / sk : (i == k ? sk : 0.0);
+        else if (i == k && j > k) a[x][y] = 0.0;   // upper triangle of L
+      }
+    }
+    if (k + 1 < M && (k + 1) % 16 == tj) {
+      const int y = (k + 1) / 16;
+#pragma unroll
+      for (int x = 0; x < TM; ++x) sm.pcol[(k + 1) & 1][ti + 16 * x] = a[x][y];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int x = 0; x < TM; ++x)
+#pragma unroll
+    for (int y = 0; y < TM; ++y) sm.Bm[(tj + 16 * y) * LDB + ti + 16 * x] = a[x][y];
+  __syncthreads();
+}
+
+// The register-blocked form needs TM^2 + 2 TM doubles per thread, which at
+// M = 128 (TM = 8) no longer fits beside the rest of the kernel; that class
+// runs a right-looking LDS form instead: the trailing lower triangle is
+// updated from the unscaled column k, then column k is scaled and its upper
+// part zeroed.
+template <int M>
+__device__ void cholesky_lds(AnaSmem<M>& sm) {
   using C = AnaCfg<M>;
   constexpr int NT = C::NT, LDB = C::LDB;
   const int tid = threadIdx.x;
@@ -468,16 +528,22 @@ __device__ void cholesky(AnaSmem<M>& sm) {
 // L J = U Sigma with U the eigenvectors of A = L L^T and lambda = sigma^2, so
 // no rotation accumulator is needed; rounding scales with sqrt(lambda), and
 // the Cholesky factor's columns start closer to orthogonal than those of A.
-// Column pairs (i, i^k), k = 1..M-1, are M-1 perfect matchings covering every
-// pair once per sweep.
+// A sweep visits the pairs (i, i^k), k = 1..M-1 (M-1 perfect matchings that
+// cover every pair once).  Steps are grouped by the highest set bit h of k:
+// within a group every pair joins a column with bit h clear (the "lower"
+// column) to one with bit h set, and each lower column meets all its
+// partners in that group, so its pair slot keeps it in registers for the
+// whole group and only the partner column goes through LDS each step.
 template <int P, int M>
 __device__ int jacobi(AnaSmem<M>& sm) {
   using C = AnaCfg<M>;
   constexpr int NT = C::NT, LDB = C::LDB, TPP = C::TPP;
   const int tid = threadIdx.x;
+  const bool active = tid < C::ACTIVE;
+  const int q = tid / TPP, sub = tid % TPP;
   // Rotations are skipped once |b_i.b_j| <= tol |b_i| |b_j|.  FP64 path: tol =
   // M eps (the rounding level of a length-M dot product).  FP32 / BF16 paths:
-  // C already carries relative errors ~1e-7 / ~1e-3, so the rotations stop
+  // C already carries relative errors ~1e-7 / ~1e-5, so the rotations stop
   // at 1e-9 / 1e-6, below what those inputs can resolve.
   const double tol = P == 0 ? (double)M * 1.1102230246251565e-16 : (P == 1 ? 1e-9 : 1e-6);
   const double tol2 = tol * tol;
@@ -493,43 +559,59 @@ __device__ int jacobi(AnaSmem<M>& sm) {
     }
     if (tid == 0) sm.s_rot = 0;
     __syncthreads();
-    for (int k = 1; k < M; ++k) {
-      if (tid < C::ACTIVE) {
-        const int q = tid / TPP, sub = tid % TPP;
-        const int h = 31 - __clz(k);
-        const int i = ((q >> h) << (h + 1)) | (q & ((1 << h) - 1));
-        const int jj = i ^ k;
-        double* bi = sm.Bm + i * LDB;
-        double* bj = sm.Bm + jj * LDB;
-        const double al = sm.nrm[i], be = sm.nrm[jj];
-        double xi[C::RPT], xj[C::RPT];
-        double gsum = 0.0;
+    for (int h = 0; (1 << h) < M; ++h) {
+      const int i = ((q >> h) << (h + 1)) | (q & ((1 << h) - 1));
+      double xi[C::RPT];
+      double al = 0.0;
+      if (active) {
 #pragma unroll
-        for (int t = 0; t < C::RPT; ++t) {
-          xi[t] = bi[sub + t * TPP];
-          xj[t] = bj[sub + t * TPP];
-          gsum += xi[t] * xj[t];
-        }
-        gsum = group_sum<TPP>(gsum);
-        if (gsum * gsum > tol2 * (al * be)) {
-          // t = tan(theta), the smaller root of t^2 + 2 zeta t - 1 = 0 with
-          // zeta = (be - al) / (2 gsum), written without the quotient zeta.
-          const double dd = be - al, g2 = 2.0 * gsum;
-          const double den = fabs(dd) + sqrt(dd * dd + g2 * g2);
-          const double t = copysign(1.0, dd) * g2 / den;
-          const double c = 1.0 / sqrt(1.0 + t * t);
-          const double sn = c * t;
+        for (int t = 0; t < C::RPT; ++t) xi[t] = sm.Bm[i * LDB + sub + t * TPP];
+        al = sm.nrm[i];
+      }
+      for (int k = 1 << h; k < (2 << h); ++k) {
+        if (active) {
+          const int jj = i ^ k;
+          double* bj = sm.Bm + jj * LDB;
+          const double be = sm.nrm[jj];
+          double xj[C::RPT];
+          double gsum = 0.0;
 #pragma unroll
-          for (int u = 0; u < C::RPT; ++u) {
-            bi[sub + u * TPP] = c * xi[u] - sn * xj[u];
-            bj[sub + u * TPP] = sn * xi[u] + c * xj[u];
+          for (int t = 0; t < C::RPT; ++t) {
+            xj[t] = bj[sub + t * TPP];
+            gsum += xi[t] * xj[t];
           }
-          if (sub == 0) {
-            sm.nrm[i] = al - t * gsum;
-            sm.nrm[jj] = be + t * gsum;
-            sm.s_rot = 1;
+          gsum = group_sum<TPP>(gsum);
+          if (gsum * gsum > tol2 * (al * be)) {
+            // t = tan(theta), the smaller root of t^2 + 2 zeta t - 1 = 0 with
+            // zeta = (be - al) / (2 gsum), written without the quotient zeta;
+            // c = (1 + t^2)^(-1/2) keeps c^2 + s^2 = 1 to rounding, so an
+            // approximate t only changes how far this rotation reduces gsum.
+            const double dd = be - al, g2 = 2.0 * gsum;
+            const double q2 = dd * dd + g2 * g2;
+            const double den = fabs(dd) + q2 * rsqrt(q2);
+            const double rd = __builtin_amdgcn_rcp(den);
+            const double t = copysign(1.0, dd) * g2 * (rd * (2.0 - den * rd));
+            const double c = rsqrt(1.0 + t * t);
+            const double sn = c * t;
+#pragma unroll
+            for (int u = 0; u < C::RPT; ++u) {
+              const double a = xi[u];
+              xi[u] = c * a - sn * xj[u];
+              bj[sub + u * TPP] = sn * a + c * xj[u];
+            }
+            al -= t * gsum;
+            if (sub == 0) {
+              sm.nrm[jj] = be + t * gsum;
+              sm.s_rot = 1;
+            }
           }
         }
+        __syncthreads();
+      }
+      if (active) {
+#pragma unroll
+        for (int t = 0; t < C::RPT; ++t) sm.Bm[i * LDB + sub + t * TPP] = xi[t];
+        if (sub == 0) sm.nrm[i] = al;
       }
       __syncthreads();
     }
@@ -733,13 +815,23 @@ __global__ __launch_bounds__(256) void k_analysis(const InstDesc* __restrict__ t
   const int obs_off = I.dom[4 * l + 2], s = I.dom[4 * l + 3];
   const int m = I.m;
   const int cur = I.st->cur;
-  double* dbg = I.dbg ? I.dbg + (size_t)l * (2 * m * m + m) : nullptr;
+  double* dbg = I.dbg ? I.dbg + (size_t)l * (2 * m * m + m + 8) : nullptr;
+  // debug: shader-clock stamps at the phase boundaries (after each phase's barrier)
+  auto stamp = [&](int k) {
+    if (dbg && threadIdx.x == 0) dbg[2 * m * m + m + k] = (double)clock64();
+  };
+  stamp(0);
 
   if constexpr (P == 0) gather_C_fp64<M>(sm, I, obs_off, s, dbg);
   else gather_C_mfma<P, M>(sm, I, obs_off, s, dbg);
-  cholesky<M>(sm);
+  stamp(1);
+  if constexpr (AnaCfg<M>::TM <= 4) cholesky<M>(sm);
+  else cholesky_lds<M>(sm);
+  stamp(2);
   const int sweeps = jacobi<P, M>(sm);
+  stamp(3);
   transform<M>(sm, m, dbg);
+  stamp(4);
   if (threadIdx.x == 0) {
     if (I.dbg_sweeps) I.dbg_sweeps[l] = sweeps;
     if (sweeps >= C::MAX_SWEEPS) atomicAdd(&I.st->unconverged, 1);
@@ -748,6 +840,7 @@ __global__ __launch_bounds__(256) void k_analysis(const InstDesc* __restrict__ t
   }
   if constexpr (P == 0) update_fp64<M>(sm, I, est_off, e, cur);
   else update_mfma<P, M>(sm, I, est_off, e, cur);
+  stamp(5);
 }
 
 // ----------------------------------------------------------------------------

@@ -149,7 +149,7 @@ Layout make_layout(const Problem& P) {
   L.mw = take((size_t)P.sum_e() * 8);
   L.static_end = off;
   if (P.flags & LETKF_FLAG_DEBUG) {
-    L.dbg = take((size_t)P.n_dom * (2 * m * m + m) * 8);
+    L.dbg = take((size_t)P.n_dom * (2 * m * m + m + 8) * 8);
     L.dbg_sweeps = take((size_t)P.n_dom * 4);
   } else {
     L.dbg = L.dbg_sweeps = 0;
@@ -386,10 +386,11 @@ int letkf_create(const letkf_dims* dims, const letkf_model* model, const letkf_d
 int letkf_destroy(letkf_handle* h) {
   if (!h) return LETKF_OK;
   if (h->server) return fail(LETKF_ESTATE, "instance belongs to a server: use letkf_server_remove");
-  if (h->y_free) { hipEventSynchronize(h->y_free); hipEventDestroy(h->y_free); }
-  for (hipEvent_t e : h->ev) hipEventDestroy(e);
-  if (h->h_y) hipHostFree(h->h_y);
-  if (h->h_out) hipHostFree(h->h_out);
+  // teardown: errors here cannot be acted on, the host state goes regardless
+  if (h->y_free) { (void)hipEventSynchronize(h->y_free); (void)hipEventDestroy(h->y_free); }
+  for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
+  if (h->h_y) (void)hipHostFree(h->h_y);
+  if (h->h_out) (void)hipHostFree(h->h_out);
   delete h;
   return LETKF_OK;
 }
@@ -506,13 +507,13 @@ int letkf_set_state(letkf_handle* h, const double* X, uint64_t frame, void* stre
 }
 
 int letkf_debug_domain(letkf_handle* h, int32_t domain, double* C_out, double* lam_out, double* T_out,
-                       int32_t* sweeps_out, void* stream) {
+                       int32_t* sweeps_out, double* cycles_out, void* stream) {
   hipStream_t s;
   int rc = access_stream(h, stream, &s);
   if (rc) return rc;
   if (!(h->P.flags & LETKF_FLAG_DEBUG)) return fail(LETKF_ESTATE, "handle created without LETKF_FLAG_DEBUG");
   if (domain < 0 || domain >= h->P.n_dom) return fail(LETKF_EINVAL, "domain out of range");
-  const size_t m = h->P.m, per = 2 * m * m + m;
+  const size_t m = h->P.m, per = 2 * m * m + m + 8;
   std::vector<double> buf(per);
   int32_t sw = 0;
   LETKF_HIP(hipMemcpyAsync(buf.data(), h->ws + h->L.dbg + domain * per * 8, per * 8, hipMemcpyDeviceToHost, s));
@@ -526,6 +527,8 @@ int letkf_debug_domain(letkf_handle* h, int32_t domain, double* C_out, double* l
   }
   if (T_out) std::memcpy(T_out, buf.data() + m * m + m, m * m * 8);
   if (sweeps_out) *sweeps_out = sw;
+  if (cycles_out)
+    for (int k = 0; k < 5; ++k) cycles_out[k] = buf[2 * m * m + m + k + 1] - buf[2 * m * m + m + k];
   return LETKF_OK;
 }
 

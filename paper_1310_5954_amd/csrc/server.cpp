@@ -152,7 +152,7 @@ int letkf_server::launch_batch(Batch& b) {
 }
 
 void letkf_server::scheduler_loop() {
-  hipSetDevice(device);
+  (void)hipSetDevice(device);  // a failure shows up as an error status of the first batch
   std::unique_lock<std::mutex> lk(mu);
   for (;;) {
     cv_work.wait(lk, [&] { return stop || pending > 0; });
@@ -220,7 +220,7 @@ void letkf_server::scheduler_loop() {
 }
 
 void letkf_server::completion_loop() {
-  hipSetDevice(device);
+  (void)hipSetDevice(device);  // a failure shows up as an error status of the first batch
   std::unique_lock<std::mutex> lk(mu);
   for (;;) {
     cv_done.wait(lk, [&] { return stop || !running.empty(); });
@@ -342,8 +342,8 @@ int letkf_server_add(letkf_server* s, const letkf_dims* dims, const letkf_model*
     h->server = s;
     s->inst[slot] = h;  // reserved; invisible to the scheduler until its queue exists
   }
-  hipSetDevice(s->device);
-  rc = upload_instance(h->P, h->L, h->ws, X0, s->upload, h->desc);
+  if (hipSetDevice(s->device) != hipSuccess) rc = fail(LETKF_EDEVICE, "hipSetDevice");
+  if (!rc) rc = upload_instance(h->P, h->L, h->ws, X0, s->upload, h->desc);
   if (!rc && hipMemcpyAsync(s->table() + h->slot, &h->desc, sizeof(InstDesc), hipMemcpyHostToDevice, s->upload) != hipSuccess)
     rc = fail(LETKF_EDEVICE, "table upload");
   if (!rc && hipStreamSynchronize(s->upload) != hipSuccess) rc = fail(LETKF_EDEVICE, "upload sync");
@@ -352,7 +352,7 @@ int letkf_server_add(letkf_server* s, const letkf_dims* dims, const letkf_model*
   if (rc) {
     s->inst[h->slot] = nullptr;
     s->free_list[h->arena_off] = h->L.total;
-    if (h->h_out) hipHostFree(h->h_out);
+    if (h->h_out) (void)hipHostFree(h->h_out);
     delete h;
     return rc;
   }
@@ -384,7 +384,7 @@ int letkf_server_remove(letkf_server* s, letkf_handle* h) {
     it->second += next->second;
     s->free_list.erase(next);
   }
-  if (h->h_out) hipHostFree(h->h_out);
+  if (h->h_out) (void)hipHostFree(h->h_out);
   delete h;
   return LETKF_OK;
 }
@@ -462,17 +462,17 @@ int letkf_server_destroy(letkf_server* s) {
   }
   for (letkf_handle* h : s->inst)
     if (h) {
-      if (h->h_out) hipHostFree(h->h_out);
+      if (h->h_out) (void)hipHostFree(h->h_out);
       delete h;
     }
   for (int k = 0; k < kSlots; ++k) {
-    if (s->h_hdr[k]) hipHostFree(s->h_hdr[k]);
-    if (s->h_y[k]) hipHostFree(s->h_y[k]);
-    if (s->h_out[k]) hipHostFree(s->h_out[k]);
-    if (s->done_ev[k]) hipEventDestroy(s->done_ev[k]);
+    if (s->h_hdr[k]) (void)hipHostFree(s->h_hdr[k]);
+    if (s->h_y[k]) (void)hipHostFree(s->h_y[k]);
+    if (s->h_out[k]) (void)hipHostFree(s->h_out[k]);
+    if (s->done_ev[k]) (void)hipEventDestroy(s->done_ev[k]);
   }
-  if (s->stream) hipStreamDestroy(s->stream);
-  if (s->upload) hipStreamDestroy(s->upload);
+  if (s->stream) (void)hipStreamDestroy(s->stream);
+  if (s->upload) (void)hipStreamDestroy(s->upload);
   delete s;
   return LETKF_OK;
 }
