@@ -63,9 +63,10 @@ __device__ __forceinline__ double row_sum(double v, double* red) {
 // Cross-lane moves of a double with DPP (VALU, no LDS round trip).
 template <int CTRL>
 __device__ __forceinline__ double dpp_f64(double v) {
+  // Every pattern used here reads a valid lane, so no "old" value is needed.
   const long long x = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)x, CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(x >> 32), CTRL, 0xF, 0xF, false);
+  const int lo = __builtin_amdgcn_mov_dpp((int)x, CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(x >> 32), CTRL, 0xF, 0xF, true);
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
@@ -440,11 +441,14 @@ __device__ void gather_C_mfma(AnaSmem<M>& sm, const InstDesc& I, int obs_off, in
 // ---- a6 (first half): Cholesky factor A = L L^T (FP64) ----------------------
 // Each thread keeps its TM x TM entries of A (rows ti + 16x, columns tj + 16y)
 // in registers; only the pivot column travels through LDS, in a double
-// buffer, so every column step costs one barrier: read the pivot column,
-// update the trailing entries, finalise the entries of column k, and (owners
-// of column k+1) publish the updated next pivot column.  A is SPD (all
-// eigenvalues >= (m-1)/rho), so every pivot is positive.  L (zero above the
-// diagonal) is written back to Bm for the Jacobi phase.
+// buffer, so every column step costs one barrier.  Step k scales the pivot
+// column by 1/sqrt(a_kk) (one rsqrt), subtracts the outer product of its
+// part below k from the trailing block (entries outside it see a zero factor
+// and stay as they are), stores the scaled column as column k of L, and the
+// owners of column k+1 publish it as the next pivot column.  The upper
+// triangle is never read for the factor and is zeroed when L is written back
+// to Bm for the Jacobi phase.  A is SPD (all eigenvalues >= (m-1)/rho), so
+// every pivot is positive.
 template <int M>
 __device__ void cholesky(AnaSmem<M>& sm) {
   using C = AnaCfg<M>;
@@ -455,44 +459,44 @@ __device__ void cholesky(AnaSmem<M>& sm) {
   for (int x = 0; x < TM; ++x)
 #pragma unroll
     for (int y = 0; y < TM; ++y) a[x][y] = sm.Bm[(tj + 16 * y) * LDB + ti + 16 * x];
-  // column 0 is the first pivot column
   if (tj == 0)
 #pragma unroll
     for (int x = 0; x < TM; ++x) sm.pcol[0][ti + 16 * x] = a[x][0];
   __syncthreads();
+#pragma unroll 2
   for (int k = 0; k < M; ++k) {
     const double* pc = sm.pcol[k & 1];
-    const double akk = pc[k];
-    const double sk = sqrt(akk);
-    const double inv = 1.0 / akk;
-    double li[TM], lj[TM];
+    const double rs = rsqrt(pc[k]);
+    double lc[TM], li[TM], lj[TM];
 #pragma unroll
     for (int x = 0; x < TM; ++x) {
-      li[x] = pc[ti + 16 * x];
-      lj[x] = pc[tj + 16 * x];
+      lc[x] = pc[ti + 16 * x] * rs;
+      li[x] = ti + 16 * x > k ? lc[x] : 0.0;
+      lj[x] = tj + 16 * x > k ? pc[tj + 16 * x] * rs : 0.0;
     }
+    const bool own_k = tj == (k & 15);
 #pragma unroll
-    for (int x = 0; x < TM; ++x) {
-      const int i = ti + 16 * x;
+    for (int x = 0; x < TM; ++x)
 #pragma unroll
       for (int y = 0; y < TM; ++y) {
-        const int j = tj + 16 * y;
-        if (i > k && j > k) a[x][y] -= li[x] * (lj[y] * inv);
-        else if (j == k) a[x][y] = i > k ? li[x] / sk : (i == k ? sk : 0.0);
-        else if (i == k && j > k) a[x][y] = 0.0;   // upper triangle of L
+        const double u = fma(-li[x], lj[y], a[x][y]);
+        a[x][y] = (own_k && y == (k >> 4)) ? lc[x] : u;
       }
-    }
-    if (k + 1 < M && (k + 1) % 16 == tj) {
-      const int y = (k + 1) / 16;
+    const int k1 = k + 1;
+    if (k1 < M && tj == (k1 & 15)) {
 #pragma unroll
-      for (int x = 0; x < TM; ++x) sm.pcol[(k + 1) & 1][ti + 16 * x] = a[x][y];
+      for (int y = 0; y < TM; ++y)
+        if (y == (k1 >> 4))
+#pragma unroll
+          for (int x = 0; x < TM; ++x) sm.pcol[k1 & 1][ti + 16 * x] = a[x][y];
     }
     __syncthreads();
   }
 #pragma unroll
   for (int x = 0; x < TM; ++x)
 #pragma unroll
-    for (int y = 0; y < TM; ++y) sm.Bm[(tj + 16 * y) * LDB + ti + 16 * x] = a[x][y];
+    for (int y = 0; y < TM; ++y)
+      sm.Bm[(tj + 16 * y) * LDB + ti + 16 * x] = (ti + 16 * x < tj + 16 * y) ? 0.0 : a[x][y];
   __syncthreads();
 }
 
@@ -524,6 +528,54 @@ __device__ void cholesky_lds(AnaSmem<M>& sm) {
   __syncthreads();
 }
 
+// 1/sqrt(x) for x in [1, 2] (no zero, infinity or denormal input): the
+// hardware estimate e0 (relative error ~2^-23) refined by one third-order step
+// c = c0 (1 + e/2 + 3e^2/8), e = 1 - x c0^2, which leaves a relative error of
+// order e^3, below the rounding of the result.
+__device__ __forceinline__ double rsqrt_1_2(double x) {
+  const double c0 = __builtin_amdgcn_rsq(x);
+  const double e = fma(-x * c0, c0, 1.0);
+  return fma(c0 * e, fma(e, 0.375, 0.5), c0);
+}
+
+// True when every pair of columns of the current B satisfies
+// (b_i.b_j)^2 <= tol2 |b_i|^2 |b_j|^2, i.e. when a further sweep would not
+// rotate.  Each thread forms a TM x TM block of B^T B from LDS (the norms are
+// the ones the sweep kept current).  Block-uniform result; ends with a barrier.
+template <int M>
+__device__ bool gram_converged(AnaSmem<M>& sm, double tol2) {
+  using C = AnaCfg<M>;
+  constexpr int LDB = C::LDB, TM = C::TM;
+  const int tid = threadIdx.x, ti = tid / 16, tj = tid % 16;
+  double g[TM][TM];
+#pragma unroll
+  for (int x = 0; x < TM; ++x)
+#pragma unroll
+    for (int y = 0; y < TM; ++y) g[x][y] = 0.0;
+#pragma unroll 2
+  for (int r = 0; r < M; ++r) {
+    double u[TM], v[TM];
+#pragma unroll
+    for (int x = 0; x < TM; ++x) {
+      u[x] = sm.Bm[(ti + 16 * x) * LDB + r];
+      v[x] = sm.Bm[(tj + 16 * x) * LDB + r];
+    }
+#pragma unroll
+    for (int x = 0; x < TM; ++x)
+#pragma unroll
+      for (int y = 0; y < TM; ++y) g[x][y] = fma(u[x], v[y], g[x][y]);
+  }
+  bool bad = false;
+#pragma unroll
+  for (int x = 0; x < TM; ++x)
+#pragma unroll
+    for (int y = 0; y < TM; ++y) {
+      const int i = ti + 16 * x, j = tj + 16 * y;
+      bad |= i < j && g[x][y] * g[x][y] > tol2 * (sm.nrm[i] * sm.nrm[j]);
+    }
+  return !__syncthreads_or(bad);
+}
+
 // ---- a6 (second half): one-sided (Hestenes) Jacobi on the columns of L ------
 // L J = U Sigma with U the eigenvectors of A = L L^T and lambda = sigma^2, so
 // no rotation accumulator is needed; rounding scales with sqrt(lambda), and
@@ -547,6 +599,11 @@ __device__ int jacobi(AnaSmem<M>& sm) {
   // at 1e-9 / 1e-6, below what those inputs can resolve.
   const double tol = P == 0 ? (double)M * 1.1102230246251565e-16 : (P == 1 ? 1e-9 : 1e-6);
   const double tol2 = tol * tol;
+  // Once no rotation of a sweep exceeded this cosine, the columns are close
+  // enough that the next sweep is most likely the one that finds nothing to
+  // do; the Gram test decides that in a fraction of a sweep's cost.
+  const double trig = tol * 100.0 > 1e-7 ? tol * 100.0 : 1e-7;
+  const double trig2 = trig * trig;
   int sweeps = 0;
   for (; sweeps < C::MAX_SWEEPS;) {
     {
@@ -559,6 +616,7 @@ __device__ int jacobi(AnaSmem<M>& sm) {
     }
     if (tid == 0) sm.s_rot = 0;
     __syncthreads();
+    bool big = false;
     for (int h = 0; (1 << h) < M; ++h) {
       const int i = ((q >> h) << (h + 1)) | (q & ((1 << h) - 1));
       double xi[C::RPT];
@@ -574,24 +632,28 @@ __device__ int jacobi(AnaSmem<M>& sm) {
           double* bj = sm.Bm + jj * LDB;
           const double be = sm.nrm[jj];
           double xj[C::RPT];
-          double gsum = 0.0;
+          double g0 = 0.0, g1 = 0.0;
 #pragma unroll
           for (int t = 0; t < C::RPT; ++t) {
             xj[t] = bj[sub + t * TPP];
-            gsum += xi[t] * xj[t];
+            if (t & 1) g1 = fma(xi[t], xj[t], g1);
+            else g0 = fma(xi[t], xj[t], g0);
           }
-          gsum = group_sum<TPP>(gsum);
-          if (gsum * gsum > tol2 * (al * be)) {
+          const double gsum = group_sum<TPP>(g0 + g1);
+          const double ab = al * be;
+          if (gsum * gsum > tol2 * ab) {
+            big |= gsum * gsum > trig2 * ab;
             // t = tan(theta), the smaller root of t^2 + 2 zeta t - 1 = 0 with
-            // zeta = (be - al) / (2 gsum), written without the quotient zeta;
-            // c = (1 + t^2)^(-1/2) keeps c^2 + s^2 = 1 to rounding, so an
-            // approximate t only changes how far this rotation reduces gsum.
+            // zeta = (be - al) / (2 gsum), written without the quotient zeta.
+            // c = (1 + t^2)^(-1/2) (correctly rounded rsqrt) keeps
+            // c^2 + s^2 = 1 to rounding for whatever t is used, so t itself
+            // comes from the hardware's approximate rsq / rcp: its error only
+            // changes how far this rotation reduces gsum, never orthogonality.
             const double dd = be - al, g2 = 2.0 * gsum;
-            const double q2 = dd * dd + g2 * g2;
-            const double den = fabs(dd) + q2 * rsqrt(q2);
-            const double rd = __builtin_amdgcn_rcp(den);
-            const double t = copysign(1.0, dd) * g2 * (rd * (2.0 - den * rd));
-            const double c = rsqrt(1.0 + t * t);
+            const double q2 = fma(dd, dd, g2 * g2);
+            const double den = fma(q2, __builtin_amdgcn_rsq(q2), fabs(dd));
+            const double t = copysign(1.0, dd) * g2 * __builtin_amdgcn_rcp(den);
+            const double c = rsqrt_1_2(fma(t, t, 1.0));
             const double sn = c * t;
 #pragma unroll
             for (int u = 0; u < C::RPT; ++u) {
@@ -617,8 +679,9 @@ __device__ int jacobi(AnaSmem<M>& sm) {
     }
     ++sweeps;
     const int any = sm.s_rot;
-    __syncthreads();
+    const int any_big = __syncthreads_or(big);
     if (!any) break;
+    if (!any_big && gram_converged<M>(sm, tol2)) break;
   }
   return sweeps;
 }
