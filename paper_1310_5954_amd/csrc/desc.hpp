@@ -58,8 +58,7 @@ struct ClassBatch {
   int32_t act_off[kMaxBatch + 1];
   int32_t slope_off[kMaxBatch + 1];
   int32_t dom_off[kMaxBatch + 1];
-  uint32_t done;                  // completion counter of the forecast launch (self-resetting)
-  uint32_t pad;
+  uint32_t pad[2];
 };
 
 struct BatchHdr {

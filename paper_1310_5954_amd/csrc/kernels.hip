@@ -183,22 +183,21 @@ __global__ __launch_bounds__(256) void k_rows(const InstDesc* __restrict__ tab,
     }
     const double s = row_sum<MP>(nx, red);
     if (active && j == 0) hdr->pmean[hdr->out_off[ent] + a] = s / (double)m;
-    // the last block to finish advances every instance of the class
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      __threadfence();
-      const unsigned prev = atomicAdd(&cb.done, 1u);
-      if (prev == gridDim.x - 1) {
-        __threadfence();
-        for (int e = 0; e < cb.n; ++e) {
-          InstState* S = tab[cb.inst[e]].st;
-          S->cur ^= 1;
-          S->frame += 1;
-        }
-        cb.done = 0;
-        __threadfence();
-      }
-    }
+  }
+}
+
+// After a forecast launch: the new instant becomes phi_k (ring swap) and the
+// frame counter advances, for every instance of the class.  A launch of its
+// own, ordered after k_rows on the stream, instead of a "last block" counter
+// in k_rows: a completion counter that every block of k_rows increments
+// serialises on one address and cost more than the whole merge.
+__global__ __launch_bounds__(64) void k_advance(const InstDesc* __restrict__ tab, const BatchHdr* __restrict__ hdr,
+                                                int cls) {
+  const ClassBatch& cb = hdr->cls[cls];
+  for (int e = threadIdx.x; e < cb.n; e += blockDim.x) {
+    InstState* S = tab[cb.inst[e]].st;
+    S->cur ^= 1;
+    S->frame += 1;
   }
 }
 
@@ -917,6 +916,7 @@ static void launch_rows_t(int mode, int rows, const InstDesc* tab, BatchHdr* hdr
   if (mode == 0) hipLaunchKernelGGL((k_rows<T, MP, 0>), dim3(grid), dim3(256), 0, s, tab, hdr, cls);
   if (mode == 1) hipLaunchKernelGGL((k_rows<T, MP, 1>), dim3(grid), dim3(256), 0, s, tab, hdr, cls);
   if (mode == 2) hipLaunchKernelGGL((k_rows<T, MP, 2>), dim3(grid), dim3(256), 0, s, tab, hdr, cls);
+  if (mode != 0) hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, s, tab, hdr, cls);
 }
 
 template <typename T, int MP>
