@@ -94,7 +94,8 @@ def cpu_baseline(case, seconds: float = 15.0):
             k += 1
     fps = len(ys) / float(np.sum(ys))
     return dict(value=round(fps, 3), unit="frames/s", cores=1, kind="oracle",
-                sample=f"first {len(ys)} frames of the same 84x84, m=64 workload (NumPy/LAPACK FP64, 1 thread)")
+                sample=f"first {len(ys)} frames of the same {case.cfg['lenslets']}x{case.cfg['lenslets']}, "
+                       f"m={case.m} workload (NumPy/LAPACK FP64, 1 thread)")
 
 
 def run_plain(case, prec, K, W, NL, ys):
@@ -222,6 +223,97 @@ def run_serving(case, prec, B, K, W, ys, depth=1):
                 mean_batch=st["batched_frames"] / max(st["batches"], 1))
 
 
+def run_mix(seconds: float, rate_scale: float, window_us: int):
+    """Six resident instances of different pupils, ensemble sizes and paths
+    (FP32 / BF16 contractions) admitted into one server by HBM budget; each
+    receives frames as an independent Poisson stream.  Smaller instances get
+    the higher rates (2000 Hz ... 500 Hz, times rate_scale).  Latency = the
+    frame's scheduled arrival time -> completion callback, so pacing jitter of
+    the submitting thread counts against the server."""
+    import threading
+
+    import torch
+
+    from paper_1310_5954_amd import BF16, FP32, Problem, Server, build_id
+    from workload.configs import (PREC_BF16, SERVING_INSTANCES, SERVING_RATES_HZ, build_case,
+                                  serving_config)
+    cases = [build_case(serving_config(i)) for i in range(len(SERVING_INSTANCES))]
+    precs = [BF16 if SERVING_INSTANCES[i][2] == PREC_BF16 else FP32 for i in range(len(cases))]
+    rates = [rate_scale * r for r in sorted(SERVING_RATES_HZ, reverse=True)]
+    probs = [Problem.from_case(c) for c in cases]
+    need = sum(pr.workspace_size(pc) for pr, pc in zip(probs, precs))
+    budget = need + (64 << 20)
+    NF = 64
+    ys = [torch.tensor(np.stack([c.slopes(k) for k in range(NF)]), dtype=torch.float64, device="cuda:0")
+          for c in cases]
+    rng = np.random.default_rng(4)
+    arrivals = []
+    for i, r in enumerate(rates):
+        t = 0.0
+        while True:
+            t += rng.exponential(1.0 / r)
+            if t >= seconds:
+                break
+            arrivals.append((t, i))
+    arrivals.sort()
+    B = len(cases)
+    sched, lat, done_t = {}, [[] for _ in range(B)], []
+    lock = threading.Lock()
+    preds = [np.empty(c.n_act) for c in cases]
+
+    def on_done(fid, status, t):
+        assert status == 0, status
+        i = fid >> 32
+        with lock:
+            lat[i].append(t - sched.pop(fid))
+            done_t.append(t)
+
+    srv = Server(budget, on_done=on_done)
+    srv.set_window(window_us)
+    insts = [srv.add(pr, c.X0, pc) for pr, c, pc in zip(probs, cases, precs)]
+    torch.cuda.synchronize()
+    # one untimed frame per instance so every kernel variant is loaded
+    for i in range(B):
+        sched[(i << 32) | 0xFFFFFFFF] = time.perf_counter()
+        assert srv.submit(insts[i], ys[i][0], (i << 32) | 0xFFFFFFFF, preds[i]) == 0
+    srv.drain()
+    for L in lat:
+        L.clear()
+    done_t.clear()
+    counts, drops = [0] * B, [0] * B
+    t0 = time.perf_counter()
+    for ta, i in arrivals:
+        while time.perf_counter() - t0 < ta:
+            pass
+        k = counts[i]
+        fid = (i << 32) | k
+        with lock:
+            sched[fid] = t0 + ta
+        if srv.submit(insts[i], ys[i][k % NF], fid, preds[i]) != 0:
+            drops[i] += 1
+            with lock:
+                sched.pop(fid)
+        counts[i] += 1
+    srv.drain()
+    st = srv.stats()
+    srv.close()
+    per = []
+    for i, c in enumerate(cases):
+        L = np.array(lat[i]) * 1e6
+        per.append(dict(lenslets=c.cfg["lenslets"], n_act=c.n_act, m=c.m, domains=c.dmap.n_domains,
+                        path="bf16" if precs[i] == BF16 else "fp32", rate_hz=round(rates[i], 1),
+                        frames=int(len(L)), dropped=drops[i],
+                        p50_us=round(float(np.percentile(L, 50)), 1) if len(L) else None,
+                        p99_us=round(float(np.percentile(L, 99)), 1) if len(L) else None))
+    all_lat = np.concatenate([np.array(L) for L in lat]) * 1e6
+    span = max(done_t) - t0
+    return dict(metric="serving mix: frames/s + p50/p99 frame latency (us), 6 AO instances, Poisson arrivals",
+                value=round(len(all_lat) / span, 1), unit="frames/s", n_gpus=1, seconds=seconds,
+                rate_scale=rate_scale, offered_fps=round(sum(rates), 1), p50_us=round(float(np.percentile(all_lat, 50)), 1),
+                p99_us=round(float(np.percentile(all_lat, 99)), 1), mean_batch=round(st["batched_frames"] / max(st["batches"], 1), 3),
+                hbm_budget_bytes=int(budget), instances=per, data="synthetic", library=build_id())
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -233,6 +325,12 @@ def main() -> int:
     ap.add_argument("--latency-frames", type=int, default=200)
     ap.add_argument("--plain-only", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--mix", type=float, default=0.0, metavar="SECONDS",
+                    help="instead of the headline run: six mixed instances with Poisson arrivals for SECONDS")
+    ap.add_argument("--rate-scale", type=float, default=1.0, help="--mix: multiplies every arrival rate")
+    ap.add_argument("--window-us", type=int, default=100, help="server batching window (microseconds)")
+    ap.add_argument("--workload", type=int, default=84, choices=[84, 128],
+                    help="84: 84x84 subapertures, m = 64 (headline); 128: 128x128, m = 128")
     ap.add_argument("--serving-only", action="store_true",
                     help="skip the plain-path runs (for profiling the serving kernels); no roofline line")
     ap.add_argument("--copy-ref", action="store_true",
@@ -254,14 +352,19 @@ def main() -> int:
         print(json.dumps(dict(copy_ref_bytes_read=nbytes, copy_ref_bytes_written=nbytes, dispatches=5)))
         return 0
 
+    if args.mix > 0:
+        print(json.dumps(run_mix(args.mix, args.rate_scale, args.window_us)), flush=True)
+        return 0
+
     from paper_1310_5954_amd import BF16, FP32, FP64, build_id
     from workload.configs import build_case
 
     prec = dict(fp64=FP64, fp32=FP32, bf16=BF16)[args.precision]
-    case = build_case(3)
+    case = build_case(3 if args.workload == 84 else 5)
     K, W, NL, B = args.steps, args.warmup, args.latency_frames, args.instances
     n_frames = W + K + NL
-    print(f"[bench] 84x84 m=64 domains={case.dmap.n_domains} library={build_id()} frames={n_frames}",
+    L_ = case.cfg["lenslets"]
+    print(f"[bench] {L_}x{L_} m={case.m} domains={case.dmap.n_domains} library={build_id()} frames={n_frames}",
           file=sys.stderr, flush=True)
     ys_host = np.stack([case.slopes(k) for k in range(n_frames)])
     ys = torch.tensor(ys_host, dtype=torch.float64, device="cuda:0")
@@ -280,8 +383,9 @@ def main() -> int:
     flops = analysis_flops(case.m, case.dmap, plain["sweeps"], plain["solves"], K) / K
     achieved = flops / (ana_ms * 1e-3) / 1e12
     roofline = dict(bound="alu", achieved=round(achieved, 3), peak=PEAK_FP64_TFLOPS, unit="TFLOP/s",
-                    frac=round(achieved / PEAK_FP64_TFLOPS, 4), traffic=measured_traffic(build_id()),
-                    kernel="k_analysis<FP64, m=64> (vector FP64: Cholesky + one-sided Jacobi dominate)")
+                    frac=round(achieved / PEAK_FP64_TFLOPS, 4),
+                    traffic=measured_traffic(build_id()) if args.workload == 84 else None,
+                    kernel=f"k_analysis<FP64, m={case.m}> (vector FP64: Cholesky + one-sided Jacobi dominate)")
     plain_out = dict(frames_per_s=round(plain["fps"], 2), p50_us=round(plain["p50_us"], 1),
                      p99_us=round(plain["p99_us"], 1),
                      kernel_ms=dict(slopes=round(plain["kernel_ms"][0], 4), analysis=round(ana_ms, 4),
@@ -308,11 +412,13 @@ def main() -> int:
         serving_out = dict(instances=B, mean_batch=round(lat["mean_batch"], 3),
                            beats_plain_fp64=bool(lat["fps"] > loaded["fps"] and lat["p99_us"] < loaded["p99_us"]))
     out = dict(
-        metric=METRIC, value=round(value, 2), unit="frames/s", n_gpus=1, steps=K, warmup=W,
+        metric=METRIC if args.workload == 84 else METRIC.replace("84×84", "128×128").replace("m=64", "m=128"),
+        value=round(value, 2), unit="frames/s", n_gpus=1, steps=K, warmup=W,
         ms_per_step=round(ms_per_step, 4), higher_is_better=True, scaling="weak", vs_baseline=None,
         dtype=dtype, data="synthetic",
-        config=dict(workload="84x84 circular SH pupil, 5713 actuators (n=11426), 5544 subapertures (p=11088), "
-                             f"m=64, {case.dmap.n_domains} overlapping 6x6-actuator domains, halo 2, "
+        config=dict(workload=f"{L_}x{L_} circular SH pupil, {case.n_act} actuators (n={2 * case.n_act}), "
+                             f"{case.n_sub} subapertures (p={2 * case.n_sub}), "
+                             f"m={case.m}, {case.dmap.n_domains} overlapping 6x6-actuator domains, halo 2, "
                              "Gaspari-Cohn taper; one frame = analysis + AR(2) forecast",
                     path=path, precision=args.precision if serving_out else "fp64"),
         p50_us=round(p50, 1), p99_us=round(p99, 1),

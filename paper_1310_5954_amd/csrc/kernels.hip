@@ -347,6 +347,14 @@ __device__ void gather_C_mfma(AnaSmem<M>& sm, const InstDesc& I, int obs_off, in
   double bpart = 0.0;
   const float* Yp = (const float*)I.Yp;
   const int nobs = 2 * s;
+  // FP32 path: every k-step's product (4 observations) comes out of the MFMA
+  // on its own and is added into an FP64 accumulator in LDS (Bm, row-major,
+  // each entry owned by one lane).  A single FP32 accumulator over all p_l
+  // observations carries ~sqrt(p_l / 4) 2^-24 of |C|, which the inverse square
+  // root amplifies by up to kappa(A) / 2 (~1e4 on the ELT workloads).
+  constexpr int LDB = C::LDB;
+  if constexpr (P == 1)
+    for (int idx = tid; idx < M * LDB; idx += NT) sm.Bm[idx] = 0.0;
   for (int q0 = 0; q0 < nobs; q0 += KCH) {
     const int kc = min(KCH, nobs - q0);
     if (tid < KCH) {
@@ -388,7 +396,12 @@ __device__ void gather_C_mfma(AnaSmem<M>& sm, const InstDesc& I, int obs_off, in
 #pragma unroll
           for (int a = 0; a < WT; ++a)
 #pragma unroll
-            for (int b = 0; b < WT; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a], bv[b], acc[a][b], 0, 0, 0);
+            for (int b = 0; b < WT; ++b) {
+              const f32x4 part = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a], bv[b], f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+              double* cr = sm.Bm + ((tr0 + a) * 16 + 4 * (lane / 16)) * LDB + (tc0 + b) * 16 + lane % 16;
+#pragma unroll
+              for (int v = 0; v < 4; ++v) cr[v * LDB] += (double)part[v];
+            }
         }
       } else {
         // C += hi hi^T + hi lo^T + lo hi^T (the lo lo^T term is below FP32 rounding)
@@ -422,9 +435,14 @@ __device__ void gather_C_mfma(AnaSmem<M>& sm, const InstDesc& I, int obs_off, in
 #pragma unroll
       for (int b = 0; b < WT; ++b)
 #pragma unroll
-        for (int v = 0; v < 4; ++v)
-          put_A<M>(sm, (tr0 + a) * 16 + 4 * (lane / 16) + v, (tc0 + b) * 16 + lane % 16, m, (double)acc[a][b][v],
-                   I.a_diag, dbg);
+        for (int v = 0; v < 4; ++v) {
+          const int i = (tr0 + a) * 16 + 4 * (lane / 16) + v, j = (tc0 + b) * 16 + lane % 16;
+          // FP32 path: put_A of (i <= j) overwrites only (i, j), which this lane
+          // owns, and (j, i), whose owner does not use its value; so every value
+          // that is used is read before anything overwrites it.
+          const double c = P == 1 ? sm.Bm[i * LDB + j] : (double)acc[a][b][v];
+          put_A<M>(sm, i, j, m, c, I.a_diag, dbg);
+        }
   }
   // b: threads sharing j = tid % M hold partial sums
   sm.red()[tid] = bpart;
@@ -685,11 +703,72 @@ __device__ int jacobi(AnaSmem<M>& sm) {
   return sweeps;
 }
 
+// One step of iterative refinement of wbar = A^-1 b (FP64 path).  U from the
+// one-sided Jacobi carries rounding of order eps |L| in every column, which the
+// weights 1/lambda of U Lambda^-1 U^T b amplify for the small eigenvalues
+// (wbar relative errors ~1e-10 at m = 100 against ~1e-12 for W).  The
+// residual res = b - A wbar is therefore formed with the exact
+// A = (m-1)/rho I + Y'^T diag(r) Y', applied through the domain's observation
+// rows (staged in LDS chunks as in the gather), and wbar += U Lambda^-1 U^T res.
+// Uses pcol[0] (residual) and pcol[1] (projection), free after the Cholesky.
+template <int M>
+__device__ void refine_wbar(AnaSmem<M>& sm, const InstDesc& I, int obs_off, int s) {
+  using C = AnaCfg<M>;
+  constexpr int NT = C::NT, KC = C::KC, LDB = C::LDB;
+  constexpr int TPR = NT / KC;  // threads per staged row for its dot product with wbar
+  static_assert(TPR <= 16 && KC <= 32, "row dot products reduce within 16 lanes");
+  double* Xc = (double*)sm.stage;
+  const int m = I.m, tid = threadIdx.x;
+  const double* Yp = (const double*)I.Yp;
+  const int nobs = 2 * s;
+  double cw = 0.0;  // (Y'^T diag(r) Y' wbar)[tid] for tid < M
+  for (int q0 = 0; q0 < nobs; q0 += KC) {
+    const int kc = min(KC, nobs - q0);
+    for (int idx = tid; idx < KC * M; idx += NT) {
+      const int qq = idx / M, j = idx % M;
+      double v = 0.0;
+      if (qq < kc && j < m) v = Yp[(size_t)I.obs_row[2 * obs_off + q0 + qq] * m + j];
+      Xc[idx] = v;
+    }
+    __syncthreads();
+    {
+      const int qq = tid / TPR, part = tid % TPR;
+      double v = 0.0;
+#pragma unroll 2
+      for (int j = part; j < M; j += TPR) v = fma(Xc[qq * M + j], sm.wbar[j], v);
+      v = group_sum<TPR>(v);
+      if (part == 0) sm.rc[qq] = qq < kc ? I.obs_r[2 * obs_off + q0 + qq] * v : 0.0;
+    }
+    __syncthreads();
+    if (tid < M)
+      for (int qq = 0; qq < kc; ++qq) cw = fma(sm.rc[qq], Xc[qq * M + tid], cw);
+    __syncthreads();
+  }
+  double* res = sm.pcol[0];
+  double* z = sm.pcol[1];
+  if (tid < M) res[tid] = tid < m ? sm.bvec[tid] - fma(I.a_diag, sm.wbar[tid], cw) : 0.0;
+  __syncthreads();
+  if (tid < M) {
+    double t = 0.0;
+#pragma unroll 4
+    for (int r = 0; r < M; ++r) t = fma(sm.Bm[tid * LDB + r], res[r], t);
+    z[tid] = tid < m ? t / sm.lam[tid] : 0.0;
+  }
+  __syncthreads();
+  if (tid < M) {
+    double w = 0.0;
+    for (int c = 0; c < m; ++c) w = fma(sm.Bm[c * LDB + tid], z[c], w);
+    if (tid < m) sm.wbar[tid] += w;
+  }
+  __syncthreads();
+}
+
 // ---- a7: lambda, U, wbar = U Lambda^-1 U^T b, T = U sqrt((m-1)/Lambda) U^T + wbar 1^T
 // (from the converged columns sigma_i u_i of L J)
 // Leaves T row-major in Bm (T[k][j] at Bm[k*LDB + j], zero outside m x m).
-template <int M>
-__device__ void transform(AnaSmem<M>& sm, int m, double* dbg) {
+template <int P, int M>
+__device__ void transform(AnaSmem<M>& sm, const InstDesc& I, int obs_off, int s, double* dbg) {
+  const int m = I.m;
   using C = AnaCfg<M>;
   constexpr int NT = C::NT, LDB = C::LDB, TM = C::TM;
   const int tid = threadIdx.x, ti = tid / 16, tj = tid % 16;
@@ -722,6 +801,7 @@ __device__ void transform(AnaSmem<M>& sm, int m, double* dbg) {
     for (int c = 0; c < m; ++c) w += sm.Bm[c * LDB + tid] * sm.zv[c];
     sm.wbar[tid] = tid < m ? w : 0.0;
   }
+  if constexpr (P == 0) refine_wbar<M>(sm, I, obs_off, s);
   double tacc[TM][TM];
 #pragma unroll
   for (int x = 0; x < TM; ++x)
@@ -892,7 +972,7 @@ __global__ __launch_bounds__(256) void k_analysis(const InstDesc* __restrict__ t
   stamp(2);
   const int sweeps = jacobi<P, M>(sm);
   stamp(3);
-  transform<M>(sm, m, dbg);
+  transform<P, M>(sm, I, obs_off, s, dbg);
   stamp(4);
   if (threadIdx.x == 0) {
     if (I.dbg_sweeps) I.dbg_sweeps[l] = sweeps;

@@ -69,6 +69,8 @@ def _check_step(case, X, k, precision, debug=False, dmap=None, check_domains=Non
         for key, v in worst.items():
             assert v < _tol(precision, key), worst
         err.update({"dom_" + k: v for k, v in worst.items()})
+    print(f"[{case.cfg['name']} m={case.m} prec={precision}] worst relative errors: "
+          + ", ".join(f"{k} {v:.1e}" for k, v in err.items()), flush=True)
     f.close()
     return err
 

@@ -138,7 +138,10 @@ def build_case(cfg, m: int | None = None, precision: int | None = None, dmap: Do
     travel = vmax * cfg["frames"] * DT
     truth = FrozenFlow(act_xy, cfg["r0"], cfg["L0"], layers, travel, screen_seed, pitch=PITCH)
     v0 = layers[0]["speed"](0.0) if callable(layers[0]["speed"]) else layers[0]["speed"]
-    phi0, phim1 = independent_screens_at(act_xy, cfg["r0"], cfg["L0"], m, ens_seed, v0 * DT, pitch=PITCH)
+    # the members need von Karman statistics at the actuator points only, so their
+    # screens use two pixels per pitch (the truth keeps four for the slopes)
+    phi0, phim1 = independent_screens_at(act_xy, cfg["r0"], cfg["L0"], m, ens_seed, v0 * DT, oversample=2,
+                                         pitch=PITCH)
     X0 = np.vstack([phi0, phim1])
     if sigma_v is None:
         ph = truth.phase(0.0)
