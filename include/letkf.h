@@ -193,13 +193,21 @@ int letkf_sweep_stats(letkf_handle* h, uint64_t* sweeps, uint64_t* domain_solves
 typedef void (*letkf_done_fn)(void* user, uint64_t frame_id, int status);
 
 /* A server sub-allocates instance workspaces from the caller's device arena
- * (arena_bytes = the HBM budget) and runs one scheduler thread that gathers
- * the pending frames of all instances (at most one per instance per batch,
- * at most max_batch frames) into one batched launch sequence on its own
- * stream.  Frames arriving while a batch runs join the next batch.
+ * (arena_bytes = the HBM budget, 256-byte aligned; letkf_server_reserved_bytes
+ * of it hold the server's own tables and staging) and runs one scheduler
+ * thread.  Instances fall into classes (padded ensemble size 16/32/64/128 x
+ * precision); a batch holds the oldest pending frame of several instances of
+ * one class (at most max_batch), every domain of which is one work item of
+ * one analysis launch.  Up to 8 batches run at once, each on a stream of its
+ * own, so the batches of different classes overlap on the GPU.  An instance
+ * has at most one frame in flight; its frames run in submission order.
  * flags: reserved, 0. */
 int letkf_server_create(void* arena, size_t arena_bytes, int32_t max_batch, uint32_t flags,
                         letkf_server** out);
+
+/* Bytes of a server's arena taken by its own instance table and staging
+ * buffers (independent of the instances admitted). */
+size_t letkf_server_reserved_bytes(void);
 
 /* Admits one instance (same arguments as letkf_create).  LETKF_ENOMEM when
  * the remaining arena cannot hold its workspace. */
@@ -229,11 +237,10 @@ int letkf_submit_frame_device(letkf_handle* h, const double* y_dev, uint64_t fra
 /* Blocks until every submitted frame has completed. */
 int letkf_server_drain(letkf_server* s);
 
-/* Batching window (default 100 us): with the GPU idle and some instances
- * without a pending frame, the scheduler waits at most this long for them
- * before launching a partial batch.  While a batch runs it never launches a
- * partial batch behind it; it waits for every instance or for the GPU to
- * drain.  0 launches as soon as a frame arrives on an idle GPU. */
+/* Batching window (default 100 us): a class is launched as soon as every
+ * idle instance of it (no frame in flight) has a pending frame; otherwise its
+ * oldest pending frame waits at most this long for the others.  0 launches
+ * every frame as soon as it arrives. */
 int letkf_server_set_window(letkf_server* s, uint32_t window_us);
 
 /* Counters since create: frames completed, batches launched, sum of batch

@@ -73,6 +73,8 @@ def _sig(lib):
     lib.letkf_server_set_window.argtypes = [P, C.c_uint32]
     lib.letkf_server_stats.argtypes = [P, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]
     lib.letkf_server_destroy.argtypes = [P]
+    lib.letkf_server_reserved_bytes.argtypes = []
+    lib.letkf_server_reserved_bytes.restype = C.c_size_t
     lib.letkf_strerror.argtypes = [C.c_int]
     lib.letkf_strerror.restype = C.c_char_p
     lib.letkf_last_error.argtypes = []

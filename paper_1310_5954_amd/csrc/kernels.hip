@@ -943,13 +943,8 @@ __device__ void update_mfma(AnaSmem<M>& sm, const InstDesc& I, int est_off, int 
 }
 
 template <int P, int M>
-__global__ __launch_bounds__(256) void k_analysis(const InstDesc* __restrict__ tab,
-                                                  BatchHdr* __restrict__ hdr, int cls) {
+__device__ void analyse_item(AnaSmem<M>& sm, const InstDesc* __restrict__ tab, const ClassBatch& cb, int item) {
   using C = AnaCfg<M>;
-  __shared__ AnaSmem<M> sm;
-  const ClassBatch& cb = hdr->cls[cls];
-  const int item = blockIdx.x;
-  if (item >= cb.dom_off[cb.n]) return;
   const int eb = find_entry(cb.dom_off, cb.n, item);
   const InstDesc& I = tab[cb.inst[eb]];
   const int l = I.order[item - cb.dom_off[eb]];
@@ -985,6 +980,16 @@ __global__ __launch_bounds__(256) void k_analysis(const InstDesc* __restrict__ t
   stamp(5);
 }
 
+// One workgroup per (instance, domain) work item, items item0 + blockIdx.x.
+template <int P, int M>
+__global__ __launch_bounds__(256) void k_analysis(const InstDesc* __restrict__ tab,
+                                                  BatchHdr* __restrict__ hdr, int cls, int item0) {
+  __shared__ AnaSmem<M> sm;
+  const ClassBatch& cb = hdr->cls[cls];
+  const int item = item0 + (int)blockIdx.x;
+  if (item < cb.dom_off[cb.n]) analyse_item<P, M>(sm, tab, cb, item);
+}
+
 // ----------------------------------------------------------------------------
 // launchers
 // ----------------------------------------------------------------------------
@@ -1006,8 +1011,14 @@ static void launch_slopes_t(int rows, const InstDesc* tab, BatchHdr* hdr, int cl
 }
 
 template <int P, int M>
-static void launch_analysis_t(int items, const InstDesc* tab, BatchHdr* hdr, int cls, hipStream_t s) {
-  if (items > 0) hipLaunchKernelGGL((k_analysis<P, M>), dim3(items), dim3(256), 0, s, tab, hdr, cls);
+static void launch_analysis_t(int items, int max_grid, const InstDesc* tab, BatchHdr* hdr, int cls, hipStream_t s) {
+  // A capped grid is issued as consecutive launches of at most max_grid items
+  // on the stream: between them the dispatcher hands CUs to the kernels of
+  // other streams (the server caps the m = 128 class, whose workgroups fill a
+  // CU's LDS, while instances of other classes are resident).
+  const int chunk = (max_grid > 0 && max_grid < items) ? max_grid : items;
+  for (int i0 = 0; i0 < items; i0 += chunk)
+    hipLaunchKernelGGL((k_analysis<P, M>), dim3(min(chunk, items - i0)), dim3(256), 0, s, tab, hdr, cls, i0);
 }
 
 #define LETKF_DISPATCH(FN, cls, ...)                                          \
@@ -1032,14 +1043,14 @@ void launch_slopes(int cls, int rows, const InstDesc* tab, BatchHdr* hdr, hipStr
 void launch_rows(int cls, int mode, int rows, const InstDesc* tab, BatchHdr* hdr, hipStream_t s) {
   LETKF_DISPATCH(launch_rows_t, cls, mode, rows, tab, hdr, cls, s);
 }
-void launch_analysis(int cls, int items, const InstDesc* tab, BatchHdr* hdr, hipStream_t s) {
+void launch_analysis(int cls, int items, const InstDesc* tab, BatchHdr* hdr, hipStream_t s, int max_grid) {
   const int prec = cls / 4, sz = cls % 4;
-#define LETKF_ANA(P)                                                   \
-  do {                                                                 \
-    if (sz == 0) launch_analysis_t<P, 16>(items, tab, hdr, cls, s);    \
-    else if (sz == 1) launch_analysis_t<P, 32>(items, tab, hdr, cls, s); \
-    else if (sz == 2) launch_analysis_t<P, 64>(items, tab, hdr, cls, s); \
-    else launch_analysis_t<P, 128>(items, tab, hdr, cls, s);           \
+#define LETKF_ANA(P)                                                                \
+  do {                                                                              \
+    if (sz == 0) launch_analysis_t<P, 16>(items, max_grid, tab, hdr, cls, s);       \
+    else if (sz == 1) launch_analysis_t<P, 32>(items, max_grid, tab, hdr, cls, s);  \
+    else if (sz == 2) launch_analysis_t<P, 64>(items, max_grid, tab, hdr, cls, s);  \
+    else launch_analysis_t<P, 128>(items, max_grid, tab, hdr, cls, s);              \
   } while (0)
   if (prec == 0) LETKF_ANA(0);
   else if (prec == 1) LETKF_ANA(1);

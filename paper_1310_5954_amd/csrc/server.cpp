@@ -5,18 +5,24 @@
 // is refused with LETKF_ENOMEM and can be admitted once others are removed.
 //
 // Continuous batching: submit_frame copies the slopes into the instance's
-// queue and returns.  A scheduler thread repeatedly takes the oldest pending
-// frame of every instance that has one (one frame per instance per batch,
-// at most max_batch) and enqueues one launch sequence for the whole batch on
-// the server stream: upload {header, slopes} -> slope synthesis per class ->
-// domain analysis per class -> merge + forecast per class -> download of the
-// prediction means.  Classes group instances of equal padded ensemble size
-// and storage precision; every domain of every instance of a class is one
-// work item of the same analysis launch.  While a batch runs, the next one is
-// prepared in another staging slot; frames that arrive meanwhile join it.
-// A completion thread waits for each batch, copies the means to the callers'
-// buffers and fires the callbacks.  Frames of one instance stay in order
-// because batches execute in stream order.
+// queue and returns.  Instances fall into classes (equal padded ensemble size
+// and storage precision); a batch holds the oldest pending frame of several
+// instances of one class (at most max_batch), and every domain of every
+// instance in it is one work item of the same analysis launch.  Each of the
+// kSlots staging slots has its own stream, so batches of different classes
+// (or of other instances of the same class) run on the GPU at the same time
+// and a light instance never waits behind a heavy one.  A batch is
+//   upload {header, slopes} -> slope synthesis -> domain analysis ->
+//   merge + forecast -> download of the prediction means
+// on its slot's stream.  An instance has at most one frame in flight, which
+// keeps its frames in order across streams.
+//
+// Launch policy (scheduler thread): a class with ready frames is launched
+// when every idle instance of the class has a frame (nothing to wait for), or
+// when its oldest ready frame has waited window_us for the others; among
+// launchable classes the one with the oldest frame goes first.  One
+// completion thread per slot waits for its batch, copies the means to the
+// callers' buffers and fires the callbacks (which may submit again).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -39,9 +45,11 @@ using namespace letkf;
 namespace {
 
 constexpr int kMaxInstances = 64;
-constexpr int kSlots = 3;                 // staging slots (batches in flight + in preparation)
+constexpr int kSlots = 8;                 // staging slots = concurrent batches (one stream each)
 constexpr size_t kStageDoubles = 1 << 18; // slopes per slot and means per slot (each 2 MiB)
 constexpr size_t kQueueCap = 64;          // pending frames per instance
+
+using Clock = std::chrono::steady_clock;
 
 struct Frame {
   uint64_t id;
@@ -50,10 +58,12 @@ struct Frame {
   void* user;
   std::vector<double> y;       // host slopes (copied at submit), or empty when ydev is set
   const double* ydev;          // caller's device slopes
+  Clock::time_point t_enq{};   // submission time (batching window)
 };
 
 struct Batch {
   int slot;
+  int grid_cap = 0;            // analysis workgroups (0 = one per domain item)
   std::vector<std::pair<letkf_handle*, Frame>> frames;
   std::vector<int32_t> out_off;
 };
@@ -65,9 +75,10 @@ struct letkf_server {
   size_t arena_bytes = 0;
   int device = 0;
   int max_batch = kMaxBatch;
-  int64_t window_us = 100;        // idle-GPU wait for the other instances' frames
-  hipStream_t stream = nullptr;   // batches
-  hipStream_t upload = nullptr;   // admissions
+  int num_cu = 256;
+  int64_t window_us = 100;        // longest wait of a ready frame for the rest of its class
+  hipStream_t stream[kSlots] = {};  // one per staging slot
+  hipStream_t upload = nullptr;   // admissions, state access of idle instances
   // arena: [table][hdr x kSlots][y x kSlots][means x kSlots][instance region]
   size_t table_off = 0, hdr_off = 0, y_off = 0, out_off = 0, region_off = 0;
   std::map<size_t, size_t> free_list;  // offset -> bytes (instance region)
@@ -76,7 +87,9 @@ struct letkf_server {
   double* h_y[kSlots] = {};
   double* h_out[kSlots] = {};
   hipEvent_t done_ev[kSlots] = {};
-  bool slot_busy[kSlots] = {};
+  bool slot_busy[kSlots] = {};     // launched or being launched
+  bool slot_has[kSlots] = {};      // slot_batch[k] is waiting for its completion thread
+  Batch slot_batch[kSlots];
 
   std::mutex mu;
   std::condition_variable cv_work;   // scheduler: new frames / stop
@@ -85,12 +98,11 @@ struct letkf_server {
   std::vector<letkf_handle*> inst;   // by table slot (nullptr = free)
   std::map<letkf_handle*, std::deque<Frame>> queues;
   std::map<letkf_handle*, int> in_flight;
-  std::deque<Batch> running;        // launched, not yet taken by the completion thread
-  int inflight = 0;                 // launched and not yet completed
+  int inflight = 0;                 // batches launched and not yet completed
   int rr = 0;
   bool stop = false;
   uint64_t frames_done = 0, batches = 0, batched_frames = 0, pending = 0;
-  std::thread sched, compl_thr;
+  std::thread sched, compl_thr[kSlots];
 
   InstDesc* table() { return (InstDesc*)(arena + table_off); }
   BatchHdr* dhdr(int s) { return (BatchHdr*)(arena + hdr_off) + s; }
@@ -98,7 +110,7 @@ struct letkf_server {
   double* dout(int s) { return (double*)(arena + out_off) + (size_t)s * 2 * kStageDoubles; }
 
   void scheduler_loop();
-  void completion_loop();
+  void completion_loop(int k);
   int launch_batch(Batch& b);
 };
 
@@ -136,18 +148,18 @@ int letkf_server::launch_batch(Batch& b) {
     rows_act[h->cls] = cb.act_off[k + 1];
     items[h->cls] = cb.dom_off[k + 1];
   }
-  LETKF_HIP(hipMemcpyAsync(dhdr(s), &H, sizeof(H), hipMemcpyHostToDevice, stream));
-  if (ytot) LETKF_HIP(hipMemcpyAsync(dy(s), h_y[s], ytot * sizeof(double), hipMemcpyHostToDevice, stream));
+  hipStream_t st = stream[s];
+  LETKF_HIP(hipMemcpyAsync(dhdr(s), &H, sizeof(H), hipMemcpyHostToDevice, st));
+  if (ytot) LETKF_HIP(hipMemcpyAsync(dy(s), h_y[s], ytot * sizeof(double), hipMemcpyHostToDevice, st));
   for (int c = 0; c < kNumClasses; ++c)
-    if (H.cls[c].n) launch_slopes(c, rows_slopes[c], table(), dhdr(s), stream);
+    if (H.cls[c].n) launch_slopes(c, rows_slopes[c], table(), dhdr(s), st);
   for (int c = 0; c < kNumClasses; ++c)
-    if (H.cls[c].n) launch_analysis(c, items[c], table(), dhdr(s), stream);
+    if (H.cls[c].n) launch_analysis(c, items[c], table(), dhdr(s), st, b.grid_cap);
   for (int c = 0; c < kNumClasses; ++c)
-    if (H.cls[c].n) launch_rows(c, 2, rows_act[c], table(), dhdr(s), stream);
+    if (H.cls[c].n) launch_rows(c, 2, rows_act[c], table(), dhdr(s), st);
   LETKF_HIP(hipGetLastError());
-  LETKF_HIP(hipMemcpyAsync(h_out[s], dout(s) + kStageDoubles, otot * sizeof(double), hipMemcpyDeviceToHost,
-                           stream));
-  LETKF_HIP(hipEventRecord(done_ev[s], stream));
+  LETKF_HIP(hipMemcpyAsync(h_out[s], dout(s) + kStageDoubles, otot * sizeof(double), hipMemcpyDeviceToHost, st));
+  LETKF_HIP(hipEventRecord(done_ev[s], st));
   return LETKF_OK;
 }
 
@@ -157,33 +169,57 @@ void letkf_server::scheduler_loop() {
   for (;;) {
     cv_work.wait(lk, [&] { return stop || pending > 0; });
     if (stop && pending == 0) return;
-    // Adaptive batching: while a batch runs, a partial batch would only queue
-    // behind it, so wait until every instance has a frame or the GPU drains;
-    // on an idle GPU wait at most window_us for the missing instances.
-    auto all_ready = [&] {
-      for (auto& kv : queues)
-        if (kv.second.empty()) return false;
-      return true;
-    };
-    if (!stop && !all_ready()) {
-      if (inflight > 0) cv_work.wait(lk, [&] { return stop || all_ready() || inflight == 0; });
-      if (!stop && !all_ready() && window_us > 0)
-        cv_work.wait_for(lk, std::chrono::microseconds(window_us), [&] { return stop || all_ready(); });
-    }
     int s = -1;
-    cv_slot.wait(lk, [&] {
-      for (int k = 0; k < kSlots; ++k)
-        if (!slot_busy[k]) { s = k; return true; }
-      return false;
-    });
-    // one frame per instance with pending work, round robin from rr
+    for (int k = 0; k < kSlots; ++k)
+      if (!slot_busy[k]) { s = k; break; }
+    if (s < 0) {
+      cv_slot.wait(lk);
+      continue;
+    }
+    // pick the class to launch
+    const auto now = Clock::now();
+    const auto window = std::chrono::microseconds(window_us);
+    int best = -1;
+    Clock::time_point best_t{}, deadline = Clock::time_point::max();
+    for (int c = 0; c < kNumClasses; ++c) {
+      bool any_ready = false, idle_empty = false;
+      Clock::time_point oldest = Clock::time_point::max();
+      for (letkf_handle* h : inst) {
+        if (!h || h->cls != c || in_flight[h] > 0) continue;
+        auto& q = queues[h];
+        if (q.empty()) {
+          idle_empty = true;
+        } else {
+          any_ready = true;
+          oldest = std::min(oldest, q.front().t_enq);
+        }
+      }
+      if (!any_ready) continue;
+      if (stop || !idle_empty || now - oldest >= window) {
+        if (best < 0 || oldest < best_t) { best = c; best_t = oldest; }
+      } else {
+        deadline = std::min(deadline, oldest + window);
+      }
+    }
+    if (best < 0) {
+      // frames of in-flight instances wait for a completion; others for their window
+      if (deadline == Clock::time_point::max()) cv_work.wait(lk);
+      else cv_work.wait_until(lk, deadline);
+      continue;
+    }
+    // one frame per ready instance of the class, round robin from rr
     Batch b;
     b.slot = s;
+    // m = 128 workgroups fill a CU each (LDS); while instances of other classes
+    // are resident, such a batch keeps a quarter of the CUs free for them
+    if (best % 4 == 3)
+      for (letkf_handle* h : inst)
+        if (h && h->cls != best) { b.grid_cap = num_cu * 3 / 4; break; }
     size_t ytot = 0, otot = 0;
     const int n = (int)inst.size();
     for (int t = 0; t < n && (int)b.frames.size() < max_batch; ++t) {
       letkf_handle* h = inst[(rr + t) % n];
-      if (!h) continue;
+      if (!h || h->cls != best || in_flight[h] > 0) continue;
       auto& q = queues[h];
       if (q.empty()) continue;
       if (ytot + h->P.p() > kStageDoubles || otot + h->P.n_act > kStageDoubles) break;
@@ -209,41 +245,47 @@ void letkf_server::scheduler_loop() {
       for (auto& [h, f] : b.frames) in_flight[h]--;
       slot_busy[s] = false;
       cv_done.notify_all();
+      cv_work.notify_all();
       continue;
     }
     ++batches;
     ++inflight;
     batched_frames += b.frames.size();
-    running.push_back(std::move(b));
+    slot_batch[s] = std::move(b);
+    slot_has[s] = true;
     cv_done.notify_all();
   }
 }
 
-void letkf_server::completion_loop() {
+void letkf_server::completion_loop(int k) {
   (void)hipSetDevice(device);  // a failure shows up as an error status of the first batch
   std::unique_lock<std::mutex> lk(mu);
   for (;;) {
-    cv_done.wait(lk, [&] { return stop || !running.empty(); });
-    if (running.empty()) {
+    cv_done.wait(lk, [&] { return stop || slot_has[k]; });
+    if (!slot_has[k]) {
       if (stop) return;
       continue;
     }
-    Batch b = std::move(running.front());
-    running.pop_front();
+    Batch b = std::move(slot_batch[k]);
+    slot_has[k] = false;
     lk.unlock();
-    const hipError_t e = hipEventSynchronize(done_ev[b.slot]);
+    const hipError_t e = hipEventSynchronize(done_ev[k]);
     const int status = e == hipSuccess ? LETKF_OK : LETKF_EDEVICE;
-    for (size_t k = 0; k < b.frames.size(); ++k) {
-      auto& [h, f] = b.frames[k];
+    for (size_t i = 0; i < b.frames.size(); ++i) {
+      auto& [h, f] = b.frames[i];
       if (status == LETKF_OK && f.pred_out)
-        std::memcpy(f.pred_out, h_out[b.slot] + b.out_off[k], sizeof(double) * h->P.n_act);
-      if (f.cb) f.cb(f.user, f.id, status);
+        std::memcpy(f.pred_out, h_out[k] + b.out_off[i], sizeof(double) * h->P.n_act);
     }
+    // callbacks first, then the instances are released: the frames that the
+    // callbacks of one batch submit are all queued when the scheduler looks
+    // at them again, so closed loops keep full batches
+    for (auto& [h, f] : b.frames)
+      if (f.cb) f.cb(f.user, f.id, status);
     lk.lock();
     for (auto& [h, f] : b.frames) in_flight[h]--;
     frames_done += b.frames.size();
     --inflight;
-    slot_busy[b.slot] = false;
+    slot_busy[k] = false;
     cv_slot.notify_all();
     cv_done.notify_all();
     cv_work.notify_all();
@@ -256,12 +298,28 @@ int letkf::server_idle_stream(letkf_handle* h, hipStream_t* stream) {
     std::lock_guard<std::mutex> lk(s->mu);
     if (!s->queues[h].empty() || s->in_flight[h] > 0) return fail(LETKF_EAGAIN, "instance has frames in flight");
   }
-  LETKF_HIP(hipStreamSynchronize(s->stream));
-  *stream = s->stream;
+  // the instance's last batch has completed (its completion thread released
+  // it), so the admission stream can touch its workspace
+  LETKF_HIP(hipStreamSynchronize(s->upload));
+  *stream = s->upload;
   return LETKF_OK;
 }
 
 extern "C" {
+
+static size_t reserved_layout(size_t* table_off, size_t* hdr_off, size_t* y_off, size_t* out_off) {
+  size_t off = 0;
+  *table_off = off; off = align256(off + sizeof(InstDesc) * kMaxInstances);
+  *hdr_off = off; off = align256(off + sizeof(BatchHdr) * kSlots);
+  *y_off = off; off = align256(off + sizeof(double) * kStageDoubles * kSlots);
+  *out_off = off; off = align256(off + 2 * sizeof(double) * kStageDoubles * kSlots);
+  return off;
+}
+
+size_t letkf_server_reserved_bytes(void) {
+  size_t a, b, c, d;
+  return reserved_layout(&a, &b, &c, &d);
+}
 
 int letkf_server_create(void* arena, size_t arena_bytes, int32_t max_batch, uint32_t flags, letkf_server** out) {
   if (!out) return fail(LETKF_EINVAL, "null out");
@@ -273,18 +331,17 @@ int letkf_server_create(void* arena, size_t arena_bytes, int32_t max_batch, uint
   s->arena = (char*)arena;
   s->arena_bytes = arena_bytes;
   s->max_batch = max_batch;
-  size_t off = 0;
-  s->table_off = off; off = align256(off + sizeof(InstDesc) * kMaxInstances);
-  s->hdr_off = off; off = align256(off + sizeof(BatchHdr) * kSlots);
-  s->y_off = off; off = align256(off + sizeof(double) * kStageDoubles * kSlots);
-  s->out_off = off; off = align256(off + 2 * sizeof(double) * kStageDoubles * kSlots);
+  const size_t off = reserved_layout(&s->table_off, &s->hdr_off, &s->y_off, &s->out_off);
   s->region_off = off;
   if (arena_bytes < off + 256) { delete s; return fail(LETKF_ENOMEM, "arena smaller than the server's own tables"); }
   s->free_list[off] = arena_bytes - off;
   s->inst.assign(kMaxInstances, nullptr);
   int rc = LETKF_OK;
   if (hipGetDevice(&s->device) != hipSuccess) rc = fail(LETKF_EDEVICE, "hipGetDevice");
-  if (!rc && hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess) rc = fail(LETKF_EDEVICE, "stream");
+  if (!rc && hipDeviceGetAttribute(&s->num_cu, hipDeviceAttributeMultiprocessorCount, s->device) != hipSuccess)
+    rc = fail(LETKF_EDEVICE, "hipDeviceGetAttribute");
+  for (int k = 0; k < kSlots && !rc; ++k)
+    if (hipStreamCreateWithFlags(&s->stream[k], hipStreamNonBlocking) != hipSuccess) rc = fail(LETKF_EDEVICE, "stream");
   if (!rc && hipStreamCreateWithFlags(&s->upload, hipStreamNonBlocking) != hipSuccess) rc = fail(LETKF_EDEVICE, "stream");
   for (int k = 0; k < kSlots && !rc; ++k) {
     if (hipHostMalloc((void**)&s->h_hdr[k], sizeof(BatchHdr)) != hipSuccess ||
@@ -295,7 +352,7 @@ int letkf_server_create(void* arena, size_t arena_bytes, int32_t max_batch, uint
   }
   if (rc) { letkf_server_destroy(s); return rc; }
   s->sched = std::thread([s] { s->scheduler_loop(); });
-  s->compl_thr = std::thread([s] { s->completion_loop(); });
+  for (int k = 0; k < kSlots; ++k) s->compl_thr[k] = std::thread([s, k] { s->completion_loop(k); });
   *out = s;
   return LETKF_OK;
 }
@@ -395,6 +452,7 @@ static int enqueue(letkf_handle* h, Frame&& f) {
   if (s->stop) return fail(LETKF_ESTATE, "server is stopping");
   auto& q = s->queues[h];
   if (q.size() >= kQueueCap) return fail(LETKF_EAGAIN, "instance queue full");
+  f.t_enq = Clock::now();
   q.push_back(std::move(f));
   s->pending++;
   s->cv_work.notify_one();
@@ -422,7 +480,7 @@ int letkf_server_drain(letkf_server* s) {
   if (!s) return fail(LETKF_EINVAL, "null server");
   std::unique_lock<std::mutex> lk(s->mu);
   s->cv_done.wait(lk, [&] {
-    if (s->pending || !s->running.empty()) return false;
+    if (s->pending || s->inflight) return false;
     for (auto& [h, n] : s->in_flight)
       if (n) return false;
     return true;
@@ -458,7 +516,7 @@ int letkf_server_destroy(letkf_server* s) {
     s->cv_done.notify_all();
     s->cv_slot.notify_all();
     s->sched.join();
-    s->compl_thr.join();
+    for (auto& t : s->compl_thr) t.join();
   }
   for (letkf_handle* h : s->inst)
     if (h) {
@@ -471,7 +529,8 @@ int letkf_server_destroy(letkf_server* s) {
     if (s->h_out[k]) (void)hipHostFree(s->h_out[k]);
     if (s->done_ev[k]) (void)hipEventDestroy(s->done_ev[k]);
   }
-  if (s->stream) (void)hipStreamDestroy(s->stream);
+  for (auto& st : s->stream)
+    if (st) (void)hipStreamDestroy(st);
   if (s->upload) (void)hipStreamDestroy(s->upload);
   delete s;
   return LETKF_OK;

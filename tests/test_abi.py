@@ -108,3 +108,10 @@ def test_create_rejects_small_workspace_before_device_work():
 def test_strerror_covers_codes():
     for code in (L.OK, L.EINVAL, L.ENOMEM, L.EAGAIN, L.EDEVICE, L.ENUMERIC, L.ESTATE):
         assert L.lib().letkf_strerror(code)
+
+
+def test_server_reserved_bytes_is_a_host_query():
+    """The server's own share of an arena is known before any device work
+    (it sizes HBM budgets); 256-byte aligned like every arena region."""
+    n = L.lib().letkf_server_reserved_bytes()
+    assert n > 0 and n % 256 == 0

@@ -1,7 +1,9 @@
 """GPU serving: continuous batching across resident instances.
 
-* A frame's result is the same alone and in a mixed batch (bit-identical:
-  per-domain work has a fixed order and the merge uses no atomics).
+* A frame's result is the same alone and in the mix, where it shares a
+  launch with frames of its class and runs beside batches of other classes
+  (bit-identical: per-domain work has a fixed order and the merge uses no
+  atomics).
 * The server path equals the plain per-frame path.
 * Instances are admitted against the HBM budget and re-admitted when
   memory frees up.
@@ -10,6 +12,7 @@ import numpy as np
 import pytest
 
 from paper_1310_5954_amd import BF16, FP32, FP64, Filter, LetkfError, Problem, Server
+from paper_1310_5954_amd import _lib as L
 from workload.configs import build_case
 
 pytestmark = pytest.mark.gpu
@@ -18,11 +21,16 @@ FRAMES = 8
 
 
 def _mix_cases():
+    """Five classes (padded ensemble size x precision) and, in the first
+    class, two instances with different pupils and ensembles, so that some
+    batches share launches and batches of other classes run beside them."""
     c16 = dict(build_case(2).cfg)
     c16.update(lenslets=16, seeds=(21, 22, 23))
     c24 = dict(build_case(2).cfg)
     c24.update(lenslets=24, seeds=(31, 32, 33), m=64)
-    return [(build_case(1), FP64), (build_case(2), FP32), (build_case(c16, m=20), FP64),
+    c12 = dict(build_case(1).cfg)
+    c12.update(lenslets=12, seeds=(41, 42, 43), window=3, stride=3)
+    return [(build_case(1), FP64), (build_case(c12), FP64), (build_case(2), FP32), (build_case(c16, m=20), FP64),
             (build_case(c24), BF16), (build_case(1, m=33), FP64)]
 
 
@@ -48,7 +56,7 @@ def _run_server(cases, frames=FRAMES, drain_each=False, budget=1 << 30):
 def test_alone_vs_in_the_mix_bit_identical():
     cases = _mix_cases()
     mixed_preds, mixed_states, stats = _run_server(cases)
-    assert stats["batched_frames"] / stats["batches"] > 1.5, stats    # frames really shared launches
+    assert stats["batched_frames"] > stats["batches"], stats    # some frames really shared launches
     for i, cp in enumerate(cases):
         alone_preds, alone_states, _ = _run_server([cp], drain_each=True)
         for k in range(FRAMES):
@@ -73,7 +81,7 @@ def test_admission_by_hbm_budget():
     pr = Problem.from_case(case)
     ws = pr.workspace_size(FP64)
     assert ws > 16 << 20
-    server_tables = 20 << 20          # staging and tables of the server itself (about 18 MiB)
+    server_tables = L.lib().letkf_server_reserved_bytes()   # staging and tables of the server itself
     srv = Server(server_tables + int(2.5 * ws))
     a = srv.add(pr, case.X0, FP64)
     b = srv.add(pr, case.X0, FP64)
