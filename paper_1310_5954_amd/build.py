@@ -19,12 +19,17 @@ ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          # keep hipcc from emitting packed FP32 VALU ops
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         # MFMA sources and results in ordinary VGPRs: accumulators in AGPRs
+         # would push the analysis kernel from 3 to 2 wavefronts per SIMD
+         "-mllvm", "-amdgpu-mfma-vgpr-form",
          "-I", os.path.join(HERE, "..", "include")]
 
 
 def source_hash() -> str:
     """Hash of every source and header the library is built from."""
     h = hashlib.sha256()
+    # compiler flags too (without the include path, which differs per checkout)
+    h.update(" ".join(f for f in FLAGS if not f.startswith(("/", "-I"))).encode())
     files = sorted(f for f in os.listdir(CSRC) if f.endswith((".hip", ".cpp", ".hpp")))
     for f in files + ["../../include/letkf.h"]:
         with open(os.path.join(CSRC, f), "rb") as fh:

@@ -324,6 +324,95 @@ __device__ void gather_C_fp64(AnaSmem<M>& sm, const InstDesc& I, int obs_off, in
   __syncthreads();
 }
 
+// ---- a4/a5 on the FP64 path with FP64 MFMA (M <= 64) -------------------------
+// As on the MFMA paths below, a chunk of KCH observations is staged transposed
+// as At[j][k] = sqrt(r_k) Y'[k][j] (FP64), and wave w owns a WT x WT block of
+// 16 x 16 tiles of C, accumulated by v_mfma_f64_16x16x4f64 in FP64 registers.
+// A single wavefront per SIMD issues a VALU instruction only every ~8.5
+// cycles, so the matrix core reaches the FP64 rate that the FMA loop cannot.
+// (M = 128 would need 64 accumulators per lane and keeps the FMA loop.)
+// Lane layout of v_mfma_f64_16x16x4f64 (measured on gfx950): A[i][k] in lane
+// i + 16 k, B[k][j] in lane j + 16 k, and result register v of lane l holds
+// D[l / 16 + 4 v][l % 16] (rows interleaved, unlike the FP32 16x16x4 form).
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+template <int M>
+__device__ void gather_C_fp64_mfma(AnaSmem<M>& sm, const InstDesc& I, int obs_off, int s, double* dbg) {
+  using C = AnaCfg<M>;
+  constexpr int NT = C::NT, KCH = 16, LDK = KCH + 2;
+  constexpr int TILES = M / 16;
+  constexpr int WT = TILES >= 2 ? TILES / 2 : 1;
+  static_assert(M <= 64 && (size_t)M * LDK * 8 <= C::STAGE_BYTES, "staging");
+  double* At = (double*)sm.stage;
+  const int m = I.m, tid = threadIdx.x, w = tid / 64, lane = tid % 64;
+  const bool wave_on = TILES >= 2 || w == 0;
+  const int tr0 = TILES >= 2 ? (w / 2) * WT : 0;
+  const int tc0 = TILES >= 2 ? (w % 2) * WT : 0;
+  f64x4 acc[WT][WT];
+#pragma unroll
+  for (int a = 0; a < WT; ++a)
+#pragma unroll
+    for (int b = 0; b < WT; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
+  double bpart = 0.0;
+  const double* Yp = (const double*)I.Yp;
+  const int nobs = 2 * s;
+  for (int q0 = 0; q0 < nobs; q0 += KCH) {
+    const int kc = min(KCH, nobs - q0);
+    if (tid < KCH) {
+      double r = 0.0, dd = 0.0;
+      if (tid < kc) {
+        r = I.obs_r[2 * obs_off + q0 + tid];
+        dd = I.d[I.obs_row[2 * obs_off + q0 + tid]];
+      }
+      sm.rc[tid] = sqrt(r);
+      sm.dc[tid] = r * dd;
+    }
+    __syncthreads();
+    for (int idx = tid; idx < KCH * M; idx += NT) {
+      const int kk = idx / M, j = idx % M;
+      double y = 0.0;
+      if (kk < kc && j < m) y = Yp[(size_t)I.obs_row[2 * obs_off + q0 + kk] * m + j];
+      bpart = fma(sm.dc[kk], y, bpart);
+      At[j * LDK + kk] = sm.rc[kk] * y;
+    }
+    __syncthreads();
+    if (wave_on) {
+#pragma unroll
+      for (int ks = 0; ks < KCH / 4; ++ks) {
+        double av[WT], bv[WT];
+#pragma unroll
+        for (int a = 0; a < WT; ++a) {
+          av[a] = At[((tr0 + a) * 16 + lane % 16) * LDK + ks * 4 + lane / 16];
+          bv[a] = At[((tc0 + a) * 16 + lane % 16) * LDK + ks * 4 + lane / 16];
+        }
+#pragma unroll
+        for (int a = 0; a < WT; ++a)
+#pragma unroll
+          for (int b = 0; b < WT; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
+  if (wave_on) {
+#pragma unroll
+    for (int a = 0; a < WT; ++a)
+#pragma unroll
+      for (int b = 0; b < WT; ++b)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          put_A<M>(sm, (tr0 + a) * 16 + lane / 16 + 4 * v, (tc0 + b) * 16 + lane % 16, m, acc[a][b][v], I.a_diag, dbg);
+  }
+  // b: threads sharing j = tid % M hold partial sums
+  sm.red()[tid] = bpart;
+  __syncthreads();
+  if (tid < M) {
+    double t = 0.0;
+    for (int q = tid; q < NT; q += M) t += sm.red()[q];
+    sm.bvec[tid] = tid < m ? t : 0.0;
+  }
+  __syncthreads();
+}
+
 // ---- a4/a5 on the MFMA paths ------------------------------------------------
 // The chunk of observations is staged transposed, At[j][k] = sqrt(r_k) Y'[k][j],
 // so that C = At At^T is one MFMA product per 16 x 16 tile.  Wave w owns a
@@ -915,24 +1004,37 @@ __device__ void load_rows(AnaSmem<M>& sm, S* X, const InstDesc& I, int est_off, 
   __syncthreads();
 }
 
-// ---- a8 on the FP64 path: Z = xbar 1^T + X' T --------------------------------
+// ---- a8 on the FP64 path: Z = xbar 1^T + X' T with FP64 MFMA ----------------
+// Chunks of 16 state rows (both instants) are staged with their member means;
+// wave w computes the 16 x 16 output tiles w, w + 4, ... of the chunk with
+// v_mfma_f64_16x16x4f64 (A = X' - xbar from LDS, B = T from Bm).
 template <int M>
 __device__ void update_fp64(AnaSmem<M>& sm, const InstDesc& I, int est_off, int e, int cur) {
   using C = AnaCfg<M>;
-  constexpr int NT = C::NT, LDB = C::LDB, KC = C::KC;
-  const int m = I.m, tid = threadIdx.x;
-  double* Xc = (double*)sm.stage;
+  constexpr int LDB = C::LDB, KR = 16, CB = M / 16;
+  static_assert((size_t)KR * M * 8 <= C::STAGE_BYTES, "staging");
+  const int m = I.m, tid = threadIdx.x, w = tid / 64, lane = tid % 64;
+  double* Xd = (double*)sm.stage;
   double* Z = (double*)I.Z + (size_t)2 * est_off * m;
-  for (int q0 = 0; q0 < 2 * e; q0 += KC) {
-    const int kc = min(KC, 2 * e - q0);
-    load_rows<M, KC, double>(sm, Xc, I, est_off, e, cur, q0, kc);
-    for (int idx = tid; idx < kc * M; idx += NT) {
-      const int qq = idx / M, j = idx % M;
-      if (j < m) {
-        const double xb = sm.rc[qq];
-        double z = 0.0;
-        for (int k = 0; k < m; ++k) z += (Xc[qq * M + k] - xb) * sm.Bm[k * LDB + j];
-        Z[(size_t)(q0 + qq) * m + j] = xb + z;
+  for (int q0 = 0; q0 < 2 * e; q0 += KR) {
+    const int kc = min(KR, 2 * e - q0);
+    load_rows<M, KR, double>(sm, Xd, I, est_off, e, cur, q0, kc);
+    for (int cb = w; cb < CB; cb += 4) {
+      const int arow = lane % 16;
+      const double xb = sm.rc[arow];
+      const int col = cb * 16 + lane % 16;
+      f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+      for (int ks = 0; ks < M / 4; ++ks) {
+        const int k = ks * 4 + lane / 16;
+        const double a = k < m ? Xd[arow * M + k] - xb : 0.0;
+        const double b = sm.Bm[k * LDB + col];
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = lane / 16 + 4 * v;
+        if (row < kc && col < m) Z[(size_t)(q0 + row) * m + col] = sm.rc[row] + acc[v];
       }
     }
     __syncthreads();
@@ -1011,7 +1113,8 @@ __device__ void analyse_item(AnaSmem<M>& sm, const InstDesc* __restrict__ tab, c
   };
   stamp(0);
 
-  if constexpr (P == 0) gather_C_fp64<M>(sm, I, obs_off, s, dbg);
+  if constexpr (P == 0 && M <= 64) gather_C_fp64_mfma<M>(sm, I, obs_off, s, dbg);
+  else if constexpr (P == 0) gather_C_fp64<M>(sm, I, obs_off, s, dbg);
   else gather_C_mfma<P, M>(sm, I, obs_off, s, dbg);
   stamp(1);
   if constexpr (AnaCfg<M>::TM <= 4) cholesky<M>(sm);
