@@ -340,6 +340,8 @@ def main() -> int:
     ap.add_argument("--window-us", type=int, default=100, help="server batching window (microseconds)")
     ap.add_argument("--workload", type=int, default=84, choices=[84, 128],
                     help="84: 84x84 subapertures, m = 64 (headline); 128: 128x128, m = 128")
+    ap.add_argument("--partitions", type=int, default=1, choices=[1, 2],
+                    help="2: the window partition plus one staggered by half a stride, averaged (Sec. 5)")
     ap.add_argument("--serving-only", action="store_true",
                     help="skip the plain-path runs (for profiling the serving kernels); no roofline line")
     ap.add_argument("--copy-ref", action="store_true",
@@ -369,7 +371,7 @@ def main() -> int:
     from workload.configs import build_case
 
     prec = dict(fp64=FP64, fp32=FP32, bf16=BF16)[args.precision]
-    case = build_case(3 if args.workload == 84 else 5)
+    case = build_case(3 if args.workload == 84 else 5, partitions=args.partitions)
     K, W, NL, B = args.steps, args.warmup, args.latency_frames, args.instances
     n_frames = W + K + NL
     L_ = case.cfg["lenslets"]
@@ -427,8 +429,9 @@ def main() -> int:
         dtype=dtype, data="synthetic",
         config=dict(workload=f"{L_}x{L_} circular SH pupil, {case.n_act} actuators (n={2 * case.n_act}), "
                              f"{case.n_sub} subapertures (p={2 * case.n_sub}), "
-                             f"m={case.m}, {case.dmap.n_domains} overlapping 6x6-actuator domains, halo 2, "
-                             "Gaspari-Cohn taper; one frame = analysis + AR(2) forecast",
+                             f"m={case.m}, {case.dmap.n_domains} overlapping 6x6-actuator domains"
+                             + (" (two staggered partitions, averaged)" if args.partitions == 2 else "")
+                             + ", halo 2, Gaspari-Cohn taper; one frame = analysis + AR(2) forecast",
                     path=path, precision=args.precision if serving_out else "fp64"),
         p50_us=round(p50, 1), p99_us=round(p99, 1),
         plain_fp64=plain_out, roofline=roofline, library=build_id(),

@@ -108,3 +108,20 @@ def test_global_domain_is_everything():
     dm = global_domain(geom)
     assert dm.n_domains == 1
     assert len(dm.est(0)) == geom.n_act and len(dm.obs(0)) == geom.n_sub
+
+
+def test_staggered_partition_covers_and_combines():
+    """A partition shifted by half a stride covers every actuator, its window
+    corners differ from the unshifted ones, and the combined map's weights
+    still sum to one per actuator."""
+    from workload.geometry import combine_maps
+    g = build_geometry(40)
+    a = window_domains(g, 5, 3, 2, taper=True)
+    b = window_domains(g, 5, 3, 2, taper=True, shift=1)
+    first = {tuple(a.est(l)[:1]) for l in range(a.n_domains)}
+    assert any(tuple(b.est(l)[:1]) not in first for l in range(b.n_domains))
+    both = combine_maps([a, b])
+    assert both.n_domains == a.n_domains + b.n_domains
+    acc = np.zeros(g.n_act)
+    np.add.at(acc, both.est_act, both.est_w)
+    np.testing.assert_allclose(acc, 1.0, rtol=0, atol=1e-14)

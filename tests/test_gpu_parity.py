@@ -160,6 +160,22 @@ def test_cfg3_full_size_fp64():
     _check_step(case, X, k, FP64, debug=True, check_domains=range(0, case.dmap.n_domains, 7))
 
 
+def test_two_partitions_cfg3_fp64():
+    """84x84 pupil with its window partition and one staggered by half a
+    stride in the same launch (761 domains, merge weights halved): the
+    equal-weight average of the two local analyses."""
+    case = build_case(3, partitions=2)
+    assert case.dmap.n_domains > 700
+    X, k = oracle_spin_up(case, 1)
+    _check_step(case, X, k, FP64, debug=True, check_domains=range(0, case.dmap.n_domains, 13))
+
+
+def test_two_partitions_cfg2_bf16():
+    case = build_case(2, partitions=2)
+    X, k = oracle_spin_up(case, 2)
+    _check_step(case, X, k, BF16)
+
+
 def test_cfg3_full_size_fp32():
     case = build_case(3)
     X, k = oracle_spin_up(case, 2)

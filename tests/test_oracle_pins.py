@@ -317,3 +317,23 @@ def test_forecast_noise_stationary_variance():
             acc.append(np.var(X[:n_act]))
     target = (1 - (-0.64)) / ((1 - 0.64) * ((1 + 0.64) ** 2 - 1.6 ** 2))
     assert abs(np.mean(acc) / target - 1) < 0.06
+
+
+def test_two_partitions_average_the_two_analyses():
+    """Sec. 5 runs two local ETKFs on different domain partitions; read as
+    an equal-weight average, one map holding both partitions' domains with
+    halved merge weights must give exactly the mean of the two analyses
+    (linearity of the weighted merge), and the two partitions must differ."""
+    from workload.geometry import combine_maps
+    rng = np.random.default_rng(21)
+    geom = build_geometry(12, "square")
+    D = fried_slope_matrix(geom).to_dense()
+    a = window_domains(geom, 4, 4, 1)
+    b = window_domains(geom, 4, 4, 1, shift=2)
+    assert a.n_domains != b.n_domains or not np.array_equal(a.est_act, b.est_act)
+    both = combine_maps([a, b])
+    X = rng.standard_normal((geom.n, 8))
+    y = rng.standard_normal(geom.p)
+    r = np.full(geom.p, 4.0)
+    avg = 0.5 * (analysis(X, y, D, a, r) + analysis(X, y, D, b, r))
+    np.testing.assert_allclose(analysis(X, y, D, both, r), avg, rtol=1e-12, atol=1e-12)

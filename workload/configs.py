@@ -22,7 +22,7 @@ from dataclasses import dataclass
 
 import numpy as np
 
-from .geometry import (CSR, DomainMap, Geometry, build_geometry, fried_slope_matrix,
+from .geometry import (CSR, DomainMap, Geometry, build_geometry, combine_maps, fried_slope_matrix,
                        global_domain, window_domains)
 from .turbulence import FrozenFlow, independent_screens_at
 
@@ -120,7 +120,9 @@ def _csr_mv(D: CSR, v: np.ndarray) -> np.ndarray:
 
 
 def build_case(cfg, m: int | None = None, precision: int | None = None, dmap: DomainMap | None = None,
-               global_map: bool = False, sigma_v: float | None = None) -> Case:
+               global_map: bool = False, sigma_v: float | None = None, partitions: int = 1) -> Case:
+    """partitions = 2: the workload's window partition plus one staggered by
+    half a stride, averaged (both run in the same analysis launch)."""
     if isinstance(cfg, int):
         cfg = CONFIGS[cfg]
     cfg = dict(cfg)
@@ -128,8 +130,13 @@ def build_case(cfg, m: int | None = None, precision: int | None = None, dmap: Do
     geom = build_geometry(cfg["lenslets"], cfg["shape"])
     D = fried_slope_matrix(geom)
     if dmap is None:
-        dmap = global_domain(geom) if global_map else window_domains(
-            geom, cfg["window"], cfg["stride"], cfg["halo"], cfg["taper"], cfg["min_actuators"])
+        if global_map:
+            dmap = global_domain(geom)
+        else:
+            parts = [window_domains(geom, cfg["window"], cfg["stride"], cfg["halo"], cfg["taper"],
+                                    cfg["min_actuators"], shift=(k * cfg["stride"]) // partitions)
+                     for k in range(partitions)]
+            dmap = parts[0] if partitions == 1 else combine_maps(parts)
     act_xy = geom.act_rc[:, ::-1].astype(float) * PITCH  # (x = column, y = row)
     screen_seed, noise_seed, ens_seed = cfg["seeds"]
     layers = [dict(L, speed=_speed_fn(L["speed"], cfg["frames"])) for L in cfg["layers"]]

@@ -228,18 +228,23 @@ def _finish_map(geom: Geometry, domains: list, halo: int, taper: bool) -> Domain
 
 
 def window_domains(geom: Geometry, window: int, stride: int, halo: int, taper: bool = False,
-                   min_actuators: int = 0) -> DomainMap:
+                   min_actuators: int = 0, shift: int = 0) -> DomainMap:
     """Square actuator windows of side ``window`` every ``stride`` actuators,
     centred on the actuator grid; observation region = subaperture rows
     [i0-halo, i1+halo-1] x columns [j0-halo, j1+halo-1] of each window
     [i0, i1] x [j0, j1].  Windows with fewer than ``min_actuators`` valid
     actuators are dropped when other windows cover all their actuators, and
     otherwise merged into the kept window sharing the most actuators (the
-    nearest one when none is shared)."""
+    nearest one when none is shared).  ``shift`` (0 < shift < stride) moves
+    the window grid by that many actuators along both axes, with one more
+    window per axis so that the edges stay covered: a staggered partition."""
     side = geom.n_lenslets + 1
     nw = max(1, math.ceil(max(side - window, 0) / stride) + 1)
     span = (nw - 1) * stride + window
     off = (side - span) // 2
+    if shift:
+        off += shift - stride
+        nw += 1
     raw = []
     for wi in range(nw):
         for wj in range(nw):
@@ -309,3 +314,23 @@ def global_domain(geom: Geometry) -> DomainMap:
     side = geom.n_lenslets + 1
     acts = np.arange(geom.n_act, dtype=np.int64)
     return _finish_map(geom, [(acts, (0, side - 1, 0, side - 1))], halo=side, taper=False)
+
+
+def combine_maps(maps: list) -> DomainMap:
+    """One map holding the domains of every map in ``maps``, with each map's
+    merge weights divided by ``len(maps)``: the analysis on it is the equal-
+    weight average of the analyses on the separate maps (several partitions
+    of the pupil run in the same frame, Sec. 5)."""
+    k = float(len(maps))
+    est_ptr, obs_ptr = [0], [0]
+    est_act, est_w, obs_sub, obs_taper = [], [], [], []
+    for dm in maps:
+        for l in range(dm.n_domains):
+            est_act.append(dm.est(l)); est_w.append(dm.weights(l) / k)
+            obs_sub.append(dm.obs(l)); obs_taper.append(dm.taper(l))
+            est_ptr.append(est_ptr[-1] + len(dm.est(l)))
+            obs_ptr.append(obs_ptr[-1] + len(dm.obs(l)))
+    return DomainMap(np.array(est_ptr, np.int32), np.concatenate(est_act).astype(np.int32),
+                     np.concatenate(est_w), np.array(obs_ptr, np.int32),
+                     np.concatenate(obs_sub).astype(np.int32), np.concatenate(obs_taper),
+                     info=dict(partitions=len(maps), parts=[dm.info for dm in maps]))
