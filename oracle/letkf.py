@@ -23,6 +23,18 @@ r = taper * R^-1 on O_l and inflation rho (1 = none):
 The whole-pupil analysis (Sec. 3.2) merges the domain estimates row by row
 with weights omega (sum over the domains covering a row = 1).
 
+Differential pistons (Sec. 3.2): slopes do not see a constant phase, and each
+domain is estimated on its own, so the domain estimates disagree by a
+constant ("differential pistons"), which a post-processing step removes before
+the whole-pupil reconstruction.  The paper does not describe its method; the
+reading here: each domain's rows of instant t (phi_k or phi_{k-1}) and member
+i are shifted by one constant c_l[t, i] chosen by least squares so that the
+domains agree on the actuators they share,
+    minimise  sum_j  sum_{l < l' covering j} (Z_l[j] + c_l - Z_l'[j] - c_l')^2,
+taking the minimum-norm solution and then the constant that leaves the merged
+sum of each member's phase unchanged (sum_l w_l c_l = 0, w_l = sum of domain
+l's merge weights).
+
 Forecast (Sec. 2.1, AR(1) or AR(2) with a2 = 0 giving AR(1)):
     phi_{k+1} = a1 * phi_k + a2 * phi_{k-1} + sigma_v z,   z ~ N(0, I)
 and the new state is [phi_{k+1} ; phi_k].
@@ -71,9 +83,42 @@ def domain_rows(dmap, l: int, n_act: int, n_sub: int):
     return E, O, state_rows, obs_rows
 
 
+def domain_pistons(Zs: list, dmap, n_act: int) -> np.ndarray:
+    """Least-squares differential pistons c[l, t, i] of the domain estimates
+    Zs[l] (rows: the domain's actuators at phi_k, then at phi_{k-1}), as read
+    in the module docstring.  Pairs of domains sharing an actuator, one term
+    per shared actuator, are accumulated into the normal equations
+    Lap c = r of the objective; numpy's pseudo-inverse gives the minimum-norm
+    solution."""
+    L = dmap.n_domains
+    m = Zs[0].shape[1] if L else 0
+    cover = [[] for _ in range(n_act)]
+    for l in range(L):
+        for pos, j in enumerate(dmap.est(l)):
+            cover[int(j)].append((l, pos))
+    lap = np.zeros((L, L))
+    r = np.zeros((L, 2, m))
+    for j in range(n_act):
+        for a, pa in cover[j]:
+            ea = len(dmap.est(a))
+            for b, pb in cover[j]:
+                if a == b:
+                    continue
+                eb = len(dmap.est(b))
+                lap[a, a] += 1.0
+                lap[a, b] -= 1.0
+                for t in (0, 1):
+                    r[a, t] += Zs[b][t * eb + pb] - Zs[a][t * ea + pa]
+    c = np.einsum("lk,ktm->ltm", np.linalg.pinv(lap), r)
+    w = np.array([np.sum(dmap.weights(l)) for l in range(L)])
+    c -= np.einsum("l,ltm->tm", w, c)[None] / w.sum()
+    return c
+
+
 def analysis(X: np.ndarray, y: np.ndarray, D: np.ndarray, dmap, r_inv: np.ndarray,
-             rho: float = 1.0, keep_domains: bool = False):
-    """Whole-pupil local ETKF analysis of the forecast ensemble X (n x m)."""
+             rho: float = 1.0, keep_domains: bool = False, pistons: bool = False):
+    """Whole-pupil local ETKF analysis of the forecast ensemble X (n x m);
+    pistons: remove the differential pistons before the merge."""
     n, m = X.shape
     n_act = n // 2
     p = D.shape[0]
@@ -87,11 +132,19 @@ def analysis(X: np.ndarray, y: np.ndarray, D: np.ndarray, dmap, r_inv: np.ndarra
         E, O, srows, orows = domain_rows(dmap, l, n_act, n_sub)
         taper = np.asarray(dmap.taper(l), dtype=float)
         r_O = np.concatenate([taper, taper]) * r_inv[orows]
-        res = domain_analysis(Xp[srows], xbar[srows], Yp[orows], d[orows], r_O, rho)
+        per_domain.append(domain_analysis(Xp[srows], xbar[srows], Yp[orows], d[orows], r_O, rho))
+    c = domain_pistons([res["Z"] for res in per_domain], dmap, n_act) if pistons else None
+    for l, res in enumerate(per_domain):
+        E, O, srows, orows = domain_rows(dmap, l, n_act, n_sub)
         w = np.asarray(dmap.weights(l), dtype=float)
-        Xa[srows] += np.concatenate([w, w])[:, None] * res["Z"]
-        if keep_domains:
-            per_domain.append(res)
+        Z = res["Z"]
+        if pistons:
+            e = len(E)
+            Z = Z + np.concatenate([np.repeat(c[l, 0][None], e, 0), np.repeat(c[l, 1][None], e, 0)])
+        Xa[srows] += np.concatenate([w, w])[:, None] * Z
+    if pistons and keep_domains:
+        for l, res in enumerate(per_domain):
+            res["piston"] = c[l]
     return (Xa, per_domain) if keep_domains else Xa
 
 

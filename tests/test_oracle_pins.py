@@ -337,3 +337,65 @@ def test_two_partitions_average_the_two_analyses():
     r = np.full(geom.p, 4.0)
     avg = 0.5 * (analysis(X, y, D, a, r) + analysis(X, y, D, b, r))
     np.testing.assert_allclose(analysis(X, y, D, both, r), avg, rtol=1e-12, atol=1e-12)
+
+
+def _overlapping_square_map(N=10, window=4, stride=3):
+    geom = build_geometry(N, "square")
+    return geom, window_domains(geom, window, stride, 1)
+
+
+def test_pistons_reattach_domains_that_differ_by_constants():
+    """Domain estimates equal to one field plus an arbitrary constant per
+    (domain, instant, member) are re-attached exactly: after the shifts
+    every domain carries the same constant, and the weighted sum of the
+    shifts is zero (gauge)."""
+    from oracle.letkf import domain_pistons
+    rng = np.random.default_rng(31)
+    geom, dm = _overlapping_square_map()
+    m = 5
+    f = rng.standard_normal((2, geom.n_act, m))
+    k = rng.standard_normal((dm.n_domains, 2, m)) * 3.0
+    Zs = []
+    for l in range(dm.n_domains):
+        E = dm.est(l)
+        Zs.append(np.vstack([f[0, E] + k[l, 0], f[1, E] + k[l, 1]]))
+    c = domain_pistons(Zs, dm, geom.n_act)
+    shifted = k + c                                   # constant left on each domain
+    np.testing.assert_allclose(shifted - shifted[:1], 0.0, atol=1e-10)
+    w = np.array([dm.weights(l).sum() for l in range(dm.n_domains)])
+    np.testing.assert_allclose(np.einsum("l,ltm->tm", w, c), 0.0, atol=1e-10)
+
+
+def test_pistons_vanish_for_consistent_or_disjoint_domains():
+    from oracle.letkf import domain_pistons
+    rng = np.random.default_rng(32)
+    geom, dm = _overlapping_square_map()
+    f = rng.standard_normal((2, geom.n_act, 3))
+    Zs = [np.vstack([f[0, dm.est(l)], f[1, dm.est(l)]]) for l in range(dm.n_domains)]
+    np.testing.assert_allclose(domain_pistons(Zs, dm, geom.n_act), 0.0, atol=1e-12)
+    sq = build_geometry(8, "square")
+    disjoint = window_domains(sq, 3, 3, 1)
+    Zs = [rng.standard_normal((2 * len(disjoint.est(l)), 3)) for l in range(disjoint.n_domains)]
+    np.testing.assert_allclose(domain_pistons(Zs, disjoint, sq.n_act), 0.0, atol=1e-12)
+
+
+def test_piston_removal_changes_only_the_merged_pistons():
+    """On a real analysis the removal moves the merged estimate but keeps each
+    member's phase sum (gauge) and leaves a non-overlapping map unchanged."""
+    rng = np.random.default_rng(33)
+    geom, dm = _overlapping_square_map()
+    D = fried_slope_matrix(geom).to_dense()
+    X = rng.standard_normal((geom.n, 6))
+    y = rng.standard_normal(geom.p)
+    r = np.full(geom.p, 4.0)
+    a0 = analysis(X, y, D, dm, r)
+    a1 = analysis(X, y, D, dm, r, pistons=True)
+    assert np.abs(a1 - a0).max() > 1e-6
+    np.testing.assert_allclose(a1[:geom.n_act].sum(0), a0[:geom.n_act].sum(0), rtol=1e-10, atol=1e-10)
+    np.testing.assert_allclose(a1[geom.n_act:].sum(0), a0[geom.n_act:].sum(0), rtol=1e-10, atol=1e-10)
+    sq = build_geometry(8, "square")
+    disjoint = window_domains(sq, 3, 3, 1)
+    Dq = fried_slope_matrix(sq).to_dense()
+    Xq = rng.standard_normal((sq.n, 4)); yq = rng.standard_normal(sq.p); rq = np.full(sq.p, 4.0)
+    np.testing.assert_allclose(analysis(Xq, yq, Dq, disjoint, rq, pistons=True), analysis(Xq, yq, Dq, disjoint, rq),
+                               rtol=1e-13, atol=1e-13)
