@@ -98,12 +98,15 @@ def cpu_baseline(case, seconds: float = 15.0):
                        f"m={case.m} workload (NumPy/LAPACK FP64, 1 thread)")
 
 
+PISTONS = False  # set from --pistons
+
+
 def run_plain(case, prec, K, W, NL, ys):
     """Plain per-frame path on one instance: throughput, latency, kernel times."""
     import torch
 
     from paper_1310_5954_amd import Filter, Problem
-    f = Filter(Problem.from_case(case), case.X0, precision=prec, device="cuda:0")
+    f = Filter(Problem.from_case(case), case.X0, precision=prec, device="cuda:0", pistons=PISTONS)
     for k in range(W):
         f.step(ys[k], pred=False)
     torch.cuda.synchronize()
@@ -139,7 +142,8 @@ def run_plain_loaded(case, B, K, W, ys):
 
     from paper_1310_5954_amd import FP64, Filter, Problem
     pr = Problem.from_case(case)
-    fs = [Filter(pr, np.roll(case.X0, i, axis=1), precision=FP64, device="cuda:0") for i in range(B)]
+    fs = [Filter(pr, np.roll(case.X0, i, axis=1), precision=FP64, device="cuda:0", pistons=PISTONS)
+          for i in range(B)]
     t_start = time.perf_counter()
     queue = collections.deque((i, 0, t_start) for i in range(B))
     lat, t0, timed = [], None, 0
@@ -172,8 +176,10 @@ def run_serving(case, prec, B, K, W, ys, depth=1):
     import torch
 
     from paper_1310_5954_amd import Problem, Server
+    from paper_1310_5954_amd import _lib as L
     pr = Problem.from_case(case)
-    budget = B * pr.workspace_size(prec) + (64 << 20)
+    flags = L.FLAG_PISTONS if PISTONS else 0
+    budget = B * pr.workspace_size(prec, flags) + L.lib().letkf_server_reserved_bytes() + (16 << 20)
     # instance i starts from the ensemble shifted by i columns and reads frame k + 7 i of the slope stream
     total = W + K
     state = dict(next=[0] * B, t_sub={}, lat=[], done=0, timing=False)
@@ -198,7 +204,7 @@ def run_serving(case, prec, B, K, W, ys, depth=1):
             cv.notify_all()
 
     srv = Server(budget, on_done=on_done)
-    insts = [srv.add(pr, np.roll(case.X0, i, axis=1), prec) for i in range(B)]
+    insts = [srv.add(pr, np.roll(case.X0, i, axis=1), prec, pistons=PISTONS) for i in range(B)]
     torch.cuda.synchronize()
     # warm-up frames 0..W-1 run in the same closed loop; the clock starts when every instance has finished them
     with cv:
@@ -342,6 +348,8 @@ def main() -> int:
                     help="84: 84x84 subapertures, m = 64 (headline); 128: 128x128, m = 128")
     ap.add_argument("--partitions", type=int, default=1, choices=[1, 2],
                     help="2: the window partition plus one staggered by half a stride, averaged (Sec. 5)")
+    ap.add_argument("--pistons", action="store_true",
+                    help="remove the differential pistons between domains before the merge (Sec. 3.2)")
     ap.add_argument("--serving-only", action="store_true",
                     help="skip the plain-path runs (for profiling the serving kernels); no roofline line")
     ap.add_argument("--copy-ref", action="store_true",
@@ -363,6 +371,8 @@ def main() -> int:
         print(json.dumps(dict(copy_ref_bytes_read=nbytes, copy_ref_bytes_written=nbytes, dispatches=5)))
         return 0
 
+    global PISTONS
+    PISTONS = args.pistons
     if args.mix > 0:
         print(json.dumps(run_mix(args.mix, args.rate_scale, args.window_us)), flush=True)
         return 0
@@ -431,6 +441,7 @@ def main() -> int:
                              f"{case.n_sub} subapertures (p={2 * case.n_sub}), "
                              f"m={case.m}, {case.dmap.n_domains} overlapping 6x6-actuator domains"
                              + (" (two staggered partitions, averaged)" if args.partitions == 2 else "")
+                             + (", differential pistons removed before the merge" if args.pistons else "")
                              + ", halo 2, Gaspari-Cohn taper; one frame = analysis + AR(2) forecast",
                     path=path, precision=args.precision if serving_out else "fp64"),
         p50_us=round(p50, 1), p99_us=round(p99, 1),

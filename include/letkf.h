@@ -82,6 +82,15 @@ extern "C" {
 
 /* ---- create flags ----------------------------------------------------- */
 #define LETKF_FLAG_DEBUG 0x1u  /* keep per-domain C, lambda, T for letkf_debug_domain */
+/* Remove the differential pistons between domain estimates before the merge
+ * (Sec. 3.2 names the step, not its method).  Each domain's analysed rows of
+ * each instant and member are shifted by one constant, chosen by least
+ * squares so that domains agree on the actuators they share (minimum-norm
+ * solution of the overlap-graph normal equations, then the constant that
+ * keeps each member's merged phase sum).  The create call forms the
+ * n_dom x n_dom operator on the host (O(n_dom^3) once) and keeps it in the
+ * workspace (8 n_dom^2 bytes). */
+#define LETKF_FLAG_PISTONS 0x2u
 
 typedef struct letkf_handle letkf_handle;
 typedef struct letkf_server letkf_server;

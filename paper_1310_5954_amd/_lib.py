@@ -14,6 +14,7 @@ LIB_PATH = os.path.join(HERE, "lib", "libletkf.so")
 OK, EINVAL, ENOMEM, EAGAIN, EDEVICE, ENUMERIC, ESTATE = 0, -1, -2, -3, -4, -5, -6
 FP64, FP32, BF16 = 0, 1, 2
 FLAG_DEBUG = 0x1
+FLAG_PISTONS = 0x2
 
 
 class Dims(C.Structure):

@@ -75,11 +75,12 @@ def _stream(device):
 class Filter:
     """One resident ensemble on the GPU (plain per-frame path)."""
 
-    def __init__(self, problem: Problem, X0, precision: int = L.FP64, debug: bool = False, device="cuda:0"):
+    def __init__(self, problem: Problem, X0, precision: int = L.FP64, debug: bool = False, device="cuda:0",
+                 pistons: bool = False):
         self.problem = problem
         self.precision = int(precision)
         self.device = torch.device(device)
-        self.flags = L.FLAG_DEBUG if debug else 0
+        self.flags = (L.FLAG_DEBUG if debug else 0) | (L.FLAG_PISTONS if pistons else 0)
         X0 = _f64(X0)
         if X0.shape != (problem.n, problem.m):
             raise ValueError(f"X0 must be ({problem.n}, {problem.m}), got {X0.shape}")
@@ -233,12 +234,13 @@ class Server:
         if self.on_done is not None:
             self.on_done(int(frame_id), int(status), t)
 
-    def add(self, problem: Problem, X0, precision: int = L.FP64) -> Instance:
+    def add(self, problem: Problem, X0, precision: int = L.FP64, pistons: bool = False) -> Instance:
         X0 = _f64(X0)
         h = C.c_void_p()
+        flags = L.FLAG_PISTONS if pistons else 0
         with torch.cuda.device(self.device):
             L.check(L.lib().letkf_server_add(self.handle, C.byref(problem.dims), C.byref(problem.model),
-                                             C.byref(problem.map), int(precision), 0, X0.ctypes.data_as(_pd),
+                                             C.byref(problem.map), int(precision), flags, X0.ctypes.data_as(_pd),
                                              C.byref(h)), "letkf_server_add")
         return Instance(self, h, problem, precision)
 

@@ -44,6 +44,13 @@ struct InstDesc {
   const int32_t* mptr;       // [n_act+1] merge CSR: covering (domain, position) entries per actuator
   const int32_t* mrow;       // [2*entries]: Z row of the phi_k copy and of the phi_{k-1} copy
   const double* mw;          // [entries]: merge weight
+  const int32_t* mdom;       // [entries]: domain of each merge entry
+  const double* pist_op;     // [n_dom][n_dom] piston operator (NULL unless LETKF_FLAG_PISTONS)
+  const int32_t* pist_ptr;   // [n_dom+1] CSR of each domain's mismatch terms
+  const int32_t* pist_row;   // [2*terms]: Z row of the term at phi_k and at phi_{k-1}
+  const double* pist_coef;   // [terms]: its coefficient (1, or 1 - k_j for the domain's own row)
+  double* pist_r;            // [n_dom][2][m] overlap mismatch of each domain, instant, member
+  double* pist_c;            // [n_dom][2][m] pistons added before the merge
   double* dbg;               // [n_dom][2*m*m + m] C, lambda, T (NULL unless debug)
   int32_t* dbg_sweeps;       // [n_dom]
   InstState* st;

@@ -26,7 +26,8 @@ int hip_fail(hipError_t e, const char* what);
 // Byte offsets of every region of one instance workspace.
 struct Layout {
   size_t desc, state, hdr, ens, Yp, d, Z, y, amean, pmean;
-  size_t a1, a2, rowptr, col, val, dom, order, est, obs_row, obs_r, mptr, mrow, mw;
+  size_t a1, a2, rowptr, col, val, dom, order, est, obs_row, obs_r, mptr, mrow, mw, mdom, pist_op;
+  size_t pist_r, pist_c, pist_ptr, pist_row, pist_coef;
   size_t dbg, dbg_sweeps;
   size_t static_begin, static_end;  // [a1, end of tables) uploaded at create
   size_t total;
@@ -45,6 +46,13 @@ struct Problem {  // validated, host-side copy of the create arguments
   int sum_e() const { return est_ptr.back(); }
   int sum_s() const { return obs_ptr.back(); }
   int zrows() const { return 2 * sum_e(); }
+  size_t piston_terms() const {  // sum over actuators of (covering domains)^2
+    std::vector<int> k(n_act, 0);
+    for (int a : est_act) ++k[a];
+    size_t t = 0;
+    for (int v : k) t += (size_t)v * v;
+    return t;
+  }
   size_t esize() const { return prec == LETKF_FP64 ? 8 : 4; }
 };
 

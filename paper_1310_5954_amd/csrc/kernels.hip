@@ -158,8 +158,15 @@ __global__ __launch_bounds__(256) void k_rows(const InstDesc* __restrict__ tab,
       const T* Z = (const T*)I.Z;
       for (int q = I.mptr[a]; q < I.mptr[a + 1]; ++q) {
         const double w = I.mw[q];
-        vk += w * ld(Z + (size_t)I.mrow[2 * q] * m + j);
-        vkm1 += w * ld(Z + (size_t)I.mrow[2 * q + 1] * m + j);
+        double z0 = ld(Z + (size_t)I.mrow[2 * q] * m + j);
+        double z1 = ld(Z + (size_t)I.mrow[2 * q + 1] * m + j);
+        if (I.pist_c) {  // differential pistons of the covering domain (both instants)
+          const double* c = I.pist_c + (size_t)I.mdom[q] * 2 * m;
+          z0 += c[j];
+          z1 += c[m + j];
+        }
+        vk += w * z0;
+        vkm1 += w * z1;
       }
       // stored value (rounded to the storage type) is what the forecast uses
       vk = (double)(T)vk;
@@ -184,6 +191,69 @@ __global__ __launch_bounds__(256) void k_rows(const InstDesc* __restrict__ tab,
     const double s = row_sum<MP>(nx, red);
     if (active && j == 0) hdr->pmean[hdr->out_off[ent] + a] = s / (double)m;
   }
+}
+
+// ---- Differential pistons (Sec. 3.2), between the analysis and the merge ----
+// One workgroup per (instance, domain) work item, thread (t, i) for instant t
+// and member i.  k_piston_rhs: the overlap mismatch
+//   r_l[t, i] = sum over the domain's actuators j of
+//               (sum of the covering domains' rows at j) - k_j (own row at j),
+// k_piston_solve: c_l = sum_l' G[l, l'] r_l' with the host-formed operator G.
+// Instances created without LETKF_FLAG_PISTONS are skipped.
+template <typename T>
+__global__ __launch_bounds__(256) void k_piston_rhs(const InstDesc* __restrict__ tab, const BatchHdr* __restrict__ hdr,
+                                                    int cls) {
+  const ClassBatch& cb = hdr->cls[cls];
+  const int item = blockIdx.x;
+  if (item >= cb.dom_off[cb.n]) return;
+  const int eb = find_entry(cb.dom_off, cb.n, item);
+  const InstDesc& I = tab[cb.inst[eb]];
+  const int m = I.m, tid = threadIdx.x;
+  if (!I.pist_op || tid >= 2 * m) return;
+  const int l = item - cb.dom_off[eb], t = tid / m, i = tid % m;
+  const T* Z = (const T*)I.Z;
+  // terms precomputed at create (row, coefficient): independent loads
+  double acc[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) acc[u] = 0.0;
+  const int q0 = I.pist_ptr[l], q1 = I.pist_ptr[l + 1];
+  int q = q0;
+  for (; q + 8 <= q1; q += 8)
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      acc[u] = fma(I.pist_coef[q + u], ld(Z + (size_t)I.pist_row[2 * (q + u) + t] * m + i), acc[u]);
+  for (; q < q1; ++q) acc[0] = fma(I.pist_coef[q], ld(Z + (size_t)I.pist_row[2 * q + t] * m + i), acc[0]);
+  double rsum = 0.0;
+#pragma unroll
+  for (int u = 0; u < 8; ++u) rsum += acc[u];
+  I.pist_r[((size_t)l * 2 + t) * m + i] = rsum;
+}
+
+__global__ __launch_bounds__(256) void k_piston_solve(const InstDesc* __restrict__ tab,
+                                                      const BatchHdr* __restrict__ hdr, int cls) {
+  const ClassBatch& cb = hdr->cls[cls];
+  const int item = blockIdx.x;
+  if (item >= cb.dom_off[cb.n]) return;
+  const int eb = find_entry(cb.dom_off, cb.n, item);
+  const InstDesc& I = tab[cb.inst[eb]];
+  const int m = I.m, tid = threadIdx.x;
+  if (!I.pist_op || tid >= 2 * m) return;
+  const int l = item - cb.dom_off[eb], t = tid / m, i = tid % m, n = I.n_dom;
+  const double* g = I.pist_op + (size_t)l * n;
+  // 16 independent partial sums keep that many L2 loads in flight
+  double acc[16];
+#pragma unroll
+  for (int u = 0; u < 16; ++u) acc[u] = 0.0;
+  const double* r = I.pist_r + (size_t)t * m + i;
+  int k = 0;
+  for (; k + 16 <= n; k += 16)
+#pragma unroll
+    for (int u = 0; u < 16; ++u) acc[u] = fma(g[k + u], r[(size_t)(k + u) * 2 * m], acc[u]);
+  for (; k < n; ++k) acc[0] = fma(g[k], r[(size_t)k * 2 * m], acc[0]);
+  double c = 0.0;
+#pragma unroll
+  for (int u = 0; u < 16; ++u) c += acc[u];
+  I.pist_c[((size_t)l * 2 + t) * m + i] = c;
 }
 
 // After a forecast launch: the new instant becomes phi_k (ring swap) and the
@@ -1195,6 +1265,13 @@ static void launch_analysis_t(int items, int max_grid, const InstDesc* tab, Batc
 void launch_slopes(int cls, int rows, const InstDesc* tab, BatchHdr* hdr, hipStream_t s) {
   LETKF_DISPATCH(launch_slopes_t, cls, rows, tab, hdr, cls, s);
 }
+void launch_pistons(int cls, int items, const InstDesc* tab, BatchHdr* hdr, hipStream_t s) {
+  if (items <= 0) return;
+  if (cls / 4 == 0) hipLaunchKernelGGL(k_piston_rhs<double>, dim3(items), dim3(256), 0, s, tab, hdr, cls);
+  else hipLaunchKernelGGL(k_piston_rhs<float>, dim3(items), dim3(256), 0, s, tab, hdr, cls);
+  hipLaunchKernelGGL(k_piston_solve, dim3(items), dim3(256), 0, s, tab, hdr, cls);
+}
+
 void launch_rows(int cls, int mode, int rows, const InstDesc* tab, BatchHdr* hdr, hipStream_t s) {
   LETKF_DISPATCH(launch_rows_t, cls, mode, rows, tab, hdr, cls, s);
 }

@@ -39,7 +39,7 @@ int validate(const letkf_dims* dims, const letkf_model* model, const letkf_domai
   if (dims->m < 2 || dims->m > 128) return fail(LETKF_EINVAL, "m must be in [2, 128]");
   if (precision != LETKF_FP64 && precision != LETKF_FP32 && precision != LETKF_BF16)
     return fail(LETKF_EINVAL, "unknown precision");
-  if (flags & ~LETKF_FLAG_DEBUG) return fail(LETKF_EINVAL, "unknown flags");
+  if (flags & ~(LETKF_FLAG_DEBUG | LETKF_FLAG_PISTONS)) return fail(LETKF_EINVAL, "unknown flags");
   P.n_act = dims->n_act;
   P.n_sub = dims->n_sub;
   P.m = dims->m;
@@ -147,7 +147,22 @@ Layout make_layout(const Problem& P) {
   L.mptr = take((n_act + 1) * 4);
   L.mrow = take((size_t)2 * P.sum_e() * 4);
   L.mw = take((size_t)P.sum_e() * 8);
+  L.mdom = take((size_t)P.sum_e() * 4);
+  L.pist_op = L.pist_ptr = L.pist_row = L.pist_coef = 0;
+  if (P.flags & LETKF_FLAG_PISTONS) {
+    L.pist_op = take((size_t)P.n_dom * P.n_dom * 8);
+    const size_t terms = P.piston_terms();
+    L.pist_ptr = take((size_t)(P.n_dom + 1) * 4);
+    L.pist_row = take(2 * terms * 4);
+    L.pist_coef = take(terms * 8);
+  }
   L.static_end = off;
+  if (P.flags & LETKF_FLAG_PISTONS) {
+    L.pist_r = take((size_t)P.n_dom * 2 * m * 8);
+    L.pist_c = take((size_t)P.n_dom * 2 * m * 8);
+  } else {
+    L.pist_r = L.pist_c = 0;
+  }
   if (P.flags & LETKF_FLAG_DEBUG) {
     L.dbg = take((size_t)P.n_dom * (2 * m * m + m + 8) * 8);
     L.dbg_sweeps = take((size_t)P.n_dom * 4);
@@ -161,6 +176,95 @@ Layout make_layout(const Problem& P) {
 template <typename T>
 static void put(std::vector<char>& blob, size_t base, size_t off, const T* src, size_t n) {
   if (n) std::memcpy(blob.data() + (off - base), src, n * sizeof(T));
+}
+
+// Piston operator G (n_dom x n_dom): c = G r turns the overlap mismatches
+// r_l = sum over actuators j of l of (sum of the covering domains' rows at j
+// minus k_j times l's own row) into the least-squares pistons.  The normal
+// equations of  min sum_j sum_{l != l' covering j} (Z_l + c_l - Z_l' - c_l')^2
+// have the overlap-graph Laplacian Lap (Lap_ll = pairs through l, Lap_ll' = -
+// shared actuators); G = (I - 1 w^T / sum w) Lap^+ with w_l the sum of domain
+// l's merge weights.  Lap^+ per connected component of size n_c > 1:
+// (Lap_c + 11^T / n_c)^-1 - 11^T / n_c (Cholesky of an SPD matrix); zero on
+// isolated domains.  Dense O(n_dom^3) on the host, once per instance.
+static std::vector<double> piston_operator(const Problem& P, const std::vector<int32_t>& mptr,
+                                           const std::vector<int32_t>& mdom) {
+  const int n = P.n_dom;
+  std::vector<double> lap((size_t)n * n, 0.0);
+  for (int a = 0; a < P.n_act; ++a)
+    for (int x = mptr[a]; x < mptr[a + 1]; ++x)
+      for (int y = mptr[a]; y < mptr[a + 1]; ++y) {
+        if (x == y) continue;
+        const int dx = mdom[x], dy = mdom[y];
+        lap[(size_t)dx * n + dx] += 1.0;
+        lap[(size_t)dx * n + dy] -= 1.0;
+      }
+  // connected components of the overlap graph
+  std::vector<int> comp(n, -1);
+  int ncomp = 0;
+  for (int s0 = 0; s0 < n; ++s0) {
+    if (comp[s0] >= 0) continue;
+    std::vector<int> stack{s0};
+    comp[s0] = ncomp;
+    while (!stack.empty()) {
+      const int u = stack.back();
+      stack.pop_back();
+      for (int v = 0; v < n; ++v)
+        if (comp[v] < 0 && lap[(size_t)u * n + v] != 0.0) { comp[v] = ncomp; stack.push_back(v); }
+    }
+    ++ncomp;
+  }
+  std::vector<double> pinv((size_t)n * n, 0.0);
+  for (int c = 0; c < ncomp; ++c) {
+    std::vector<int> idx;
+    for (int v = 0; v < n; ++v)
+      if (comp[v] == c) idx.push_back(v);
+    const int k = (int)idx.size();
+    if (k < 2) continue;
+    // M = Lap_c + 11^T / k, Cholesky M = R R^T (lower R, in place)
+    std::vector<double> M((size_t)k * k);
+    for (int i = 0; i < k; ++i)
+      for (int j = 0; j < k; ++j) M[(size_t)i * k + j] = lap[(size_t)idx[i] * n + idx[j]] + 1.0 / k;
+    for (int j = 0; j < k; ++j) {
+      double d = M[(size_t)j * k + j];
+      for (int q = 0; q < j; ++q) d -= M[(size_t)j * k + q] * M[(size_t)j * k + q];
+      d = std::sqrt(d);
+      M[(size_t)j * k + j] = d;
+      for (int i = j + 1; i < k; ++i) {
+        double v = M[(size_t)i * k + j];
+        for (int q = 0; q < j; ++q) v -= M[(size_t)i * k + q] * M[(size_t)j * k + q];
+        M[(size_t)i * k + j] = v / d;
+      }
+    }
+    // columns of M^-1 by forward and back substitution, minus 11^T / k
+    std::vector<double> x(k);
+    for (int col = 0; col < k; ++col) {
+      for (int i = 0; i < k; ++i) {
+        double v = (i == col) ? 1.0 : 0.0;
+        for (int q = 0; q < i; ++q) v -= M[(size_t)i * k + q] * x[q];
+        x[i] = v / M[(size_t)i * k + i];
+      }
+      for (int i = k - 1; i >= 0; --i) {
+        double v = x[i];
+        for (int q = i + 1; q < k; ++q) v -= M[(size_t)q * k + i] * x[q];
+        x[i] = v / M[(size_t)i * k + i];
+      }
+      for (int i = 0; i < k; ++i) pinv[(size_t)idx[i] * n + idx[col]] = x[i] - 1.0 / k;
+    }
+  }
+  // gauge: G = (I - 1 w^T / sum w) Lap^+
+  std::vector<double> w(n, 0.0);
+  for (int l = 0; l < n; ++l)
+    for (int q = P.est_ptr[l]; q < P.est_ptr[l + 1]; ++q) w[l] += P.est_w[q];
+  double wsum = 0.0;
+  for (double v : w) wsum += v;
+  std::vector<double> g(n, 0.0);  // w^T Lap^+ / sum w
+  for (int l = 0; l < n; ++l)
+    for (int j = 0; j < n; ++j) g[j] += w[l] * pinv[(size_t)l * n + j];
+  for (int j = 0; j < n; ++j) g[j] /= wsum;
+  for (int l = 0; l < n; ++l)
+    for (int j = 0; j < n; ++j) pinv[(size_t)l * n + j] -= g[j];
+  return pinv;
 }
 
 int upload_instance(const Problem& P, const Layout& L, char* ws, const double* X0, hipStream_t stream,
@@ -209,7 +313,7 @@ int upload_instance(const Problem& P, const Layout& L, char* ws, const double* X
   std::vector<int32_t> mptr(n_act + 1, 0);
   for (int q = 0; q < P.sum_e(); ++q) mptr[P.est_act[q] + 1]++;
   for (int a = 0; a < n_act; ++a) mptr[a + 1] += mptr[a];
-  std::vector<int32_t> fill(mptr.begin(), mptr.end() - 1), mrow(2 * P.sum_e());
+  std::vector<int32_t> fill(mptr.begin(), mptr.end() - 1), mrow(2 * P.sum_e()), mdom(P.sum_e());
   std::vector<double> mw(P.sum_e());
   for (int l = 0; l < P.n_dom; ++l) {
     const int e0 = P.est_ptr[l], e = P.est_ptr[l + 1] - e0;
@@ -219,11 +323,37 @@ int upload_instance(const Problem& P, const Layout& L, char* ws, const double* X
       mrow[2 * k] = 2 * e0 + q;
       mrow[2 * k + 1] = 2 * e0 + e + q;
       mw[k] = P.est_w[e0 + q];
+      mdom[k] = l;
     }
   }
   put(blob, B, L.mptr, mptr.data(), mptr.size());
   put(blob, B, L.mrow, mrow.data(), mrow.size());
   put(blob, B, L.mw, mw.data(), mw.size());
+  put(blob, B, L.mdom, mdom.data(), mdom.size());
+  if (P.flags & LETKF_FLAG_PISTONS) {
+    const std::vector<double> G = piston_operator(P, mptr, mdom);
+    put(blob, B, L.pist_op, G.data(), G.size());
+    // mismatch terms of each domain: for every actuator j of the domain, the
+    // rows of all domains covering j with coefficient 1, the domain's own
+    // row with 1 - k_j (k_j = domains covering j)
+    std::vector<int32_t> pptr(P.n_dom + 1, 0), prow;
+    std::vector<double> pcoef;
+    for (int l = 0; l < P.n_dom; ++l) {
+      for (int q = P.est_ptr[l]; q < P.est_ptr[l + 1]; ++q) {
+        const int a = P.est_act[q];
+        const int k = mptr[a + 1] - mptr[a];
+        for (int x = mptr[a]; x < mptr[a + 1]; ++x) {
+          prow.push_back(mrow[2 * x]);
+          prow.push_back(mrow[2 * x + 1]);
+          pcoef.push_back(mdom[x] == l ? 1.0 - k : 1.0);
+        }
+      }
+      pptr[l + 1] = (int32_t)pcoef.size();
+    }
+    put(blob, B, L.pist_ptr, pptr.data(), pptr.size());
+    put(blob, B, L.pist_row, prow.data(), prow.size());
+    put(blob, B, L.pist_coef, pcoef.data(), pcoef.size());
+  }
 
   // ---- descriptor
   std::memset(&D, 0, sizeof(D));
@@ -241,6 +371,15 @@ int upload_instance(const Problem& P, const Layout& L, char* ws, const double* X
   D.obs_row = (const int32_t*)(ws + L.obs_row); D.obs_r = (const double*)(ws + L.obs_r);
   D.mptr = (const int32_t*)(ws + L.mptr); D.mrow = (const int32_t*)(ws + L.mrow);
   D.mw = (const double*)(ws + L.mw);
+  D.mdom = (const int32_t*)(ws + L.mdom);
+  if (P.flags & LETKF_FLAG_PISTONS) {
+    D.pist_op = (const double*)(ws + L.pist_op);
+    D.pist_ptr = (const int32_t*)(ws + L.pist_ptr);
+    D.pist_row = (const int32_t*)(ws + L.pist_row);
+    D.pist_coef = (const double*)(ws + L.pist_coef);
+    D.pist_r = (double*)(ws + L.pist_r);
+    D.pist_c = (double*)(ws + L.pist_c);
+  }
   D.dbg = L.dbg ? (double*)(ws + L.dbg) : nullptr;
   D.dbg_sweeps = L.dbg_sweeps ? (int32_t*)(ws + L.dbg_sweeps) : nullptr;
   D.st = (InstState*)(ws + L.state);
@@ -429,6 +568,7 @@ int letkf_analyse(letkf_handle* h, const double* y, int y_on_device, double* mea
   launch_slopes(h->cls, h->P.p(), dev_desc(h), dev_hdr(h), s);
   if ((rc = mark(h, 1, s))) return rc;
   launch_analysis(h->cls, h->P.n_dom, dev_desc(h), dev_hdr(h), s);
+  if (h->P.flags & LETKF_FLAG_PISTONS) launch_pistons(h->cls, h->P.n_dom, dev_desc(h), dev_hdr(h), s);
   if ((rc = mark(h, 2, s))) return rc;
   launch_rows(h->cls, 0, h->P.n_act, dev_desc(h), dev_hdr(h), s);
   if ((rc = mark(h, 3, s))) return rc;
@@ -458,6 +598,7 @@ int letkf_step(letkf_handle* h, const double* y, int y_on_device, double* pred_o
   launch_slopes(h->cls, h->P.p(), dev_desc(h), dev_hdr(h), s);
   if ((rc = mark(h, 1, s))) return rc;
   launch_analysis(h->cls, h->P.n_dom, dev_desc(h), dev_hdr(h), s);
+  if (h->P.flags & LETKF_FLAG_PISTONS) launch_pistons(h->cls, h->P.n_dom, dev_desc(h), dev_hdr(h), s);
   if ((rc = mark(h, 2, s))) return rc;
   launch_rows(h->cls, 2, h->P.n_act, dev_desc(h), dev_hdr(h), s);
   if ((rc = mark(h, 3, s))) return rc;

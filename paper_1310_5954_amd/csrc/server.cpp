@@ -64,6 +64,7 @@ struct Frame {
 struct Batch {
   int slot;
   int grid_cap = 0;            // analysis workgroups (0 = one per domain item)
+  bool pistons = false;        // some instance of the batch removes differential pistons
   std::vector<std::pair<letkf_handle*, Frame>> frames;
   std::vector<int32_t> out_off;
 };
@@ -155,6 +156,9 @@ int letkf_server::launch_batch(Batch& b) {
     if (H.cls[c].n) launch_slopes(c, rows_slopes[c], table(), dhdr(s), st);
   for (int c = 0; c < kNumClasses; ++c)
     if (H.cls[c].n) launch_analysis(c, items[c], table(), dhdr(s), st, b.grid_cap);
+  if (b.pistons)
+    for (int c = 0; c < kNumClasses; ++c)
+      if (H.cls[c].n) launch_pistons(c, items[c], table(), dhdr(s), st);
   for (int c = 0; c < kNumClasses; ++c)
     if (H.cls[c].n) launch_rows(c, 2, rows_act[c], table(), dhdr(s), st);
   LETKF_HIP(hipGetLastError());
@@ -225,6 +229,7 @@ void letkf_server::scheduler_loop() {
       if (ytot + h->P.p() > kStageDoubles || otot + h->P.n_act > kStageDoubles) break;
       ytot += h->P.p();
       otot += h->P.n_act;
+      b.pistons |= (h->P.flags & LETKF_FLAG_PISTONS) != 0;
       b.frames.emplace_back(h, std::move(q.front()));
       q.pop_front();
       in_flight[h]++;

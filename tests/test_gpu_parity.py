@@ -36,10 +36,10 @@ def _tol(precision, key):
     return TOLS[precision][key]
 
 
-def _check_step(case, X, k, precision, debug=False, dmap=None, check_domains=None):
+def _check_step(case, X, k, precision, debug=False, dmap=None, check_domains=None, pistons=False):
     """Load X at frame k, analyse y_k, compare; forecast, compare."""
     dm = dmap if dmap is not None else case.dmap
-    f = Filter(Problem.from_case(case, dmap=dm), X, precision=precision, debug=debug)
+    f = Filter(Problem.from_case(case, dmap=dm), X, precision=precision, debug=debug, pistons=pistons)
     f.set_state(X, frame=k)
     Xg, fr = f.get_state()
     assert fr == k
@@ -47,7 +47,7 @@ def _check_step(case, X, k, precision, debug=False, dmap=None, check_domains=Non
     D = sparse_D(case)
     mean = f.analyse(y, mean=True)
     Xa_g, _ = f.get_state()
-    Xa_o, doms = oracle.analysis(Xg, y, D, dm, case.r_inv, case.inflation, keep_domains=True)
+    Xa_o, doms = oracle.analysis(Xg, y, D, dm, case.r_inv, case.inflation, keep_domains=True, pistons=pistons)
     f.forecast()
     Xf_g, fr2 = f.get_state()
     assert fr2 == k + 1
@@ -174,6 +174,40 @@ def test_two_partitions_cfg2_bf16():
     case = build_case(2, partitions=2)
     X, k = oracle_spin_up(case, 2)
     _check_step(case, X, k, BF16)
+
+
+def test_pistons_ragged_overlapping_fp64():
+    """Differential-piston removal (Sec. 3.2) on a clipped, overlapping,
+    tapered 16x16 map: every result against the oracle's least-squares
+    pistons."""
+    cfg = dict(build_case(2).cfg)
+    cfg.update(lenslets=16)
+    case = build_case(cfg)
+    X, k = oracle_spin_up(case, 2)
+    _check_step(case, X, k, FP64, pistons=True)
+
+
+def test_pistons_cfg3_full_size_fp64_and_bf16():
+    """84x84, 375 domains: the 375 x 375 operator formed at create, mismatch
+    and pistons on the GPU, merged with the domain rows."""
+    case = build_case(3)
+    X, k = oracle_spin_up(case, 1)
+    _check_step(case, X, k, FP64, pistons=True)
+    _check_step(case, X, k, BF16, pistons=True)
+
+
+def test_pistons_disjoint_map_is_plain_analysis():
+    """Non-overlapping windows share no actuator: no piston moves anything."""
+    case = build_case(1)
+    X, k = oracle_spin_up(case, 2)
+    y = case.slopes(k)
+    outs = []
+    for pist in (False, True):
+        f = Filter(Problem.from_case(case), X, precision=FP64, pistons=pist)
+        f.set_state(X, frame=k)
+        outs.append(f.analyse(y, mean=True))
+        f.close()
+    np.testing.assert_allclose(outs[1], outs[0], rtol=0, atol=1e-13)
 
 
 def test_cfg3_full_size_fp32():

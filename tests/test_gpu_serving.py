@@ -65,6 +65,24 @@ def test_alone_vs_in_the_mix_bit_identical():
         assert alone_states[0][1] == mixed_states[i][1] == FRAMES
 
 
+def test_server_pistons_equal_plain_pistons():
+    """A server instance with differential-piston removal gives the same
+    predictions as the plain path with it."""
+    cfg = dict(build_case(2).cfg)
+    cfg.update(lenslets=16)
+    case = build_case(cfg)
+    srv = Server(1 << 30)
+    inst = srv.add(Problem.from_case(case), case.X0, FP64, pistons=True)
+    preds = [np.empty(case.n_act) for _ in range(4)]
+    for k in range(4):
+        assert srv.submit(inst, case.slopes(k), k, preds[k]) == 0
+    srv.drain()
+    srv.close()
+    f = Filter(Problem.from_case(case), case.X0, precision=FP64, pistons=True)
+    for k in range(4):
+        assert np.array_equal(f.step(case.slopes(k), pred=True), preds[k]), k
+
+
 def test_server_equals_plain_path():
     case = build_case(1)
     preds, states, _ = _run_server([(case, FP64)], drain_each=True)
