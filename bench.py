@@ -133,6 +133,33 @@ def run_plain(case, prec, K, W, NL, ys):
                 kernel_ms=[v / K for v in ms], sweeps=sw1 - sw0, solves=so1 - so0)
 
 
+def run_plain_graph(case, K, W, NL, ys):
+    """The plain FP64 path with the frame's launch sequence replayed from a
+    captured hipGraph (LETKF_FLAG_GRAPH): throughput and latency only (kernel
+    timing would switch the replay off)."""
+    import torch
+
+    from paper_1310_5954_amd import FP64, Filter, Problem
+    f = Filter(Problem.from_case(case), case.X0, precision=FP64, device="cuda:0", pistons=PISTONS, graph=True)
+    for k in range(W):
+        f.step(ys[k], pred=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(W, W + K):
+        f.step(ys[k], pred=False)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    lat = []
+    for k in range(W + K, W + K + NL):
+        ts = time.perf_counter()
+        f.step(ys[k], pred=True)
+        lat.append(time.perf_counter() - ts)
+    assert f.unconverged() == 0
+    f.close()
+    lat_us = np.array(lat) * 1e6
+    return dict(fps=K / (t1 - t0), p50_us=float(np.percentile(lat_us, 50)), p99_us=float(np.percentile(lat_us, 99)))
+
+
 def run_plain_loaded(case, B, K, W, ys):
     """The plain per-frame FP64 path under the serving load: B resident
     instances in a closed loop (an instance releases its next frame when the
@@ -400,6 +427,9 @@ def main() -> int:
     plain = run_plain(case, FP64, K, W, NL, ys)
     print(f"[bench] plain fp64: {plain['fps']:.1f} frames/s p50 {plain['p50_us']:.0f} us "
           f"p99 {plain['p99_us']:.0f} us", file=sys.stderr, flush=True)
+    graph = run_plain_graph(case, K, W, NL, ys)
+    print(f"[bench] plain fp64, graph replay: {graph['fps']:.1f} frames/s p50 {graph['p50_us']:.0f} us "
+          f"p99 {graph['p99_us']:.0f} us", file=sys.stderr, flush=True)
     ana_ms = plain["kernel_ms"][1]
     flops = analysis_flops(case.m, case.dmap, plain["sweeps"], plain["solves"], K) / K
     achieved = flops / (ana_ms * 1e-3) / 1e12
@@ -411,7 +441,9 @@ def main() -> int:
                      p99_us=round(plain["p99_us"], 1),
                      kernel_ms=dict(slopes=round(plain["kernel_ms"][0], 4), analysis=round(ana_ms, 4),
                                     merge_forecast=round(plain["kernel_ms"][2], 4)),
-                     jacobi_sweeps_mean=round(plain["sweeps"] / max(plain["solves"], 1), 3))
+                     jacobi_sweeps_mean=round(plain["sweeps"] / max(plain["solves"], 1), 3),
+                     graph_replay=dict(frames_per_s=round(graph["fps"], 2), p50_us=round(graph["p50_us"], 1),
+                                       p99_us=round(graph["p99_us"], 1)))
     dname = {FP64: "f64", FP32: "f32", BF16: "bf16+f64"}
     if args.plain_only:
         value, p50, p99, dtype, path = plain["fps"], plain["p50_us"], plain["p99_us"], "f64", "plain"

@@ -91,6 +91,14 @@ extern "C" {
  * n_dom x n_dom operator on the host (O(n_dom^3) once) and keeps it in the
  * workspace (8 n_dom^2 bytes). */
 #define LETKF_FLAG_PISTONS 0x2u
+/* letkf_step replays a hipGraph of the frame's launch sequence (slopes,
+ * analysis, pistons, merge + forecast, state advance), captured at the first
+ * step on a private stream of the handle and launched on the caller's stream
+ * afterwards; the slope upload and the read-back of the means stay ordinary
+ * copies around it.  Every kernel reads the frame's state from the device
+ * (ring slot, frame counter), so the graph is replayed unchanged.  While
+ * kernel timing is enabled, letkf_step launches the kernels one by one. */
+#define LETKF_FLAG_GRAPH 0x4u
 
 typedef struct letkf_handle letkf_handle;
 typedef struct letkf_server letkf_server;

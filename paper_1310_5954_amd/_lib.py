@@ -15,6 +15,7 @@ OK, EINVAL, ENOMEM, EAGAIN, EDEVICE, ENUMERIC, ESTATE = 0, -1, -2, -3, -4, -5, -
 FP64, FP32, BF16 = 0, 1, 2
 FLAG_DEBUG = 0x1
 FLAG_PISTONS = 0x2
+FLAG_GRAPH = 0x4
 
 
 class Dims(C.Structure):

@@ -76,11 +76,12 @@ class Filter:
     """One resident ensemble on the GPU (plain per-frame path)."""
 
     def __init__(self, problem: Problem, X0, precision: int = L.FP64, debug: bool = False, device="cuda:0",
-                 pistons: bool = False):
+                 pistons: bool = False, graph: bool = False):
         self.problem = problem
         self.precision = int(precision)
         self.device = torch.device(device)
-        self.flags = (L.FLAG_DEBUG if debug else 0) | (L.FLAG_PISTONS if pistons else 0)
+        self.flags = ((L.FLAG_DEBUG if debug else 0) | (L.FLAG_PISTONS if pistons else 0)
+                      | (L.FLAG_GRAPH if graph else 0))
         X0 = _f64(X0)
         if X0.shape != (problem.n, problem.m):
             raise ValueError(f"X0 must be ({problem.n}, {problem.m}), got {X0.shape}")

@@ -89,6 +89,9 @@ struct letkf_handle {
   size_t ev_used = 0;              // quads recorded since the last flush
   double ms_acc[3] = {0, 0, 0};
   uint64_t timed_calls = 0;
+  // captured frame (LETKF_FLAG_GRAPH)
+  hipStream_t graph_stream = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
   // serving
   letkf_server* server = nullptr;
   int slot = -1;               // index in the server's instance table

@@ -39,7 +39,7 @@ int validate(const letkf_dims* dims, const letkf_model* model, const letkf_domai
   if (dims->m < 2 || dims->m > 128) return fail(LETKF_EINVAL, "m must be in [2, 128]");
   if (precision != LETKF_FP64 && precision != LETKF_FP32 && precision != LETKF_BF16)
     return fail(LETKF_EINVAL, "unknown precision");
-  if (flags & ~(LETKF_FLAG_DEBUG | LETKF_FLAG_PISTONS)) return fail(LETKF_EINVAL, "unknown flags");
+  if (flags & ~(LETKF_FLAG_DEBUG | LETKF_FLAG_PISTONS | LETKF_FLAG_GRAPH)) return fail(LETKF_EINVAL, "unknown flags");
   P.n_act = dims->n_act;
   P.n_sub = dims->n_sub;
   P.m = dims->m;
@@ -528,6 +528,8 @@ int letkf_destroy(letkf_handle* h) {
   // teardown: errors here cannot be acted on, the host state goes regardless
   if (h->y_free) { (void)hipEventSynchronize(h->y_free); (void)hipEventDestroy(h->y_free); }
   for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
+  if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
+  if (h->graph_stream) (void)hipStreamDestroy(h->graph_stream);
   if (h->h_y) (void)hipHostFree(h->h_y);
   if (h->h_out) (void)hipHostFree(h->h_out);
   delete h;
@@ -589,11 +591,47 @@ int letkf_forecast(letkf_handle* h, void* stream) {
   return LETKF_OK;
 }
 
+// The kernels of one frame (slopes, analysis, pistons, merge + forecast,
+// state advance), all reading the frame's state from the device.
+static void launch_frame(letkf_handle* h, hipStream_t s) {
+  launch_slopes(h->cls, h->P.p(), dev_desc(h), dev_hdr(h), s);
+  launch_analysis(h->cls, h->P.n_dom, dev_desc(h), dev_hdr(h), s);
+  if (h->P.flags & LETKF_FLAG_PISTONS) launch_pistons(h->cls, h->P.n_dom, dev_desc(h), dev_hdr(h), s);
+  launch_rows(h->cls, 2, h->P.n_act, dev_desc(h), dev_hdr(h), s);
+}
+
+// Captures launch_frame on the handle's private stream into a graph.
+static int capture_frame(letkf_handle* h) {
+  if (!h->graph_stream) LETKF_HIP(hipStreamCreateWithFlags(&h->graph_stream, hipStreamNonBlocking));
+  hipGraph_t g = nullptr;
+  LETKF_HIP(hipStreamBeginCapture(h->graph_stream, hipStreamCaptureModeThreadLocal));
+  launch_frame(h, h->graph_stream);
+  const hipError_t le = hipGetLastError();
+  const hipError_t ee = hipStreamEndCapture(h->graph_stream, &g);
+  if (le != hipSuccess || ee != hipSuccess || !g) {
+    if (g) (void)hipGraphDestroy(g);
+    return fail(LETKF_EDEVICE, "stream capture of the frame failed");
+  }
+  const hipError_t ie = hipGraphInstantiate(&h->graph_exec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (ie != hipSuccess) {
+    h->graph_exec = nullptr;
+    return fail(LETKF_EDEVICE, "hipGraphInstantiate");
+  }
+  return LETKF_OK;
+}
+
 int letkf_step(letkf_handle* h, const double* y, int y_on_device, double* pred_out, void* stream) {
   int rc = check_plain(h);
   if (rc) return rc;
   hipStream_t s = (hipStream_t)stream;
   if ((rc = stage_y(h, y, y_on_device, s))) return rc;
+  if ((h->P.flags & LETKF_FLAG_GRAPH) && !h->timing) {
+    if (!h->graph_exec && (rc = capture_frame(h))) return rc;
+    LETKF_HIP(hipGraphLaunch(h->graph_exec, s));
+    if (pred_out) return read_means(h, h->L.pmean, pred_out, s);
+    return LETKF_OK;
+  }
   if ((rc = mark(h, 0, s))) return rc;
   launch_slopes(h->cls, h->P.p(), dev_desc(h), dev_hdr(h), s);
   if ((rc = mark(h, 1, s))) return rc;

@@ -291,3 +291,28 @@ def test_nonfinite_slopes_rejected():
     assert ei.value.status == -5
     # the filter is still usable afterwards
     f.analyse(case.slopes(0))
+
+
+@pytest.mark.parametrize("pistons", [False, True])
+def test_graph_replay_equals_eager_steps(pistons):
+    """LETKF_FLAG_GRAPH: the captured frame is replayed with eager work
+    (state reads, a state reload) between replays, and every prediction and
+    state equals the one-by-one launches bit for bit."""
+    cfg = dict(build_case(2).cfg)
+    cfg.update(lenslets=16)
+    case = build_case(cfg)
+    pr = Problem.from_case(case)
+    eager = Filter(pr, case.X0, precision=FP64, pistons=pistons)
+    graph = Filter(pr, case.X0, precision=FP64, pistons=pistons, graph=True)
+    for k in range(6):
+        y = case.slopes(k)
+        a, b = eager.step(y, pred=True), graph.step(y, pred=True)
+        assert np.array_equal(a, b), k
+        Xe, fe = eager.get_state()
+        Xg, fg = graph.get_state()
+        assert fe == fg == k + 1 and np.array_equal(Xe, Xg), k
+        if k == 2:                       # reload a state: the replay must follow it
+            eager.set_state(Xe, frame=fe)
+            graph.set_state(Xe, frame=fe)
+    eager.close()
+    graph.close()
