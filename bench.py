@@ -42,15 +42,15 @@ METRIC = "frames/s + p50/p99 frame latency (µs), LETKF 84×84 subaps m=64"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_analysis_fp64_84x84_m64_traffic.txt")
 
 
-def measured_traffic(library: str):
+def measured_traffic(kernels: str):
     """HBM bytes per k_analysis launch from the committed rocprofv3 counter
     summary (FETCH_SIZE x fetch scale + WRITE_SIZE x write scale), or None when
-    the summary was taken on another build of the kernels."""
+    the summary was taken on another build of the device code."""
     try:
         kv = dict(line.split(":", 1) for line in open(TRAFFIC_FILE) if ":" in line and not line.startswith("#"))
     except OSError:
         return None
-    if kv.get("library", "").strip() != library:
+    if kv.get("kernels", "").strip() != kernels:
         return None
     return float(kv["traffic_bytes_per_launch"])
 
@@ -99,6 +99,8 @@ def cpu_baseline(case, seconds: float = 15.0):
 
 
 PISTONS = False  # set from --pistons
+TUNE = True      # autotune the analysis launch of every filter / server class first (--no-tune: defaults)
+GRAPHS = False   # server batches replayed from captured graphs (--server-graphs 1); measured slower here
 
 
 def run_plain(case, prec, K, W, NL, ys):
@@ -107,6 +109,7 @@ def run_plain(case, prec, K, W, NL, ys):
 
     from paper_1310_5954_amd import Filter, Problem
     f = Filter(Problem.from_case(case), case.X0, precision=prec, device="cuda:0", pistons=PISTONS)
+    tuning = f.autotune() if TUNE else None
     for k in range(W):
         f.step(ys[k], pred=False)
     torch.cuda.synchronize()
@@ -130,7 +133,7 @@ def run_plain(case, prec, K, W, NL, ys):
     f.close()
     lat_us = np.array(lat) * 1e6
     return dict(fps=K / (t1 - t0), p50_us=float(np.percentile(lat_us, 50)), p99_us=float(np.percentile(lat_us, 99)),
-                kernel_ms=[v / K for v in ms], sweeps=sw1 - sw0, solves=so1 - so0)
+                kernel_ms=[v / K for v in ms], sweeps=sw1 - sw0, solves=so1 - so0, tuning=tuning)
 
 
 def run_plain_graph(case, K, W, NL, ys):
@@ -141,6 +144,8 @@ def run_plain_graph(case, K, W, NL, ys):
 
     from paper_1310_5954_amd import FP64, Filter, Problem
     f = Filter(Problem.from_case(case), case.X0, precision=FP64, device="cuda:0", pistons=PISTONS, graph=True)
+    if TUNE:
+        f.autotune()
     for k in range(W):
         f.step(ys[k], pred=False)
     torch.cuda.synchronize()
@@ -171,6 +176,9 @@ def run_plain_loaded(case, B, K, W, ys):
     pr = Problem.from_case(case)
     fs = [Filter(pr, np.roll(case.X0, i, axis=1), precision=FP64, device="cuda:0", pistons=PISTONS)
           for i in range(B)]
+    if TUNE:
+        for f in fs:
+            f.autotune()
     t_start = time.perf_counter()
     queue = collections.deque((i, 0, t_start) for i in range(B))
     lat, t0, timed = [], None, 0
@@ -230,8 +238,9 @@ def run_serving(case, prec, B, K, W, ys, depth=1):
             state["done"] += 1
             cv.notify_all()
 
-    srv = Server(budget, on_done=on_done)
+    srv = Server(budget, on_done=on_done, graphs=GRAPHS)
     insts = [srv.add(pr, np.roll(case.X0, i, axis=1), prec, pistons=PISTONS) for i in range(B)]
+    tuning = list(srv.autotune().values())[0] if TUNE else None
     torch.cuda.synchronize()
     # warm-up frames 0..W-1 run in the same closed loop; the clock starts when every instance has finished them
     with cv:
@@ -253,7 +262,7 @@ def run_serving(case, prec, B, K, W, ys, depth=1):
     lat_us = np.array(state["lat"]) * 1e6
     return dict(fps=B * K / (t1 - t0), p50_us=float(np.percentile(lat_us, 50)),
                 p99_us=float(np.percentile(lat_us, 99)), batches=st["batches"],
-                mean_batch=st["batched_frames"] / max(st["batches"], 1))
+                mean_batch=st["batched_frames"] / max(st["batches"], 1), tuning=tuning)
 
 
 def run_mix(seconds: float, rate_scale: float, window_us: int):
@@ -301,9 +310,11 @@ def run_mix(seconds: float, rate_scale: float, window_us: int):
             lat[i].append(t - sched.pop(fid))
             done_t.append(t)
 
-    srv = Server(budget, on_done=on_done)
+    srv = Server(budget, on_done=on_done, graphs=GRAPHS)
     srv.set_window(window_us)
     insts = [srv.add(pr, c.X0, pc) for pr, c, pc in zip(probs, cases, precs)]
+    if TUNE:
+        srv.autotune()
     torch.cuda.synchronize()
     # one untimed frame per instance so every kernel variant is loaded
     for i in range(B):
@@ -379,6 +390,10 @@ def main() -> int:
                     help="remove the differential pistons between domains before the merge (Sec. 3.2)")
     ap.add_argument("--serving-only", action="store_true",
                     help="skip the plain-path runs (for profiling the serving kernels); no roofline line")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip autotuning the analysis launch shapes (default grid and order)")
+    ap.add_argument("--server-graphs", type=int, default=0, choices=[0, 1],
+                    help="1: server batches replayed from captured hipGraphs; 0: launched one by one")
     ap.add_argument("--copy-ref", action="store_true",
                     help="only run a plain 512 MiB device-to-device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -398,13 +413,16 @@ def main() -> int:
         print(json.dumps(dict(copy_ref_bytes_read=nbytes, copy_ref_bytes_written=nbytes, dispatches=5)))
         return 0
 
-    global PISTONS
+    global PISTONS, TUNE, GRAPHS
     PISTONS = args.pistons
+    TUNE = not args.no_tune
+    GRAPHS = bool(args.server_graphs)
     if args.mix > 0:
         print(json.dumps(run_mix(args.mix, args.rate_scale, args.window_us)), flush=True)
         return 0
 
     from paper_1310_5954_amd import BF16, FP32, FP64, build_id
+    from paper_1310_5954_amd.build import kernel_hash
     from workload.configs import build_case
 
     prec = dict(fp64=FP64, fp32=FP32, bf16=BF16)[args.precision]
@@ -422,7 +440,7 @@ def main() -> int:
         print(json.dumps(dict(metric=METRIC, value=round(lat["fps"], 2), unit="frames/s", n_gpus=1, steps=K,
                               warmup=W, p50_us=round(lat["p50_us"], 1), p99_us=round(lat["p99_us"], 1),
                               mean_batch=round(lat["mean_batch"], 3), precision=args.precision,
-                              library=build_id())), flush=True)
+                              graphs=GRAPHS, tuning=lat["tuning"], library=build_id())), flush=True)
         return 0
     plain = run_plain(case, FP64, K, W, NL, ys)
     print(f"[bench] plain fp64: {plain['fps']:.1f} frames/s p50 {plain['p50_us']:.0f} us "
@@ -435,7 +453,7 @@ def main() -> int:
     achieved = flops / (ana_ms * 1e-3) / 1e12
     roofline = dict(bound="alu", achieved=round(achieved, 3), peak=PEAK_FP64_TFLOPS, unit="TFLOP/s",
                     frac=round(achieved / PEAK_FP64_TFLOPS, 4),
-                    traffic=measured_traffic(build_id()) if args.workload == 84 else None,
+                    traffic=measured_traffic(kernel_hash()) if args.workload == 84 else None,
                     kernel=f"k_analysis<FP64, m={case.m}> (vector FP64: Cholesky + one-sided Jacobi dominate)")
     plain_out = dict(frames_per_s=round(plain["fps"], 2), p50_us=round(plain["p50_us"], 1),
                      p99_us=round(plain["p99_us"], 1),
@@ -443,7 +461,8 @@ def main() -> int:
                                     merge_forecast=round(plain["kernel_ms"][2], 4)),
                      jacobi_sweeps_mean=round(plain["sweeps"] / max(plain["solves"], 1), 3),
                      graph_replay=dict(frames_per_s=round(graph["fps"], 2), p50_us=round(graph["p50_us"], 1),
-                                       p99_us=round(graph["p99_us"], 1)))
+                                       p99_us=round(graph["p99_us"], 1)),
+                     tuning=plain["tuning"])
     dname = {FP64: "f64", FP32: "f32", BF16: "bf16+f64"}
     if args.plain_only:
         value, p50, p99, dtype, path = plain["fps"], plain["p50_us"], plain["p99_us"], "f64", "plain"
@@ -462,7 +481,7 @@ def main() -> int:
         ms_per_step = 1e3 * B / lat["fps"]
         plain_out["closed_loop"] = dict(instances=B, frames_per_s=round(loaded["fps"], 2),
                                         p50_us=round(loaded["p50_us"], 1), p99_us=round(loaded["p99_us"], 1))
-        serving_out = dict(instances=B, mean_batch=round(lat["mean_batch"], 3),
+        serving_out = dict(instances=B, mean_batch=round(lat["mean_batch"], 3), graphs=GRAPHS, tuning=lat["tuning"],
                            beats_plain_fp64=bool(lat["fps"] > loaded["fps"] and lat["p99_us"] < loaded["p99_us"]))
     out = dict(
         metric=METRIC if args.workload == 84 else METRIC.replace("84×84", "128×128").replace("m=64", "m=128"),

@@ -197,6 +197,39 @@ int letkf_unconverged_domains(letkf_handle* h, int32_t* count, void* stream);
  * recorded events.  At most 65536 frames are timed per enable. */
 int letkf_kernel_times(letkf_handle* h, int enable, double* ms_out, uint64_t* frames_out);
 
+/* Result of an autotuning run of the domain-analysis launch. */
+typedef struct letkf_tuning {
+  int32_t grid;           /* analysis workgroups per launch chosen (persistent: they share the items) */
+  int32_t by_cost;        /* 1: domains enter by decreasing cost (actuators + subapertures); 0: map order */
+  int32_t blocks_per_cu;  /* analysis workgroups of this class one CU holds at once */
+  int32_t candidates;     /* configurations timed */
+  float best_us;          /* mean analysis launch time of the choice (microseconds) */
+  float default_us;       /* same for the default: by cost, grid = min(domains, blocks_per_cu x CUs) */
+} letkf_tuning;
+
+/* Picks the analysis launch shape of this instance by timing it on its own
+ * resident data: the grid of the persistent analysis kernel (how many
+ * domains run on a CU at once: ceil(k x CUs / 2) workgroups, k = 1 ..
+ * 2 x blocks_per_cu, or one per domain; capped at the domain count) and the
+ * order in which the
+ * domains are claimed (by decreasing cost, or the map's order).  Each
+ * candidate is timed over `reps` launches (1..100) after one warm-up, with
+ * HIP events on `stream`; the choice is kept by the handle (a captured
+ * LETKF_FLAG_GRAPH frame is re-captured).  The instance's state (ensemble,
+ * frame and sweep counters) is unchanged; letkf_debug_domain reads the
+ * tuning runs' intermediates until the next analysis.  Results of later
+ * frames do not depend on the choice: every domain's analysis is computed
+ * the same way whichever workgroup runs it.  `out` may be NULL.  Waits for
+ * the stream. */
+int letkf_autotune(letkf_handle* h, int32_t reps, letkf_tuning* out, void* stream);
+
+/* Applies a launch shape chosen earlier (say a letkf_tuning kept from a
+ * letkf_autotune run on the same GPU model and domain map): grid in
+ * [1, 65535] workgroups (more than the domain count acts as the domain
+ * count) and by_cost (0 or 1); the other fields are ignored.  Waits for the
+ * stream.  LETKF_EINVAL for out-of-range fields. */
+int letkf_set_tuning(letkf_handle* h, const letkf_tuning* t, void* stream);
+
 /* Totals since create (or set_state): Jacobi sweeps over all domain solves,
  * and the number of domain solves.  Waits for the stream. */
 int letkf_sweep_stats(letkf_handle* h, uint64_t* sweeps, uint64_t* domain_solves, void* stream);
@@ -218,9 +251,37 @@ typedef void (*letkf_done_fn)(void* user, uint64_t frame_id, int status);
  * one analysis launch.  Up to 8 batches run at once, each on a stream of its
  * own, so the batches of different classes overlap on the GPU.  An instance
  * has at most one frame in flight; its frames run in submission order.
- * flags: reserved, 0. */
+ * A batch's analysis runs in the persistent kernel with the class's grid
+ * (letkf_server_autotune; by default as many workgroups as the GPU holds at
+ * once, at most one per domain item).  flags: 0 or LETKF_SERVER_GRAPHS. */
 int letkf_server_create(void* arena, size_t arena_bytes, int32_t max_batch, uint32_t flags,
                         letkf_server** out);
+
+/* Server flag: each batch's kernels (slope synthesis, analysis, pistons,
+ * merge + forecast, state advance) are replayed from a hipGraph captured on
+ * the first batch of the same shape (class, analysis grid, pistons, and the
+ * power-of-two buckets of its slope rows, domains and actuators) on the same
+ * staging slot; the uploads of the batch header and slopes and the download
+ * of the means stay ordinary copies around the replay.  The kernels read the
+ * batch's composition from the slot's header, so one graph serves every
+ * batch of that shape. */
+#define LETKF_SERVER_GRAPHS 0x1u
+
+/* Times the analysis launch of every class with admitted instances on their
+ * resident data (a batch of up to max_batch of them, as letkf_autotune does
+ * for one instance) and keeps the fastest grid per class; the instances'
+ * domain orders are set to the fastest order.  out (nullable) has 12 entries,
+ * one per class (padded size 16/32/64/128 x precision FP64/FP32/BF16, index
+ * precision x 4 + size); classes without instances are zeroed.  Only while
+ * idle: LETKF_EAGAIN when frames are queued or in flight.  Frames submitted
+ * during the call wait until it returns.  Instance states are unchanged. */
+int letkf_server_autotune(letkf_server* s, int32_t reps, letkf_tuning* out);
+
+/* Sets the analysis grid of class cls (index precision x 4 + size, as in
+ * letkf_server_autotune's output) and the domain order of its admitted
+ * instances (instances admitted later keep the default order).  Only while
+ * idle (LETKF_EAGAIN otherwise); LETKF_EINVAL for out-of-range fields. */
+int letkf_server_set_tuning(letkf_server* s, int32_t cls, const letkf_tuning* t);
 
 /* Bytes of a server's arena taken by its own instance table and staging
  * buffers (independent of the instances admitted). */

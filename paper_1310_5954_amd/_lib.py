@@ -16,6 +16,7 @@ FP64, FP32, BF16 = 0, 1, 2
 FLAG_DEBUG = 0x1
 FLAG_PISTONS = 0x2
 FLAG_GRAPH = 0x4
+SERVER_GRAPHS = 0x1
 
 
 class Dims(C.Structure):
@@ -35,6 +36,15 @@ class DomainMapC(C.Structure):
                 ("est_act", C.POINTER(C.c_int32)), ("est_w", C.POINTER(C.c_double)),
                 ("obs_ptr", C.POINTER(C.c_int32)), ("obs_sub", C.POINTER(C.c_int32)),
                 ("obs_taper", C.POINTER(C.c_double))]
+
+
+class Tuning(C.Structure):
+    _fields_ = [("grid", C.c_int32), ("by_cost", C.c_int32), ("blocks_per_cu", C.c_int32),
+                ("candidates", C.c_int32), ("best_us", C.c_float), ("default_us", C.c_float)]
+
+    def as_dict(self) -> dict:
+        return dict(grid=self.grid, by_cost=bool(self.by_cost), blocks_per_cu=self.blocks_per_cu,
+                    candidates=self.candidates, best_us=round(self.best_us, 2), default_us=round(self.default_us, 2))
 
 
 DONE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_uint64, C.c_int)
@@ -65,6 +75,10 @@ def _sig(lib):
     lib.letkf_unconverged_domains.argtypes = [P, C.POINTER(C.c_int32), P]
     lib.letkf_kernel_times.argtypes = [P, C.c_int, pd, C.POINTER(C.c_uint64)]
     lib.letkf_sweep_stats.argtypes = [P, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64), P]
+    lib.letkf_autotune.argtypes = [P, C.c_int32, C.POINTER(Tuning), P]
+    lib.letkf_server_autotune.argtypes = [P, C.c_int32, C.POINTER(Tuning)]
+    lib.letkf_set_tuning.argtypes = [P, C.POINTER(Tuning), P]
+    lib.letkf_server_set_tuning.argtypes = [P, C.c_int32, C.POINTER(Tuning)]
     lib.letkf_server_create.argtypes = [P, C.c_size_t, C.c_int32, C.c_uint32, C.POINTER(P)]
     lib.letkf_server_add.argtypes = [P, C.POINTER(Dims), C.POINTER(Model), C.POINTER(DomainMapC), C.c_int,
                                      C.c_uint32, pd, C.POINTER(P)]
@@ -85,7 +99,8 @@ def _sig(lib):
     lib.letkf_build_id.restype = C.c_char_p
     for name in ("letkf_workspace_size", "letkf_create", "letkf_destroy", "letkf_analyse", "letkf_forecast",
                  "letkf_step", "letkf_get_state", "letkf_set_state", "letkf_debug_domain",
-                 "letkf_unconverged_domains", "letkf_kernel_times", "letkf_sweep_stats", "letkf_server_create", "letkf_server_add", "letkf_server_remove",
+                 "letkf_unconverged_domains", "letkf_kernel_times", "letkf_sweep_stats", "letkf_autotune",
+                 "letkf_server_autotune", "letkf_set_tuning", "letkf_server_set_tuning", "letkf_server_create", "letkf_server_add", "letkf_server_remove",
                  "letkf_submit_frame", "letkf_submit_frame_device", "letkf_server_drain", "letkf_server_set_window", "letkf_server_stats", "letkf_server_destroy"):
         getattr(lib, name).restype = C.c_int
 

@@ -177,6 +177,21 @@ class Filter:
                     "letkf_sweep_stats")
         return int(sw.value), int(so.value)
 
+    def autotune(self, reps: int = 3) -> dict:
+        """Times the analysis launch shapes on the resident data and keeps the
+        fastest (letkf_autotune); returns the choice and its timings."""
+        t = L.Tuning()
+        with torch.cuda.device(self.device):
+            L.check(L.lib().letkf_autotune(self.handle, int(reps), C.byref(t), _stream(self.device)),
+                    "letkf_autotune")
+        return t.as_dict()
+
+    def set_tuning(self, grid: int, by_cost: bool = True):
+        """Applies a launch shape chosen earlier (letkf_set_tuning)."""
+        t = L.Tuning(grid=int(grid), by_cost=1 if by_cost else 0)
+        with torch.cuda.device(self.device):
+            L.check(L.lib().letkf_set_tuning(self.handle, C.byref(t), _stream(self.device)), "letkf_set_tuning")
+
     def unconverged(self) -> int:
         c = C.c_int32()
         with torch.cuda.device(self.device):
@@ -213,7 +228,7 @@ class Server:
     through ``done`` (frame_id -> (status, perf_counter time)) and the
     caller's prediction buffer is filled before the frame is marked done."""
 
-    def __init__(self, budget_bytes: int, max_batch: int = 64, device="cuda:0", on_done=None):
+    def __init__(self, budget_bytes: int, max_batch: int = 64, device="cuda:0", on_done=None, graphs: bool = False):
         self.device = torch.device(device)
         self.arena = torch.empty(int(budget_bytes), dtype=torch.uint8, device=self.device)
         self.done = {}
@@ -224,7 +239,7 @@ class Server:
         with torch.cuda.device(self.device):
             torch.cuda.synchronize(self.device)
             L.check(L.lib().letkf_server_create(C.c_void_p(self.arena.data_ptr()), int(budget_bytes), int(max_batch),
-                                                0, C.byref(h)), "letkf_server_create")
+                                                L.SERVER_GRAPHS if graphs else 0, C.byref(h)), "letkf_server_create")
         self.handle = h
 
     def _on_done(self, user, frame_id, status):
@@ -280,6 +295,21 @@ class Server:
 
     def set_window(self, window_us: int):
         L.check(L.lib().letkf_server_set_window(self.handle, int(window_us)), "letkf_server_set_window")
+
+    def autotune(self, reps: int = 3) -> dict:
+        """Per-class analysis launch shapes timed on the admitted instances
+        (letkf_server_autotune, only while idle); returns {class index: choice}
+        for the classes that have instances."""
+        t = (L.Tuning * 12)()
+        with torch.cuda.device(self.device):
+            L.check(L.lib().letkf_server_autotune(self.handle, int(reps), t), "letkf_server_autotune")
+        return {c: t[c].as_dict() for c in range(12) if t[c].candidates > 0}
+
+    def set_tuning(self, cls: int, grid: int, by_cost: bool = True):
+        """Sets one class's analysis grid and its instances' domain order (idle only)."""
+        t = L.Tuning(grid=int(grid), by_cost=1 if by_cost else 0)
+        with torch.cuda.device(self.device):
+            L.check(L.lib().letkf_server_set_tuning(self.handle, int(cls), C.byref(t)), "letkf_server_set_tuning")
 
     def stats(self):
         a, b, c = C.c_uint64(), C.c_uint64(), C.c_uint64()

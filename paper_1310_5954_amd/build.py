@@ -37,6 +37,18 @@ def source_hash() -> str:
     return h.hexdigest()[:16]
 
 
+def kernel_hash() -> str:
+    """Hash of the device code alone (kernels.hip, the headers it includes and
+    the compiler flags): hardware-counter summaries are keyed on it, since a
+    change to the host runtime leaves the kernels' memory traffic as it was."""
+    h = hashlib.sha256()
+    h.update(" ".join(f for f in FLAGS if not f.startswith(("/", "-I"))).encode())
+    for f in ("kernels.hip", "desc.hpp", "launch.hpp"):
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(f.encode() + b"\0" + fh.read())
+    return h.hexdigest()[:16]
+
+
 def _compile(src: str, obj: str, build_id: str) -> None:
     cmd = ["hipcc", *FLAGS, f'-DLETKF_BUILD_ID="{build_id}"', "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)

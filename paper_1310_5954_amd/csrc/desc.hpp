@@ -65,7 +65,8 @@ struct ClassBatch {
   int32_t act_off[kMaxBatch + 1];
   int32_t slope_off[kMaxBatch + 1];
   int32_t dom_off[kMaxBatch + 1];
-  uint32_t pad[2];
+  uint32_t next;                  // analysis work counter: items claimed past the first grid (k_slopes zeroes it)
+  uint32_t pad;
 };
 
 struct BatchHdr {

@@ -69,6 +69,19 @@ int server_idle_stream(letkf_handle* h, hipStream_t* stream);
 int upload_instance(const Problem& P, const Layout& L, char* ws, const double* X0, hipStream_t stream,
                     InstDesc& desc);
 
+// The order in which an instance's domains become work items: by decreasing
+// estimated cost (actuators + subapertures), or the map's own order.
+std::vector<int32_t> domain_order(const Problem& P, bool by_cost);
+// Writes the instance's domain order to its workspace on `s` and waits.
+int upload_order(letkf_handle* h, bool by_cost, hipStream_t s);
+
+// Autotuning of one class's analysis launch over the batch described by the
+// device header `hdr` (instances `insts`, whose domain orders it sets).
+// Fills `res` and returns the chosen grid in *grid_out.
+int tune_class(int cls, const InstDesc* tab, BatchHdr* hdr, int slope_rows, int items,
+               const std::vector<letkf_handle*>& insts, int num_cu, int reps, hipStream_t s,
+               letkf_tuning* res, int* grid_out);
+
 }  // namespace letkf
 
 struct letkf_handle {
@@ -92,6 +105,9 @@ struct letkf_handle {
   // captured frame (LETKF_FLAG_GRAPH)
   hipStream_t graph_stream = nullptr;
   hipGraphExec_t graph_exec = nullptr;
+  // analysis launch: persistent grid and domain order (letkf_autotune)
+  int ana_grid = 0;
+  bool by_cost = true;
   // serving
   letkf_server* server = nullptr;
   int slot = -1;               // index in the server's instance table

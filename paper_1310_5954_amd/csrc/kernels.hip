@@ -100,26 +100,32 @@ __global__ __launch_bounds__(256) void k_slopes(const InstDesc* __restrict__ tab
                                                 BatchHdr* __restrict__ hdr, int cls) {
   constexpr int RPB = 256 / MP;
   __shared__ double red[4];
-  const ClassBatch& cb = hdr->cls[cls];
-  if (blockIdx.x == 0 && (int)threadIdx.x < cb.n) tab[cb.inst[threadIdx.x]].st->unconverged = 0;
-  const int j = threadIdx.x % MP;
-  const int g = blockIdx.x * RPB + threadIdx.x / MP;
-  const int total = cb.slope_off[cb.n];
-  const bool active = g < total;
-  const int b = find_entry(cb.slope_off, cb.n, active ? g : 0);
-  const InstDesc& I = tab[cb.inst[b]];
-  const int m = I.m;
-  const int o = g - cb.slope_off[b];
-  double v = 0.0;
-  if (active && j < m) {
-    const T* ens = (const T*)I.ens + (size_t)I.st->cur * I.n_act * m;
-    for (int k = I.d_rowptr[o]; k < I.d_rowptr[o + 1]; ++k)
-      v += I.d_val[k] * ld(ens + (size_t)I.d_col[k] * m + j);
+  ClassBatch& cb = hdr->cls[cls];
+  if (blockIdx.x == 0) {
+    if ((int)threadIdx.x < cb.n) tab[cb.inst[threadIdx.x]].st->unconverged = 0;
+    if (threadIdx.x == 0) cb.next = 0;  // the analysis launch that follows claims items from zero
   }
-  const double ybar = row_sum<MP>(v, red) / (double)m;
-  if (active) {
-    if (j < m) st((T*)I.Yp + (size_t)o * m + j, v - ybar);
-    if (j == 0) I.d[o] = hdr->yptr[cb.ent[b]][o] - ybar;
+  const int j = threadIdx.x % MP;
+  const int total = cb.slope_off[cb.n];
+  // grid-stride over row groups (the trip count is uniform within a block)
+  for (int base = blockIdx.x * RPB; base < total; base += gridDim.x * RPB) {
+    const int g = base + threadIdx.x / MP;
+    const bool active = g < total;
+    const int b = find_entry(cb.slope_off, cb.n, active ? g : 0);
+    const InstDesc& I = tab[cb.inst[b]];
+    const int m = I.m;
+    const int o = g - cb.slope_off[b];
+    double v = 0.0;
+    if (active && j < m) {
+      const T* ens = (const T*)I.ens + (size_t)I.st->cur * I.n_act * m;
+      for (int k = I.d_rowptr[o]; k < I.d_rowptr[o + 1]; ++k)
+        v += I.d_val[k] * ld(ens + (size_t)I.d_col[k] * m + j);
+    }
+    const double ybar = row_sum<MP>(v, red) / (double)m;
+    if (active) {
+      if (j < m) st((T*)I.Yp + (size_t)o * m + j, v - ybar);
+      if (j == 0) I.d[o] = hdr->yptr[cb.ent[b]][o] - ybar;
+    }
   }
 }
 
@@ -136,60 +142,63 @@ __global__ __launch_bounds__(256) void k_rows(const InstDesc* __restrict__ tab,
   __shared__ double red[4];
   ClassBatch& cb = hdr->cls[cls];
   const int j = threadIdx.x % MP;
-  const int g = blockIdx.x * RPB + threadIdx.x / MP;
   const int total = cb.act_off[cb.n];
-  const bool active = g < total;
-  const int b = find_entry(cb.act_off, cb.n, active ? g : 0);
-  const InstDesc& I = tab[cb.inst[b]];
-  const int m = I.m;
-  const int a = g - cb.act_off[b];
-  const int cur = I.st->cur;
-  const size_t slot = (size_t)I.n_act * m;
-  T* ens = (T*)I.ens;
-  T* e_cur = ens + (size_t)cur * slot;
-  T* e_prev = ens + (size_t)(cur ^ 1) * slot;
-  const bool live = active && j < m;
-  double vk = 0.0, vkm1 = 0.0;
-  if (live) {
-    if (MODE == 1) {
-      vk = ld(e_cur + (size_t)a * m + j);
-      vkm1 = ld(e_prev + (size_t)a * m + j);
-    } else {
-      const T* Z = (const T*)I.Z;
-      for (int q = I.mptr[a]; q < I.mptr[a + 1]; ++q) {
-        const double w = I.mw[q];
-        double z0 = ld(Z + (size_t)I.mrow[2 * q] * m + j);
-        double z1 = ld(Z + (size_t)I.mrow[2 * q + 1] * m + j);
-        if (I.pist_c) {  // differential pistons of the covering domain (both instants)
-          const double* c = I.pist_c + (size_t)I.mdom[q] * 2 * m;
-          z0 += c[j];
-          z1 += c[m + j];
-        }
-        vk += w * z0;
-        vkm1 += w * z1;
-      }
-      // stored value (rounded to the storage type) is what the forecast uses
-      vk = (double)(T)vk;
-      vkm1 = (double)(T)vkm1;
-      st(e_cur + (size_t)a * m + j, vk);
-      if (MODE == 0) st(e_prev + (size_t)a * m + j, vkm1);
-    }
-  }
-  const int ent = cb.ent[b];
-  if (MODE != 1) {
-    const double s = row_sum<MP>(live ? vk : 0.0, red);
-    if (active && j == 0) hdr->amean[hdr->out_off[ent] + a] = s / (double)m;
-  }
-  if (MODE != 0) {
-    double nx = 0.0;
+  // grid-stride over row groups (the trip count is uniform within a block)
+  for (int base = blockIdx.x * RPB; base < total; base += gridDim.x * RPB) {
+    const int g = base + threadIdx.x / MP;
+    const bool active = g < total;
+    const int b = find_entry(cb.act_off, cb.n, active ? g : 0);
+    const InstDesc& I = tab[cb.inst[b]];
+    const int m = I.m;
+    const int a = g - cb.act_off[b];
+    const int cur = I.st->cur;
+    const size_t slot = (size_t)I.n_act * m;
+    T* ens = (T*)I.ens;
+    T* e_cur = ens + (size_t)cur * slot;
+    T* e_prev = ens + (size_t)(cur ^ 1) * slot;
+    const bool live = active && j < m;
+    double vk = 0.0, vkm1 = 0.0;
     if (live) {
-      nx = I.a1[a] * vk + I.a2[a] * vkm1;
-      if (I.sigma_v != 0.0) nx += I.sigma_v * philox_normal(I.seed, I.st->frame, (uint32_t)a, (uint32_t)j);
-      nx = (double)(T)nx;
-      st(e_prev + (size_t)a * m + j, nx);
+      if (MODE == 1) {
+        vk = ld(e_cur + (size_t)a * m + j);
+        vkm1 = ld(e_prev + (size_t)a * m + j);
+      } else {
+        const T* Z = (const T*)I.Z;
+        for (int q = I.mptr[a]; q < I.mptr[a + 1]; ++q) {
+          const double w = I.mw[q];
+          double z0 = ld(Z + (size_t)I.mrow[2 * q] * m + j);
+          double z1 = ld(Z + (size_t)I.mrow[2 * q + 1] * m + j);
+          if (I.pist_c) {  // differential pistons of the covering domain (both instants)
+            const double* c = I.pist_c + (size_t)I.mdom[q] * 2 * m;
+            z0 += c[j];
+            z1 += c[m + j];
+          }
+          vk += w * z0;
+          vkm1 += w * z1;
+        }
+        // stored value (rounded to the storage type) is what the forecast uses
+        vk = (double)(T)vk;
+        vkm1 = (double)(T)vkm1;
+        st(e_cur + (size_t)a * m + j, vk);
+        if (MODE == 0) st(e_prev + (size_t)a * m + j, vkm1);
+      }
     }
-    const double s = row_sum<MP>(nx, red);
-    if (active && j == 0) hdr->pmean[hdr->out_off[ent] + a] = s / (double)m;
+    const int ent = cb.ent[b];
+    if (MODE != 1) {
+      const double s = row_sum<MP>(live ? vk : 0.0, red);
+      if (active && j == 0) hdr->amean[hdr->out_off[ent] + a] = s / (double)m;
+    }
+    if (MODE != 0) {
+      double nx = 0.0;
+      if (live) {
+        nx = I.a1[a] * vk + I.a2[a] * vkm1;
+        if (I.sigma_v != 0.0) nx += I.sigma_v * philox_normal(I.seed, I.st->frame, (uint32_t)a, (uint32_t)j);
+        nx = (double)(T)nx;
+        st(e_prev + (size_t)a * m + j, nx);
+      }
+      const double s = row_sum<MP>(nx, red);
+      if (active && j == 0) hdr->pmean[hdr->out_off[ent] + a] = s / (double)m;
+    }
   }
 }
 
@@ -204,56 +213,58 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_piston_rhs(const InstDesc* __restrict__ tab, const BatchHdr* __restrict__ hdr,
                                                     int cls) {
   const ClassBatch& cb = hdr->cls[cls];
-  const int item = blockIdx.x;
-  if (item >= cb.dom_off[cb.n]) return;
-  const int eb = find_entry(cb.dom_off, cb.n, item);
-  const InstDesc& I = tab[cb.inst[eb]];
-  const int m = I.m, tid = threadIdx.x;
-  if (!I.pist_op || tid >= 2 * m) return;
-  const int l = item - cb.dom_off[eb], t = tid / m, i = tid % m;
-  const T* Z = (const T*)I.Z;
-  // terms precomputed at create (row, coefficient): independent loads
-  double acc[8];
+  const int total = cb.dom_off[cb.n], tid = threadIdx.x;
+  for (int item = blockIdx.x; item < total; item += gridDim.x) {
+    const int eb = find_entry(cb.dom_off, cb.n, item);
+    const InstDesc& I = tab[cb.inst[eb]];
+    const int m = I.m;
+    if (!I.pist_op || tid >= 2 * m) continue;
+    const int l = item - cb.dom_off[eb], t = tid / m, i = tid % m;
+    const T* Z = (const T*)I.Z;
+    // terms precomputed at create (row, coefficient): independent loads
+    double acc[8];
 #pragma unroll
-  for (int u = 0; u < 8; ++u) acc[u] = 0.0;
-  const int q0 = I.pist_ptr[l], q1 = I.pist_ptr[l + 1];
-  int q = q0;
-  for (; q + 8 <= q1; q += 8)
+    for (int u = 0; u < 8; ++u) acc[u] = 0.0;
+    const int q0 = I.pist_ptr[l], q1 = I.pist_ptr[l + 1];
+    int q = q0;
+    for (; q + 8 <= q1; q += 8)
 #pragma unroll
-    for (int u = 0; u < 8; ++u)
-      acc[u] = fma(I.pist_coef[q + u], ld(Z + (size_t)I.pist_row[2 * (q + u) + t] * m + i), acc[u]);
-  for (; q < q1; ++q) acc[0] = fma(I.pist_coef[q], ld(Z + (size_t)I.pist_row[2 * q + t] * m + i), acc[0]);
-  double rsum = 0.0;
+      for (int u = 0; u < 8; ++u)
+        acc[u] = fma(I.pist_coef[q + u], ld(Z + (size_t)I.pist_row[2 * (q + u) + t] * m + i), acc[u]);
+    for (; q < q1; ++q) acc[0] = fma(I.pist_coef[q], ld(Z + (size_t)I.pist_row[2 * q + t] * m + i), acc[0]);
+    double rsum = 0.0;
 #pragma unroll
-  for (int u = 0; u < 8; ++u) rsum += acc[u];
-  I.pist_r[((size_t)l * 2 + t) * m + i] = rsum;
+    for (int u = 0; u < 8; ++u) rsum += acc[u];
+    I.pist_r[((size_t)l * 2 + t) * m + i] = rsum;
+  }
 }
 
 __global__ __launch_bounds__(256) void k_piston_solve(const InstDesc* __restrict__ tab,
                                                       const BatchHdr* __restrict__ hdr, int cls) {
   const ClassBatch& cb = hdr->cls[cls];
-  const int item = blockIdx.x;
-  if (item >= cb.dom_off[cb.n]) return;
-  const int eb = find_entry(cb.dom_off, cb.n, item);
-  const InstDesc& I = tab[cb.inst[eb]];
-  const int m = I.m, tid = threadIdx.x;
-  if (!I.pist_op || tid >= 2 * m) return;
-  const int l = item - cb.dom_off[eb], t = tid / m, i = tid % m, n = I.n_dom;
-  const double* g = I.pist_op + (size_t)l * n;
-  // 16 independent partial sums keep that many L2 loads in flight
-  double acc[16];
+  const int total = cb.dom_off[cb.n], tid = threadIdx.x;
+  for (int item = blockIdx.x; item < total; item += gridDim.x) {
+    const int eb = find_entry(cb.dom_off, cb.n, item);
+    const InstDesc& I = tab[cb.inst[eb]];
+    const int m = I.m;
+    if (!I.pist_op || tid >= 2 * m) continue;
+    const int l = item - cb.dom_off[eb], t = tid / m, i = tid % m, n = I.n_dom;
+    const double* g = I.pist_op + (size_t)l * n;
+    // 16 independent partial sums keep that many L2 loads in flight
+    double acc[16];
 #pragma unroll
-  for (int u = 0; u < 16; ++u) acc[u] = 0.0;
-  const double* r = I.pist_r + (size_t)t * m + i;
-  int k = 0;
-  for (; k + 16 <= n; k += 16)
+    for (int u = 0; u < 16; ++u) acc[u] = 0.0;
+    const double* r = I.pist_r + (size_t)t * m + i;
+    int k = 0;
+    for (; k + 16 <= n; k += 16)
 #pragma unroll
-    for (int u = 0; u < 16; ++u) acc[u] = fma(g[k + u], r[(size_t)(k + u) * 2 * m], acc[u]);
-  for (; k < n; ++k) acc[0] = fma(g[k], r[(size_t)k * 2 * m], acc[0]);
-  double c = 0.0;
+      for (int u = 0; u < 16; ++u) acc[u] = fma(g[k + u], r[(size_t)(k + u) * 2 * m], acc[u]);
+    for (; k < n; ++k) acc[0] = fma(g[k], r[(size_t)k * 2 * m], acc[0]);
+    double c = 0.0;
 #pragma unroll
-  for (int u = 0; u < 16; ++u) c += acc[u];
-  I.pist_c[((size_t)l * 2 + t) * m + i] = c;
+    for (int u = 0; u < 16; ++u) c += acc[u];
+    I.pist_c[((size_t)l * 2 + t) * m + i] = c;
+  }
 }
 
 // After a forecast launch: the new instant becomes phi_k (ring swap) and the
@@ -283,6 +294,17 @@ __global__ __launch_bounds__(64) void k_advance(const InstDesc* __restrict__ tab
 // ----------------------------------------------------------------------------
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// The thread index as a value the compiler may not move: every phase of the
+// analysis derives its index arithmetic from it afresh.  Otherwise, inside the
+// persistent item loop, the arithmetic of all phases (invariant across items)
+// is hoisted out of the loop and stays live through the whole body, which
+// costs registers and so occupancy.
+__device__ __forceinline__ int phase_tid() {
+  int t = threadIdx.x;
+  asm volatile("" : "+v"(t));
+  return t;
+}
 
 template <int M> struct AnaCfg {
   static constexpr int NT = 256;
@@ -342,7 +364,7 @@ __device__ void gather_C_fp64(AnaSmem<M>& sm, const InstDesc& I, int obs_off, in
   using C = AnaCfg<M>;
   constexpr int NT = C::NT, KC = C::KC, TM = C::TM;
   double* Xc = (double*)sm.stage;
-  const int m = I.m, tid = threadIdx.x, ti = tid / 16, tj = tid % 16;
+  const int m = I.m, tid = phase_tid(), ti = tid / 16, tj = tid % 16;
   double acc[TM][TM];
 #pragma unroll
   for (int x = 0; x < TM; ++x)
@@ -414,7 +436,7 @@ __device__ void gather_C_fp64_mfma(AnaSmem<M>& sm, const InstDesc& I, int obs_of
   constexpr int WT = TILES >= 2 ? TILES / 2 : 1;
   static_assert(M <= 64 && (size_t)M * LDK * 8 <= C::STAGE_BYTES, "staging");
   double* At = (double*)sm.stage;
-  const int m = I.m, tid = threadIdx.x, w = tid / 64, lane = tid % 64;
+  const int m = I.m, tid = phase_tid(), w = tid / 64, lane = tid % 64;
   const bool wave_on = TILES >= 2 || w == 0;
   const int tr0 = TILES >= 2 ? (w / 2) * WT : 0;
   const int tc0 = TILES >= 2 ? (w % 2) * WT : 0;
@@ -494,7 +516,7 @@ __device__ void gather_C_mfma(AnaSmem<M>& sm, const InstDesc& I, int obs_off, in
   constexpr int KCH = P == 1 ? C::KCF : C::KCB;
   constexpr int TILES = M / 16;
   constexpr int WT = TILES >= 2 ? TILES / 2 : 1;
-  const int m = I.m, tid = threadIdx.x, w = tid / 64, lane = tid % 64;
+  const int m = I.m, tid = phase_tid(), w = tid / 64, lane = tid % 64;
   const bool wave_on = TILES >= 2 || w == 0;
   const int tr0 = TILES >= 2 ? (w / 2) * WT : 0;
   const int tc0 = TILES >= 2 ? (w % 2) * WT : 0;
@@ -629,7 +651,7 @@ template <int M>
 __device__ void cholesky(AnaSmem<M>& sm) {
   using C = AnaCfg<M>;
   constexpr int LDB = C::LDB, TM = C::TM;
-  const int tid = threadIdx.x, ti = tid / 16, tj = tid % 16;
+  const int tid = phase_tid(), ti = tid / 16, tj = tid % 16;
   double a[TM][TM];
 #pragma unroll
   for (int x = 0; x < TM; ++x)
@@ -685,7 +707,7 @@ template <int M>
 __device__ void cholesky_lds(AnaSmem<M>& sm) {
   using C = AnaCfg<M>;
   constexpr int NT = C::NT, LDB = C::LDB;
-  const int tid = threadIdx.x;
+  const int tid = phase_tid();
   for (int k = 0; k < M; ++k) {
     const double akk = sm.Bm[k * LDB + k];
     const double sk = sqrt(akk);
@@ -722,7 +744,7 @@ template <int M>
 __device__ bool gram_converged(AnaSmem<M>& sm, double tol2) {
   using C = AnaCfg<M>;
   constexpr int LDB = C::LDB, TM = C::TM;
-  const int tid = threadIdx.x, ti = tid / 16, tj = tid % 16;
+  const int tid = phase_tid(), ti = tid / 16, tj = tid % 16;
   double g[TM][TM];
 #pragma unroll
   for (int x = 0; x < TM; ++x)
@@ -766,7 +788,7 @@ template <int P, int M>
 __device__ int jacobi(AnaSmem<M>& sm) {
   using C = AnaCfg<M>;
   constexpr int NT = C::NT, LDB = C::LDB, TPP = C::TPP;
-  const int tid = threadIdx.x;
+  const int tid = phase_tid();
   const bool active = tid < C::ACTIVE;
   const int q = tid / TPP, sub = tid % TPP;
   // Rotations are skipped once |b_i.b_j| <= tol |b_i| |b_j|; the W and T this
@@ -880,7 +902,7 @@ __device__ void refine_wbar(AnaSmem<M>& sm, const InstDesc& I, int obs_off, int 
   constexpr int TPR = NT / KC;  // threads per staged row for its dot product with wbar
   static_assert(TPR <= 16 && KC <= 32, "row dot products reduce within 16 lanes");
   double* Xc = (double*)sm.stage;
-  const int m = I.m, tid = threadIdx.x;
+  const int m = I.m, tid = phase_tid();
   const double* Yp = (const double*)I.Yp;
   const int nobs = 2 * s;
   double cw = 0.0;  // (Y'^T diag(r) Y' wbar)[tid] for tid < M
@@ -937,7 +959,7 @@ __device__ void refine_wbar(AnaSmem<M>& sm, const InstDesc& I, int obs_off, int 
 template <int M>
 __device__ void refine_wbar_lj(AnaSmem<M>& sm, int m) {
   constexpr int LDB = AnaCfg<M>::LDB;
-  const int tid = threadIdx.x;
+  const int tid = phase_tid();
   double* z = sm.pcol[0];
   double* res = sm.pcol[1];
   __syncthreads();  // wbar was written by M threads (two wavefronts at M = 128)
@@ -977,7 +999,7 @@ __device__ void transform(AnaSmem<M>& sm, const InstDesc& I, int obs_off, int s,
   const int m = I.m;
   using C = AnaCfg<M>;
   constexpr int NT = C::NT, LDB = C::LDB, TM = C::TM;
-  const int tid = threadIdx.x, ti = tid / 16, tj = tid % 16;
+  const int tid = phase_tid(), ti = tid / 16, tj = tid % 16;
   {
     constexpr int TPC = NT / M;
     const int c = tid / TPC, part = tid % TPC;
@@ -1050,7 +1072,7 @@ __device__ void transform(AnaSmem<M>& sm, const InstDesc& I, int obs_off, int s,
 template <int M, int KCH, typename T, typename S>
 __device__ void load_rows(AnaSmem<M>& sm, S* X, const InstDesc& I, int est_off, int e, int cur, int q0, int kc) {
   constexpr int NT = AnaCfg<M>::NT;
-  const int m = I.m, tid = threadIdx.x;
+  const int m = I.m, tid = phase_tid();
   const T* ens = (const T*)I.ens;
   const size_t slot = (size_t)I.n_act * m;
   for (int idx = tid; idx < KCH * M; idx += NT) {
@@ -1083,7 +1105,7 @@ __device__ void update_fp64(AnaSmem<M>& sm, const InstDesc& I, int est_off, int 
   using C = AnaCfg<M>;
   constexpr int LDB = C::LDB, KR = 16, CB = M / 16;
   static_assert((size_t)KR * M * 8 <= C::STAGE_BYTES, "staging");
-  const int m = I.m, tid = threadIdx.x, w = tid / 64, lane = tid % 64;
+  const int m = I.m, tid = phase_tid(), w = tid / 64, lane = tid % 64;
   double* Xd = (double*)sm.stage;
   double* Z = (double*)I.Z + (size_t)2 * est_off * m;
   for (int q0 = 0; q0 < 2 * e; q0 += KR) {
@@ -1119,7 +1141,7 @@ __device__ void update_mfma(AnaSmem<M>& sm, const InstDesc& I, int est_off, int 
   using C = AnaCfg<M>;
   constexpr int LDB = C::LDB, KR = C::KR;
   constexpr int RB = KR / 16, CB = M / 16, NTILE = RB * CB;
-  const int m = I.m, tid = threadIdx.x, w = tid / 64, lane = tid % 64;
+  const int m = I.m, tid = phase_tid(), w = tid / 64, lane = tid % 64;
   float* Xf = (float*)sm.stage;
   float* Z = (float*)I.Z + (size_t)2 * est_off * m;
   for (int q0 = 0; q0 < 2 * e; q0 += KR) {
@@ -1205,23 +1227,42 @@ __device__ void analyse_item(AnaSmem<M>& sm, const InstDesc* __restrict__ tab, c
   stamp(5);
 }
 
-// One workgroup per (instance, domain) work item, items item0 + blockIdx.x.
+// Persistent: a workgroup analyses item blockIdx.x, then claims further items
+// from the class's work counter (zeroed by the slope kernel that precedes
+// every analysis launch) until the items run out, so the launch's grid can be
+// smaller than the work (fixed grids for replayed graphs, a cap on the CUs the
+// class occupies) and the heaviest domains, which come first in each
+// instance's order, start first.  Every workgroup leaves once a claim passes
+// the item count.
 template <int P, int M>
 __global__ __launch_bounds__(256) void k_analysis(const InstDesc* __restrict__ tab,
-                                                  BatchHdr* __restrict__ hdr, int cls, int item0) {
+                                                  BatchHdr* __restrict__ hdr, int cls) {
   __shared__ AnaSmem<M> sm;
-  const ClassBatch& cb = hdr->cls[cls];
-  const int item = item0 + (int)blockIdx.x;
-  if (item < cb.dom_off[cb.n]) analyse_item<P, M>(sm, tab, cb, item);
+  __shared__ int s_next;
+  ClassBatch& cb = hdr->cls[cls];
+  const int total = cb.dom_off[cb.n];
+  int item = blockIdx.x;
+  while (item < total) {
+    analyse_item<P, M>(sm, tab, cb, item);
+    if (threadIdx.x == 0) s_next = (int)gridDim.x + (int)atomicAdd(&cb.next, 1u);
+    __syncthreads();
+    item = s_next;
+    __syncthreads();
+  }
 }
 
 // ----------------------------------------------------------------------------
 // launchers
 // ----------------------------------------------------------------------------
+// Row and item kernels loop grid-stride, so their grids are capped: a launch
+// never needs more than this many workgroups to cover its work.
+constexpr int kRowGridCap = 4096;
+constexpr int kItemGridCap = 2048;
+
 template <typename T, int MP>
 static void launch_rows_t(int mode, int rows, const InstDesc* tab, BatchHdr* hdr, int cls,
                           hipStream_t s) {
-  const int grid = (rows + 256 / MP - 1) / (256 / MP);
+  const int grid = min((rows + 256 / MP - 1) / (256 / MP), kRowGridCap);
   if (grid <= 0) return;
   if (mode == 0) hipLaunchKernelGGL((k_rows<T, MP, 0>), dim3(grid), dim3(256), 0, s, tab, hdr, cls);
   if (mode == 1) hipLaunchKernelGGL((k_rows<T, MP, 1>), dim3(grid), dim3(256), 0, s, tab, hdr, cls);
@@ -1231,19 +1272,8 @@ static void launch_rows_t(int mode, int rows, const InstDesc* tab, BatchHdr* hdr
 
 template <typename T, int MP>
 static void launch_slopes_t(int rows, const InstDesc* tab, BatchHdr* hdr, int cls, hipStream_t s) {
-  const int grid = (rows + 256 / MP - 1) / (256 / MP);
+  const int grid = min((rows + 256 / MP - 1) / (256 / MP), kRowGridCap);
   if (grid > 0) hipLaunchKernelGGL((k_slopes<T, MP>), dim3(grid), dim3(256), 0, s, tab, hdr, cls);
-}
-
-template <int P, int M>
-static void launch_analysis_t(int items, int max_grid, const InstDesc* tab, BatchHdr* hdr, int cls, hipStream_t s) {
-  // A capped grid is issued as consecutive launches of at most max_grid items
-  // on the stream: between them the dispatcher hands CUs to the kernels of
-  // other streams (the server caps the m = 128 class, whose workgroups fill a
-  // CU's LDS, while instances of other classes are resident).
-  const int chunk = (max_grid > 0 && max_grid < items) ? max_grid : items;
-  for (int i0 = 0; i0 < items; i0 += chunk)
-    hipLaunchKernelGGL((k_analysis<P, M>), dim3(min(chunk, items - i0)), dim3(256), 0, s, tab, hdr, cls, i0);
 }
 
 #define LETKF_DISPATCH(FN, cls, ...)                                          \
@@ -1262,32 +1292,57 @@ static void launch_analysis_t(int items, int max_grid, const InstDesc* tab, Batc
     }                                                                         \
   } while (0)
 
+// The analysis kernel of a class (P = precision path, M = padded size).
+#define LETKF_ANA_KERNEL(cls, FN)                                   \
+  do {                                                              \
+    const int prec_ = (cls) / 4, sz_ = (cls) % 4;                   \
+    if (prec_ == 0) {                                               \
+      if (sz_ == 0) FN((k_analysis<0, 16>));                        \
+      else if (sz_ == 1) FN((k_analysis<0, 32>));                   \
+      else if (sz_ == 2) FN((k_analysis<0, 64>));                   \
+      else FN((k_analysis<0, 128>));                                \
+    } else if (prec_ == 1) {                                        \
+      if (sz_ == 0) FN((k_analysis<1, 16>));                        \
+      else if (sz_ == 1) FN((k_analysis<1, 32>));                   \
+      else if (sz_ == 2) FN((k_analysis<1, 64>));                   \
+      else FN((k_analysis<1, 128>));                                \
+    } else {                                                        \
+      if (sz_ == 0) FN((k_analysis<2, 16>));                        \
+      else if (sz_ == 1) FN((k_analysis<2, 32>));                   \
+      else if (sz_ == 2) FN((k_analysis<2, 64>));                   \
+      else FN((k_analysis<2, 128>));                                \
+    }                                                               \
+  } while (0)
+
 void launch_slopes(int cls, int rows, const InstDesc* tab, BatchHdr* hdr, hipStream_t s) {
   LETKF_DISPATCH(launch_slopes_t, cls, rows, tab, hdr, cls, s);
 }
 void launch_pistons(int cls, int items, const InstDesc* tab, BatchHdr* hdr, hipStream_t s) {
-  if (items <= 0) return;
-  if (cls / 4 == 0) hipLaunchKernelGGL(k_piston_rhs<double>, dim3(items), dim3(256), 0, s, tab, hdr, cls);
-  else hipLaunchKernelGGL(k_piston_rhs<float>, dim3(items), dim3(256), 0, s, tab, hdr, cls);
-  hipLaunchKernelGGL(k_piston_solve, dim3(items), dim3(256), 0, s, tab, hdr, cls);
+  const int grid = min(items, kItemGridCap);
+  if (grid <= 0) return;
+  if (cls / 4 == 0) hipLaunchKernelGGL(k_piston_rhs<double>, dim3(grid), dim3(256), 0, s, tab, hdr, cls);
+  else hipLaunchKernelGGL(k_piston_rhs<float>, dim3(grid), dim3(256), 0, s, tab, hdr, cls);
+  hipLaunchKernelGGL(k_piston_solve, dim3(grid), dim3(256), 0, s, tab, hdr, cls);
 }
 
 void launch_rows(int cls, int mode, int rows, const InstDesc* tab, BatchHdr* hdr, hipStream_t s) {
   LETKF_DISPATCH(launch_rows_t, cls, mode, rows, tab, hdr, cls, s);
 }
-void launch_analysis(int cls, int items, const InstDesc* tab, BatchHdr* hdr, hipStream_t s, int max_grid) {
-  const int prec = cls / 4, sz = cls % 4;
-#define LETKF_ANA(P)                                                                \
-  do {                                                                              \
-    if (sz == 0) launch_analysis_t<P, 16>(items, max_grid, tab, hdr, cls, s);       \
-    else if (sz == 1) launch_analysis_t<P, 32>(items, max_grid, tab, hdr, cls, s);  \
-    else if (sz == 2) launch_analysis_t<P, 64>(items, max_grid, tab, hdr, cls, s);  \
-    else launch_analysis_t<P, 128>(items, max_grid, tab, hdr, cls, s);              \
-  } while (0)
-  if (prec == 0) LETKF_ANA(0);
-  else if (prec == 1) LETKF_ANA(1);
-  else LETKF_ANA(2);
-#undef LETKF_ANA
+
+void launch_analysis(int cls, int grid, const InstDesc* tab, BatchHdr* hdr, hipStream_t s) {
+  if (grid <= 0) return;
+#define LETKF_LAUNCH_ANA(K) hipLaunchKernelGGL(K, dim3(grid), dim3(256), 0, s, tab, hdr, cls)
+  LETKF_ANA_KERNEL(cls, LETKF_LAUNCH_ANA);
+#undef LETKF_LAUNCH_ANA
+}
+
+int analysis_blocks_per_cu(int cls) {
+  int n = 0;
+  hipError_t e = hipSuccess;
+#define LETKF_OCC(K) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, K, 256, 0)
+  LETKF_ANA_KERNEL(cls, LETKF_OCC);
+#undef LETKF_OCC
+  return (e == hipSuccess && n > 0) ? n : 1;
 }
 
 }  // namespace letkf

@@ -1,6 +1,8 @@
 // Host launchers of the frame kernels (kernels.hip).  `cls` selects the
-// batch class (padded ensemble size, storage precision); row and item counts
-// are the launch's upper bounds (blocks past the class's work exit at once).
+// batch class (padded ensemble size, storage precision).  Row and item counts
+// size the grids (capped): every kernel reads the class's actual work from the
+// batch header and loops grid-stride over it, so a grid sized for more work
+// than the batch holds is still correct (its spare blocks exit at once).
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -15,8 +17,11 @@ void launch_rows(int cls, int mode, int act_rows, const InstDesc* tab, BatchHdr*
 // others are skipped): overlap mismatches, then pistons; between the analysis
 // and the merge.
 void launch_pistons(int cls, int domain_items, const InstDesc* tab, BatchHdr* hdr, hipStream_t s);
-// max_grid > 0 splits the items into consecutive launches of at most max_grid
-// workgroups (one workgroup per item in every case).
-void launch_analysis(int cls, int domain_items, const InstDesc* tab, BatchHdr* hdr, hipStream_t s, int max_grid = 0);
+// The persistent analysis kernel with `grid` workgroups: they share the
+// class's domain items through its work counter, which the slope kernel
+// launched before it zeroes, so any grid >= 1 covers every item.
+void launch_analysis(int cls, int grid, const InstDesc* tab, BatchHdr* hdr, hipStream_t s);
+// Analysis workgroups of the class one CU holds at once (LDS and registers).
+int analysis_blocks_per_cu(int cls);
 
 }  // namespace letkf

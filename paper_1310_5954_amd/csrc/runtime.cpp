@@ -267,6 +267,19 @@ static std::vector<double> piston_operator(const Problem& P, const std::vector<i
   return pinv;
 }
 
+std::vector<int32_t> domain_order(const Problem& P, bool by_cost) {
+  std::vector<int32_t> order(P.n_dom);
+  std::iota(order.begin(), order.end(), 0);
+  if (by_cost) {
+    // largest work first: the heaviest domains start first and the light ones fill the tail
+    auto cost = [&](int l) {
+      return (P.est_ptr[l + 1] - P.est_ptr[l]) + (P.obs_ptr[l + 1] - P.obs_ptr[l]);
+    };
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost(a) > cost(b); });
+  }
+  return order;
+}
+
 int upload_instance(const Problem& P, const Layout& L, char* ws, const double* X0, hipStream_t stream,
                     InstDesc& D) {
   const int n_act = P.n_act, m = P.m, p = P.p();
@@ -286,11 +299,7 @@ int upload_instance(const Problem& P, const Layout& L, char* ws, const double* X
     dom[4 * l + 2] = P.obs_ptr[l];
     dom[4 * l + 3] = P.obs_ptr[l + 1] - P.obs_ptr[l];
   }
-  // largest work first: with one workgroup per domain the dispatcher then packs the tail
-  std::iota(order.begin(), order.end(), 0);
-  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-    return dom[4 * a + 1] + dom[4 * a + 3] > dom[4 * b + 1] + dom[4 * b + 3];
-  });
+  order = domain_order(P, true);
   put(blob, B, L.dom, dom.data(), dom.size());
   put(blob, B, L.order, order.data(), order.size());
   put(blob, B, L.est, P.est_act.data(), P.est_act.size());
@@ -415,6 +424,8 @@ int upload_instance(const Problem& P, const Layout& L, char* ws, const double* X
   LETKF_HIP(hipMemcpyAsync(ws + L.hdr, &H, sizeof(H), hipMemcpyHostToDevice, stream));
   LETKF_HIP(hipMemcpyAsync(ws + L.ens, ens.data(), ens.size(), hipMemcpyHostToDevice, stream));
   if (L.dbg) LETKF_HIP(hipMemsetAsync(ws + L.dbg, 0, L.total - L.dbg, stream));
+  // slopes read before the first frame is staged (letkf_autotune) are zeros, not stale memory
+  LETKF_HIP(hipMemsetAsync(ws + L.y, 0, sizeof(double) * P.p(), stream));
   LETKF_HIP(hipStreamSynchronize(stream));
   return LETKF_OK;
 }
@@ -480,6 +491,100 @@ static int mark(letkf_handle* h, int k, hipStream_t s) {
 }
 static BatchHdr* dev_hdr(letkf_handle* h) { return (BatchHdr*)(h->ws + h->L.hdr); }
 
+namespace letkf {
+
+int upload_order(letkf_handle* h, bool by_cost, hipStream_t s) {
+  const std::vector<int32_t> order = domain_order(h->P, by_cost);
+  LETKF_HIP(hipMemcpyAsync(h->ws + h->L.order, order.data(), sizeof(int32_t) * order.size(),
+                           hipMemcpyHostToDevice, s));
+  LETKF_HIP(hipStreamSynchronize(s));  // `order` is a local
+  h->by_cost = by_cost;
+  return LETKF_OK;
+}
+
+// Candidates: domain order {by decreasing cost, map order} x grid
+// {ceil(k num_cu / 2), k = 1 .. 2 x (analysis workgroups per CU)} plus one
+// workgroup per item, each grid capped at the item count.  Every candidate is timed with HIP events over
+// `reps` analysis launches after one warm-up launch; each launch follows a
+// slope launch (which zeroes the work counter).  The analysis only rewrites
+// its own outputs (slope perturbations, per-domain rows, debug readback), so
+// the runs are repeatable; the instances' states (ring slot, frame and sweep
+// counters) are saved before and restored after.
+int tune_class(int cls, const InstDesc* tab, BatchHdr* hdr, int slope_rows, int items,
+               const std::vector<letkf_handle*>& insts, int num_cu, int reps, hipStream_t s,
+               letkf_tuning* res, int* grid_out) {
+  if (items <= 0 || insts.empty()) return fail(LETKF_EINVAL, "nothing to tune");
+  reps = std::max(1, std::min(reps, 100));
+  const int bpc = analysis_blocks_per_cu(cls);
+  std::vector<int> grids;
+  for (int k = 1; k <= 2 * bpc; ++k) grids.push_back(std::min(items, (k * num_cu + 1) / 2));
+  grids.push_back(std::min(items, 65535));  // one workgroup per item: the hardware dispatcher balances
+  std::sort(grids.begin(), grids.end());
+  grids.erase(std::unique(grids.begin(), grids.end()), grids.end());
+  const int def_grid = std::min(items, bpc * num_cu);
+
+  std::vector<InstState> saved(insts.size());
+  for (size_t i = 0; i < insts.size(); ++i)
+    LETKF_HIP(hipMemcpyAsync(&saved[i], insts[i]->ws + insts[i]->L.state, sizeof(InstState), hipMemcpyDeviceToHost, s));
+  LETKF_HIP(hipStreamSynchronize(s));
+
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int rc = LETKF_OK;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) rc = fail(LETKF_EDEVICE, "hipEventCreate");
+  auto time_one = [&](int grid, float* us) -> int {
+    float total = 0.f;
+    for (int r = 0; r <= reps; ++r) {
+      launch_slopes(cls, slope_rows, tab, hdr, s);
+      LETKF_HIP(hipEventRecord(e0, s));
+      launch_analysis(cls, grid, tab, hdr, s);
+      LETKF_HIP(hipEventRecord(e1, s));
+      LETKF_HIP(hipGetLastError());
+      LETKF_HIP(hipEventSynchronize(e1));
+      float ms = 0.f;
+      LETKF_HIP(hipEventElapsedTime(&ms, e0, e1));
+      if (r > 0) total += ms;  // r = 0 is the warm-up
+    }
+    *us = 1e3f * total / (float)reps;
+    return LETKF_OK;
+  };
+  float best_us = 0.f, def_us = 0.f;
+  int best_grid = def_grid, best_cost = 1, cand = 0;
+  for (int by_cost = 1; by_cost >= 0 && !rc; --by_cost) {
+    for (letkf_handle* h : insts)
+      if (!rc) rc = upload_order(h, by_cost != 0, s);
+    for (int g : grids) {
+      if (rc) break;
+      float us = 0.f;
+      if ((rc = time_one(g, &us))) break;
+      ++cand;
+      if (by_cost && g == def_grid) def_us = us;
+      if (cand == 1 || us < best_us) { best_us = us; best_grid = g; best_cost = by_cost; }
+    }
+  }
+  for (letkf_handle* h : insts)
+    if (!rc) rc = upload_order(h, best_cost != 0, s);
+  for (size_t i = 0; i < insts.size() && !rc; ++i) {
+    if (hipMemcpyAsync(insts[i]->ws + insts[i]->L.state, &saved[i], sizeof(InstState), hipMemcpyHostToDevice, s) != hipSuccess)
+      rc = fail(LETKF_EDEVICE, "state restore");
+  }
+  if (!rc && hipStreamSynchronize(s) != hipSuccess) rc = fail(LETKF_EDEVICE, "hipStreamSynchronize");
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (rc) return rc;
+  if (res) {
+    res->grid = best_grid;
+    res->by_cost = best_cost;
+    res->blocks_per_cu = bpc;
+    res->candidates = cand;
+    res->best_us = best_us;
+    res->default_us = def_us;
+  }
+  *grid_out = best_grid;
+  return LETKF_OK;
+}
+
+}  // namespace letkf
+
 extern "C" {
 
 int letkf_workspace_size(const letkf_dims* dims, const letkf_model* model, const letkf_domain_map* map,
@@ -514,6 +619,12 @@ int letkf_create(const letkf_dims* dims, const letkf_model* model, const letkf_d
   h->mpad = padded_members(h->P.m);
   h->cls = class_of(h->mpad, h->P.prec);
   rc = upload_instance(h->P, h->L, h->ws, X0, (hipStream_t)stream, h->desc);
+  if (!rc) {
+    int num_cu = 0;
+    if (hipDeviceGetAttribute(&num_cu, hipDeviceAttributeMultiprocessorCount, h->device) != hipSuccess || num_cu < 1)
+      rc = fail(LETKF_EDEVICE, "hipDeviceGetAttribute");
+    h->ana_grid = std::min(h->P.n_dom, analysis_blocks_per_cu(h->cls) * num_cu);
+  }
   if (!rc && hipHostMalloc((void**)&h->h_y, sizeof(double) * h->P.p()) != hipSuccess) rc = fail(LETKF_EDEVICE, "hipHostMalloc");
   if (!rc && hipHostMalloc((void**)&h->h_out, sizeof(double) * h->P.n_act) != hipSuccess) rc = fail(LETKF_EDEVICE, "hipHostMalloc");
   if (!rc && hipEventCreateWithFlags(&h->y_free, hipEventDisableTiming) != hipSuccess) rc = fail(LETKF_EDEVICE, "hipEventCreate");
@@ -569,7 +680,7 @@ int letkf_analyse(letkf_handle* h, const double* y, int y_on_device, double* mea
   if ((rc = mark(h, 0, s))) return rc;
   launch_slopes(h->cls, h->P.p(), dev_desc(h), dev_hdr(h), s);
   if ((rc = mark(h, 1, s))) return rc;
-  launch_analysis(h->cls, h->P.n_dom, dev_desc(h), dev_hdr(h), s);
+  launch_analysis(h->cls, h->ana_grid, dev_desc(h), dev_hdr(h), s);
   if (h->P.flags & LETKF_FLAG_PISTONS) launch_pistons(h->cls, h->P.n_dom, dev_desc(h), dev_hdr(h), s);
   if ((rc = mark(h, 2, s))) return rc;
   launch_rows(h->cls, 0, h->P.n_act, dev_desc(h), dev_hdr(h), s);
@@ -595,7 +706,7 @@ int letkf_forecast(letkf_handle* h, void* stream) {
 // state advance), all reading the frame's state from the device.
 static void launch_frame(letkf_handle* h, hipStream_t s) {
   launch_slopes(h->cls, h->P.p(), dev_desc(h), dev_hdr(h), s);
-  launch_analysis(h->cls, h->P.n_dom, dev_desc(h), dev_hdr(h), s);
+  launch_analysis(h->cls, h->ana_grid, dev_desc(h), dev_hdr(h), s);
   if (h->P.flags & LETKF_FLAG_PISTONS) launch_pistons(h->cls, h->P.n_dom, dev_desc(h), dev_hdr(h), s);
   launch_rows(h->cls, 2, h->P.n_act, dev_desc(h), dev_hdr(h), s);
 }
@@ -635,7 +746,7 @@ int letkf_step(letkf_handle* h, const double* y, int y_on_device, double* pred_o
   if ((rc = mark(h, 0, s))) return rc;
   launch_slopes(h->cls, h->P.p(), dev_desc(h), dev_hdr(h), s);
   if ((rc = mark(h, 1, s))) return rc;
-  launch_analysis(h->cls, h->P.n_dom, dev_desc(h), dev_hdr(h), s);
+  launch_analysis(h->cls, h->ana_grid, dev_desc(h), dev_hdr(h), s);
   if (h->P.flags & LETKF_FLAG_PISTONS) launch_pistons(h->cls, h->P.n_dom, dev_desc(h), dev_hdr(h), s);
   if ((rc = mark(h, 2, s))) return rc;
   launch_rows(h->cls, 2, h->P.n_act, dev_desc(h), dev_hdr(h), s);
@@ -740,6 +851,37 @@ int letkf_kernel_times(letkf_handle* h, int enable, double* ms_out, uint64_t* fr
     h->ev_used = 0;
   }
   h->timing = enable != 0;
+  return LETKF_OK;
+}
+
+int letkf_autotune(letkf_handle* h, int32_t reps, letkf_tuning* out, void* stream) {
+  int rc = check_plain(h);
+  if (rc) return rc;
+  int num_cu = 0;
+  LETKF_HIP(hipDeviceGetAttribute(&num_cu, hipDeviceAttributeMultiprocessorCount, h->device));
+  int grid = h->ana_grid;
+  if ((rc = tune_class(h->cls, dev_desc(h), dev_hdr(h), h->P.p(), h->P.n_dom, {h}, num_cu, reps,
+                       (hipStream_t)stream, out, &grid)))
+    return rc;
+  h->ana_grid = grid;
+  if (h->graph_exec) {  // the captured frame launches the old grid
+    (void)hipGraphExecDestroy(h->graph_exec);
+    h->graph_exec = nullptr;
+  }
+  return LETKF_OK;
+}
+
+int letkf_set_tuning(letkf_handle* h, const letkf_tuning* t, void* stream) {
+  int rc = check_plain(h);
+  if (rc) return rc;
+  if (!t || t->grid < 1 || t->grid > 65535 || (t->by_cost != 0 && t->by_cost != 1))
+    return fail(LETKF_EINVAL, "tuning: grid must be in [1, 65535] and by_cost 0 or 1");
+  if ((rc = upload_order(h, t->by_cost != 0, (hipStream_t)stream))) return rc;
+  h->ana_grid = std::min(t->grid, std::max(h->P.n_dom, 1));
+  if (h->graph_exec) {
+    (void)hipGraphExecDestroy(h->graph_exec);
+    h->graph_exec = nullptr;
+  }
   return LETKF_OK;
 }
 

@@ -35,6 +35,7 @@
 #include <map>
 #include <mutex>
 #include <thread>
+#include <tuple>
 #include <vector>
 
 #include "internal.hpp"
@@ -63,11 +64,30 @@ struct Frame {
 
 struct Batch {
   int slot;
-  int grid_cap = 0;            // analysis workgroups (0 = one per domain item)
+  int cls = 0;                 // the class of every instance in the batch
+  int grid_cap = 0;            // upper bound on the analysis workgroups (0 = none)
   bool pistons = false;        // some instance of the batch removes differential pistons
   std::vector<std::pair<letkf_handle*, Frame>> frames;
   std::vector<int32_t> out_off;
 };
+
+// A replayable launch sequence: class, analysis grid, pistons, and the
+// power-of-two buckets of slope rows, domain items and actuator rows that
+// size the other grids (their kernels loop over the batch's actual work).
+struct GraphKey {
+  int cls, grid, pistons, rows_s, items, rows_a;
+  bool operator<(const GraphKey& o) const {
+    return std::tie(cls, grid, pistons, rows_s, items, rows_a) <
+           std::tie(o.cls, o.grid, o.pistons, o.rows_s, o.items, o.rows_a);
+  }
+};
+constexpr size_t kMaxGraphsPerSlot = 32;
+
+int pow2ceil(int x) {
+  int p = 1;
+  while (p < x) p *= 2;
+  return p;
+}
 
 }  // namespace
 
@@ -78,6 +98,11 @@ struct letkf_server {
   int max_batch = kMaxBatch;
   int num_cu = 256;
   int64_t window_us = 100;        // longest wait of a ready frame for the rest of its class
+  uint32_t flags = 0;
+  int bpc[kNumClasses] = {};       // analysis workgroups of each class one CU holds
+  int cls_grid[kNumClasses] = {};  // analysis grid per class (letkf_server_autotune; 0 = bpc x CUs)
+  hipStream_t capture = nullptr;   // graph capture (scheduler thread only)
+  std::map<GraphKey, hipGraphExec_t> graphs[kSlots];
   hipStream_t stream[kSlots] = {};  // one per staging slot
   hipStream_t upload = nullptr;   // admissions, state access of idle instances
   // arena: [table][hdr x kSlots][y x kSlots][means x kSlots][instance region]
@@ -113,21 +138,63 @@ struct letkf_server {
   void scheduler_loop();
   void completion_loop(int k);
   int launch_batch(Batch& b);
+  int graph_for(int slot, const GraphKey& k, hipGraphExec_t* out);
+  void drop_graphs();
 };
 
 static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+void letkf_server::drop_graphs() {
+  for (auto& cache : graphs) {
+    for (auto& kv : cache) (void)hipGraphExecDestroy(kv.second);
+    cache.clear();
+  }
+}
+
+// The kernels of a batch on slot `slot` captured once per key (their
+// arguments are the slot's device header and the instance table, whose
+// contents change from batch to batch, not their addresses).
+int letkf_server::graph_for(int slot, const GraphKey& k, hipGraphExec_t* out) {
+  auto& cache = graphs[slot];
+  auto it = cache.find(k);
+  if (it != cache.end()) { *out = it->second; return LETKF_OK; }
+  if (cache.size() >= kMaxGraphsPerSlot) {
+    for (auto& kv : cache) (void)hipGraphExecDestroy(kv.second);
+    cache.clear();
+  }
+  hipGraph_t g = nullptr;
+  LETKF_HIP(hipStreamBeginCapture(capture, hipStreamCaptureModeThreadLocal));
+  launch_slopes(k.cls, k.rows_s, table(), dhdr(slot), capture);
+  launch_analysis(k.cls, k.grid, table(), dhdr(slot), capture);
+  if (k.pistons) launch_pistons(k.cls, k.items, table(), dhdr(slot), capture);
+  launch_rows(k.cls, 2, k.rows_a, table(), dhdr(slot), capture);
+  const hipError_t le = hipGetLastError();
+  const hipError_t ee = hipStreamEndCapture(capture, &g);
+  if (le != hipSuccess || ee != hipSuccess || !g) {
+    if (g) (void)hipGraphDestroy(g);
+    return fail(LETKF_EDEVICE, "stream capture of a batch failed");
+  }
+  hipGraphExec_t ex = nullptr;
+  const hipError_t ie = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (ie != hipSuccess) return fail(LETKF_EDEVICE, "hipGraphInstantiate");
+  cache[k] = ex;
+  *out = ex;
+  return LETKF_OK;
+}
+
 int letkf_server::launch_batch(Batch& b) {
-  const int s = b.slot;
+  const int s = b.slot, c = b.cls;
   BatchHdr& H = *h_hdr[s];
   std::memset(&H, 0, sizeof(H));
   H.amean = dout(s);
   H.pmean = dout(s) + kStageDoubles;
   size_t ytot = 0, otot = 0;
-  int rows_slopes[kNumClasses] = {}, rows_act[kNumClasses] = {}, items[kNumClasses] = {};
+  ClassBatch& cb = H.cls[c];
   for (size_t e = 0; e < b.frames.size(); ++e) {
     letkf_handle* h = b.frames[e].first;
     const Frame& f = b.frames[e].second;
+    if (h->cls != c) return fail(LETKF_ESTATE, "batch mixes classes");
     H.out_off[e] = (int32_t)otot;
     if (f.ydev) {
       H.yptr[e] = f.ydev;
@@ -138,30 +205,32 @@ int letkf_server::launch_batch(Batch& b) {
     }
     b.out_off.push_back((int32_t)otot);
     otot += h->P.n_act;
-    ClassBatch& cb = H.cls[h->cls];
     const int k = cb.n++;
     cb.inst[k] = h->slot;
     cb.ent[k] = (int32_t)e;
     cb.act_off[k + 1] = cb.act_off[k] + h->P.n_act;
     cb.slope_off[k + 1] = cb.slope_off[k] + h->P.p();
     cb.dom_off[k + 1] = cb.dom_off[k] + h->P.n_dom;
-    rows_slopes[h->cls] = cb.slope_off[k + 1];
-    rows_act[h->cls] = cb.act_off[k + 1];
-    items[h->cls] = cb.dom_off[k + 1];
   }
+  const int rows_s = cb.slope_off[cb.n], rows_a = cb.act_off[cb.n], items = cb.dom_off[cb.n];
+  int grid = std::min(items, cls_grid[c] ? cls_grid[c] : bpc[c] * num_cu);
+  if (b.grid_cap) grid = std::min(grid, b.grid_cap);
   hipStream_t st = stream[s];
   LETKF_HIP(hipMemcpyAsync(dhdr(s), &H, sizeof(H), hipMemcpyHostToDevice, st));
   if (ytot) LETKF_HIP(hipMemcpyAsync(dy(s), h_y[s], ytot * sizeof(double), hipMemcpyHostToDevice, st));
-  for (int c = 0; c < kNumClasses; ++c)
-    if (H.cls[c].n) launch_slopes(c, rows_slopes[c], table(), dhdr(s), st);
-  for (int c = 0; c < kNumClasses; ++c)
-    if (H.cls[c].n) launch_analysis(c, items[c], table(), dhdr(s), st, b.grid_cap);
-  if (b.pistons)
-    for (int c = 0; c < kNumClasses; ++c)
-      if (H.cls[c].n) launch_pistons(c, items[c], table(), dhdr(s), st);
-  for (int c = 0; c < kNumClasses; ++c)
-    if (H.cls[c].n) launch_rows(c, 2, rows_act[c], table(), dhdr(s), st);
-  LETKF_HIP(hipGetLastError());
+  if (flags & LETKF_SERVER_GRAPHS) {
+    const GraphKey key{c, grid, b.pistons ? 1 : 0, pow2ceil(rows_s), pow2ceil(items), pow2ceil(rows_a)};
+    hipGraphExec_t ex = nullptr;
+    int rc = graph_for(s, key, &ex);
+    if (rc) return rc;
+    LETKF_HIP(hipGraphLaunch(ex, st));
+  } else {
+    launch_slopes(c, rows_s, table(), dhdr(s), st);
+    launch_analysis(c, grid, table(), dhdr(s), st);
+    if (b.pistons) launch_pistons(c, items, table(), dhdr(s), st);
+    launch_rows(c, 2, rows_a, table(), dhdr(s), st);
+    LETKF_HIP(hipGetLastError());
+  }
   LETKF_HIP(hipMemcpyAsync(h_out[s], dout(s) + kStageDoubles, otot * sizeof(double), hipMemcpyDeviceToHost, st));
   LETKF_HIP(hipEventRecord(done_ev[s], st));
   return LETKF_OK;
@@ -214,6 +283,7 @@ void letkf_server::scheduler_loop() {
     // one frame per ready instance of the class, round robin from rr
     Batch b;
     b.slot = s;
+    b.cls = best;
     // m = 128 workgroups fill a CU each (LDS); while instances of other classes
     // are resident, such a batch keeps a quarter of the CUs free for them
     if (best % 4 == 3)
@@ -331,8 +401,9 @@ int letkf_server_create(void* arena, size_t arena_bytes, int32_t max_batch, uint
   *out = nullptr;
   if (!arena || ((uintptr_t)arena & 255)) return fail(LETKF_EINVAL, "arena must be non-null and 256-byte aligned");
   if (max_batch < 1 || max_batch > kMaxBatch) return fail(LETKF_EINVAL, "max_batch must be in [1, 64]");
-  if (flags) return fail(LETKF_EINVAL, "unknown flags");
+  if (flags & ~LETKF_SERVER_GRAPHS) return fail(LETKF_EINVAL, "unknown flags");
   auto* s = new letkf_server();
+  s->flags = flags;
   s->arena = (char*)arena;
   s->arena_bytes = arena_bytes;
   s->max_batch = max_batch;
@@ -348,6 +419,8 @@ int letkf_server_create(void* arena, size_t arena_bytes, int32_t max_batch, uint
   for (int k = 0; k < kSlots && !rc; ++k)
     if (hipStreamCreateWithFlags(&s->stream[k], hipStreamNonBlocking) != hipSuccess) rc = fail(LETKF_EDEVICE, "stream");
   if (!rc && hipStreamCreateWithFlags(&s->upload, hipStreamNonBlocking) != hipSuccess) rc = fail(LETKF_EDEVICE, "stream");
+  if (!rc && hipStreamCreateWithFlags(&s->capture, hipStreamNonBlocking) != hipSuccess) rc = fail(LETKF_EDEVICE, "stream");
+  for (int c = 0; c < kNumClasses && !rc; ++c) s->bpc[c] = analysis_blocks_per_cu(c);
   for (int k = 0; k < kSlots && !rc; ++k) {
     if (hipHostMalloc((void**)&s->h_hdr[k], sizeof(BatchHdr)) != hipSuccess ||
         hipHostMalloc((void**)&s->h_y[k], sizeof(double) * kStageDoubles) != hipSuccess ||
@@ -509,6 +582,67 @@ int letkf_server_stats(letkf_server* s, uint64_t* frames, uint64_t* batches, uin
   return LETKF_OK;
 }
 
+int letkf_server_autotune(letkf_server* s, int32_t reps, letkf_tuning* out) {
+  if (!s) return fail(LETKF_EINVAL, "null server");
+  std::unique_lock<std::mutex> lk(s->mu);  // held throughout: nothing is launched meanwhile
+  if (s->pending > 0 || s->inflight > 0) return fail(LETKF_EAGAIN, "server has frames queued or in flight");
+  const int slot = 0;
+  hipStream_t st = s->stream[slot];
+  for (int c = 0; c < kNumClasses; ++c) {
+    if (out) out[c] = letkf_tuning{};
+    BatchHdr& H = *s->h_hdr[slot];
+    std::memset(&H, 0, sizeof(H));
+    H.amean = s->dout(slot);
+    H.pmean = s->dout(slot) + kStageDoubles;
+    ClassBatch& cb = H.cls[c];
+    std::vector<letkf_handle*> insts;
+    size_t ytot = 0, otot = 0;
+    for (letkf_handle* h : s->inst) {
+      if (!h || h->cls != c || cb.n >= s->max_batch) continue;
+      if (ytot + h->P.p() > kStageDoubles || otot + h->P.n_act > kStageDoubles) break;
+      const int k = cb.n++;
+      H.yptr[k] = s->dy(slot) + ytot;  // zero slopes: the solve's cost does not depend on them
+      H.out_off[k] = (int32_t)otot;
+      ytot += h->P.p();
+      otot += h->P.n_act;
+      cb.inst[k] = h->slot;
+      cb.ent[k] = k;
+      cb.act_off[k + 1] = cb.act_off[k] + h->P.n_act;
+      cb.slope_off[k + 1] = cb.slope_off[k] + h->P.p();
+      cb.dom_off[k + 1] = cb.dom_off[k] + h->P.n_dom;
+      insts.push_back(h);
+    }
+    if (insts.empty()) continue;
+    LETKF_HIP(hipMemsetAsync(s->dy(slot), 0, ytot * sizeof(double), st));
+    LETKF_HIP(hipMemcpyAsync(s->dhdr(slot), &H, sizeof(H), hipMemcpyHostToDevice, st));
+    LETKF_HIP(hipStreamSynchronize(st));  // H is reused for the next class
+    int grid = 0;
+    int rc = tune_class(c, s->table(), s->dhdr(slot), cb.slope_off[cb.n], cb.dom_off[cb.n], insts, s->num_cu, reps,
+                        st, out ? &out[c] : nullptr, &grid);
+    if (rc) return rc;
+    s->cls_grid[c] = grid;
+  }
+  s->drop_graphs();  // captured with the old grids
+  return LETKF_OK;
+}
+
+int letkf_server_set_tuning(letkf_server* s, int32_t cls, const letkf_tuning* t) {
+  if (!s) return fail(LETKF_EINVAL, "null server");
+  if (cls < 0 || cls >= kNumClasses) return fail(LETKF_EINVAL, "class must be in [0, 12)");
+  if (!t || t->grid < 1 || t->grid > 65535 || (t->by_cost != 0 && t->by_cost != 1))
+    return fail(LETKF_EINVAL, "tuning: grid must be in [1, 65535] and by_cost 0 or 1");
+  std::unique_lock<std::mutex> lk(s->mu);
+  if (s->pending > 0 || s->inflight > 0) return fail(LETKF_EAGAIN, "server has frames queued or in flight");
+  for (letkf_handle* h : s->inst)
+    if (h && h->cls == cls) {
+      int rc = upload_order(h, t->by_cost != 0, s->upload);
+      if (rc) return rc;
+    }
+  s->cls_grid[cls] = t->grid;
+  s->drop_graphs();
+  return LETKF_OK;
+}
+
 int letkf_server_destroy(letkf_server* s) {
   if (!s) return LETKF_OK;
   if (s->sched.joinable()) {
@@ -534,9 +668,11 @@ int letkf_server_destroy(letkf_server* s) {
     if (s->h_out[k]) (void)hipHostFree(s->h_out[k]);
     if (s->done_ev[k]) (void)hipEventDestroy(s->done_ev[k]);
   }
+  s->drop_graphs();
   for (auto& st : s->stream)
     if (st) (void)hipStreamDestroy(st);
   if (s->upload) (void)hipStreamDestroy(s->upload);
+  if (s->capture) (void)hipStreamDestroy(s->capture);
   delete s;
   return LETKF_OK;
 }

@@ -316,3 +316,53 @@ def test_graph_replay_equals_eager_steps(pistons):
             graph.set_state(Xe, frame=fe)
     eager.close()
     graph.close()
+
+
+@pytest.mark.parametrize("grid,by_cost", [(1, False), (7, True), (128, False)])
+def test_persistent_grid_and_order_leave_frames_unchanged(grid, by_cost):
+    """The persistent analysis kernel launched with fewer workgroups than
+    domains (they claim the rest through the work counter), in either domain
+    order, gives the same frames bit for bit as the default launch on the
+    84x84 / m = 64 workload (FP64)."""
+    case = build_case(3)
+    pr = Problem.from_case(case)
+    ref = Filter(pr, case.X0, precision=FP64)
+    f = Filter(pr, case.X0, precision=FP64)
+    f.set_tuning(grid, by_cost)
+    for k in range(2):
+        y = case.slopes(k)
+        assert np.array_equal(ref.step(y), f.step(y)), k
+    Xr, fr = ref.get_state()
+    Xf, ff = f.get_state()
+    assert fr == ff == 2 and np.array_equal(Xr, Xf)
+    assert ref.sweep_stats() == f.sweep_stats()
+    ref.close()
+    f.close()
+
+
+def test_autotune_keeps_state_and_frames():
+    """letkf_autotune times its candidates on the resident data without
+    changing the filter: state and counters are as before, and the frames
+    after it (replayed from a re-captured graph) equal those of an untuned
+    filter bit for bit."""
+    case = build_case(3)
+    pr = Problem.from_case(case)
+    ref = Filter(pr, case.X0, precision=FP64)
+    f = Filter(pr, case.X0, precision=FP64, graph=True)
+    y0 = case.slopes(0)
+    assert np.array_equal(ref.step(y0), f.step(y0))
+    X0, f0 = f.get_state()
+    sw0 = f.sweep_stats()
+    t = f.autotune(reps=2)
+    n_dom = case.dmap.n_domains
+    assert t["candidates"] >= 2 and 1 <= t["grid"] <= n_dom and t["best_us"] > 0, t
+    assert t["best_us"] <= t["default_us"] + 1e-3, t
+    X1, f1 = f.get_state()
+    assert f1 == f0 and np.array_equal(X0, X1) and f.sweep_stats() == sw0
+    for k in range(1, 4):
+        y = case.slopes(k)
+        assert np.array_equal(ref.step(y), f.step(y)), k
+    assert f.unconverged() == 0
+    ref.close()
+    f.close()
+

@@ -34,9 +34,17 @@ def _mix_cases():
             (build_case(c24), BF16), (build_case(1, m=33), FP64)]
 
 
-def _run_server(cases, frames=FRAMES, drain_each=False, budget=1 << 30):
-    srv = Server(budget)
+def _run_server(cases, frames=FRAMES, drain_each=False, budget=1 << 30, graphs=False, tune=False, grid=None):
+    srv = Server(budget, graphs=graphs)
     insts = [srv.add(Problem.from_case(c), c.X0, p) for c, p in cases]
+    if tune:
+        choice = srv.autotune(reps=1)
+        classes = {L_class(c.m, p) for c, p in cases}
+        assert set(choice) == classes, (choice, classes)
+        assert all(1 <= t["grid"] and t["candidates"] >= 2 for t in choice.values()), choice
+    if grid is not None:                 # persistent analysis with `grid` workgroups, map order
+        for cls in range(12):
+            srv.set_tuning(cls, grid, by_cost=False)
     ys = [[c.slopes(k) for k in range(frames)] for c, _ in cases]
     preds = [[np.empty(c.n_act) for _ in range(frames)] for c, _ in cases]
     for k in range(frames):
@@ -51,6 +59,31 @@ def _run_server(cases, frames=FRAMES, drain_each=False, budget=1 << 30):
     stats = srv.stats()
     srv.close()
     return preds, states, stats
+
+
+def L_class(m, precision):
+    """Class index of an instance: precision x 4 + padded-size index."""
+    pm = 16
+    while pm < m:
+        pm *= 2
+    return precision * 4 + {16: 0, 32: 1, 64: 2, 128: 3}[pm]
+
+
+@pytest.mark.parametrize("graphs,tune,grid", [(True, False, None), (True, True, None), (False, False, 1),
+                                              (True, False, 3)])
+def test_graphs_tuning_and_grid_leave_mix_results_unchanged(graphs, tune, grid):
+    """Replayed batch graphs (LETKF_SERVER_GRAPHS), autotuned launch shapes,
+    and a persistent analysis grid far below the domain count (the
+    workgroups claim the remaining domains through the work counter) give
+    the mix the same predictions and states, bit for bit, as the default
+    one-by-one launches."""
+    cases = _mix_cases()
+    ref_preds, ref_states, _ = _run_server(cases)
+    preds, states, _ = _run_server(cases, graphs=graphs, tune=tune, grid=grid)
+    for i in range(len(cases)):
+        for k in range(FRAMES):
+            assert np.array_equal(ref_preds[i][k], preds[i][k]), (i, k)
+        assert np.array_equal(ref_states[i][0], states[i][0]) and ref_states[i][1] == states[i][1], i
 
 
 def test_alone_vs_in_the_mix_bit_identical():
