@@ -197,22 +197,29 @@ int letkf_unconverged_domains(letkf_handle* h, int32_t* count, void* stream);
  * recorded events.  At most 65536 frames are timed per enable. */
 int letkf_kernel_times(letkf_handle* h, int enable, double* ms_out, uint64_t* frames_out);
 
+/* Order in which an instance's domains become work items of the analysis
+ * launch (workgroup b takes the b-th first, further ones are claimed in
+ * order). */
+#define LETKF_ORDER_MAP 0   /* the domain map's order */
+#define LETKF_ORDER_COST 1  /* decreasing cost (actuators + subapertures): the default */
+#define LETKF_ORDER_XCD 2   /* the map's order cut into 8 contiguous chunks, position b from chunk b % 8: \
+                               workgroup b runs on XCD b % 8, so neighbouring domains share an L2 */
+
 /* Result of an autotuning run of the domain-analysis launch. */
 typedef struct letkf_tuning {
   int32_t grid;           /* analysis workgroups per launch chosen (persistent: they share the items) */
-  int32_t by_cost;        /* 1: domains enter by decreasing cost (actuators + subapertures); 0: map order */
+  int32_t order;          /* LETKF_ORDER_* */
   int32_t blocks_per_cu;  /* analysis workgroups of this class one CU holds at once */
   int32_t candidates;     /* configurations timed */
   float best_us;          /* mean analysis launch time of the choice (microseconds) */
-  float default_us;       /* same for the default: by cost, grid = min(domains, blocks_per_cu x CUs) */
+  float default_us;       /* same for the default: LETKF_ORDER_COST, grid = min(domains, blocks_per_cu x CUs) */
 } letkf_tuning;
 
 /* Picks the analysis launch shape of this instance by timing it on its own
  * resident data: the grid of the persistent analysis kernel (how many
  * domains run on a CU at once: ceil(k x CUs / 2) workgroups, k = 1 ..
  * 2 x blocks_per_cu, or one per domain; capped at the domain count) and the
- * order in which the
- * domains are claimed (by decreasing cost, or the map's order).  Each
+ * order in which the domains are claimed (LETKF_ORDER_*).  Each
  * candidate is timed over `reps` launches (1..100) after one warm-up, with
  * HIP events on `stream`; the choice is kept by the handle (a captured
  * LETKF_FLAG_GRAPH frame is re-captured).  The instance's state (ensemble,
@@ -226,8 +233,8 @@ int letkf_autotune(letkf_handle* h, int32_t reps, letkf_tuning* out, void* strea
 /* Applies a launch shape chosen earlier (say a letkf_tuning kept from a
  * letkf_autotune run on the same GPU model and domain map): grid in
  * [1, 65535] workgroups (more than the domain count acts as the domain
- * count) and by_cost (0 or 1); the other fields are ignored.  Waits for the
- * stream.  LETKF_EINVAL for out-of-range fields. */
+ * count) and order (LETKF_ORDER_*); the other fields are ignored.  Waits for
+ * the stream.  LETKF_EINVAL for out-of-range fields. */
 int letkf_set_tuning(letkf_handle* h, const letkf_tuning* t, void* stream);
 
 /* Totals since create (or set_state): Jacobi sweeps over all domain solves,

@@ -17,6 +17,8 @@ FLAG_DEBUG = 0x1
 FLAG_PISTONS = 0x2
 FLAG_GRAPH = 0x4
 SERVER_GRAPHS = 0x1
+ORDER_MAP, ORDER_COST, ORDER_XCD = 0, 1, 2
+ORDER_NAMES = {ORDER_MAP: "map", ORDER_COST: "cost", ORDER_XCD: "xcd"}
 
 
 class Dims(C.Structure):
@@ -39,11 +41,11 @@ class DomainMapC(C.Structure):
 
 
 class Tuning(C.Structure):
-    _fields_ = [("grid", C.c_int32), ("by_cost", C.c_int32), ("blocks_per_cu", C.c_int32),
+    _fields_ = [("grid", C.c_int32), ("order", C.c_int32), ("blocks_per_cu", C.c_int32),
                 ("candidates", C.c_int32), ("best_us", C.c_float), ("default_us", C.c_float)]
 
     def as_dict(self) -> dict:
-        return dict(grid=self.grid, by_cost=bool(self.by_cost), blocks_per_cu=self.blocks_per_cu,
+        return dict(grid=self.grid, order=ORDER_NAMES.get(self.order, self.order), blocks_per_cu=self.blocks_per_cu,
                     candidates=self.candidates, best_us=round(self.best_us, 2), default_us=round(self.default_us, 2))
 
 

@@ -186,9 +186,9 @@ class Filter:
                     "letkf_autotune")
         return t.as_dict()
 
-    def set_tuning(self, grid: int, by_cost: bool = True):
-        """Applies a launch shape chosen earlier (letkf_set_tuning)."""
-        t = L.Tuning(grid=int(grid), by_cost=1 if by_cost else 0)
+    def set_tuning(self, grid: int, order: int = L.ORDER_COST):
+        """Applies a launch shape chosen earlier (letkf_set_tuning; order: L.ORDER_*)."""
+        t = L.Tuning(grid=int(grid), order=int(order))
         with torch.cuda.device(self.device):
             L.check(L.lib().letkf_set_tuning(self.handle, C.byref(t), _stream(self.device)), "letkf_set_tuning")
 
@@ -305,9 +305,9 @@ class Server:
             L.check(L.lib().letkf_server_autotune(self.handle, int(reps), t), "letkf_server_autotune")
         return {c: t[c].as_dict() for c in range(12) if t[c].candidates > 0}
 
-    def set_tuning(self, cls: int, grid: int, by_cost: bool = True):
+    def set_tuning(self, cls: int, grid: int, order: int = L.ORDER_COST):
         """Sets one class's analysis grid and its instances' domain order (idle only)."""
-        t = L.Tuning(grid=int(grid), by_cost=1 if by_cost else 0)
+        t = L.Tuning(grid=int(grid), order=int(order))
         with torch.cuda.device(self.device):
             L.check(L.lib().letkf_server_set_tuning(self.handle, int(cls), C.byref(t)), "letkf_server_set_tuning")
 

@@ -69,11 +69,13 @@ int server_idle_stream(letkf_handle* h, hipStream_t* stream);
 int upload_instance(const Problem& P, const Layout& L, char* ws, const double* X0, hipStream_t stream,
                     InstDesc& desc);
 
-// The order in which an instance's domains become work items: by decreasing
-// estimated cost (actuators + subapertures), or the map's own order.
-std::vector<int32_t> domain_order(const Problem& P, bool by_cost);
+// XCDs of the GPU (MI355X): consecutive workgroups of a launch go to them in turn.
+constexpr int kXcds = 8;
+
+// The order in which an instance's domains become work items (LETKF_ORDER_*).
+std::vector<int32_t> domain_order(const Problem& P, int policy);
 // Writes the instance's domain order to its workspace on `s` and waits.
-int upload_order(letkf_handle* h, bool by_cost, hipStream_t s);
+int upload_order(letkf_handle* h, int policy, hipStream_t s);
 
 // Autotuning of one class's analysis launch over the batch described by the
 // device header `hdr` (instances `insts`, whose domain orders it sets).
@@ -107,7 +109,7 @@ struct letkf_handle {
   hipGraphExec_t graph_exec = nullptr;
   // analysis launch: persistent grid and domain order (letkf_autotune)
   int ana_grid = 0;
-  bool by_cost = true;
+  int order = LETKF_ORDER_COST;
   // serving
   letkf_server* server = nullptr;
   int slot = -1;               // index in the server's instance table

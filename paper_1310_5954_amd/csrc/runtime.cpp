@@ -267,15 +267,32 @@ static std::vector<double> piston_operator(const Problem& P, const std::vector<i
   return pinv;
 }
 
-std::vector<int32_t> domain_order(const Problem& P, bool by_cost) {
-  std::vector<int32_t> order(P.n_dom);
+std::vector<int32_t> domain_order(const Problem& P, int policy) {
+  const int n = P.n_dom;
+  std::vector<int32_t> order(n);
   std::iota(order.begin(), order.end(), 0);
-  if (by_cost) {
+  if (policy == LETKF_ORDER_COST) {
     // largest work first: the heaviest domains start first and the light ones fill the tail
     auto cost = [&](int l) {
       return (P.est_ptr[l + 1] - P.est_ptr[l]) + (P.obs_ptr[l + 1] - P.obs_ptr[l]);
     };
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost(a) > cost(b); });
+  } else if (policy == LETKF_ORDER_XCD) {
+    // Workgroup b of a launch runs on XCD b % 8.  Cut the map order into 8
+    // contiguous chunks and give position b the next domain of chunk b % 8
+    // (of another chunk once that one is used up), so that neighbouring
+    // domains, which gather overlapping rows, share an XCD's L2.
+    constexpr int X = kXcds;
+    std::vector<int> head(X), end(X);
+    for (int x = 0; x < X; ++x) {
+      head[x] = (int)((int64_t)n * x / X);
+      end[x] = (int)((int64_t)n * (x + 1) / X);
+    }
+    for (int b = 0; b < n; ++b) {
+      int x = b % X;
+      while (head[x] == end[x]) x = (x + 1) % X;
+      order[b] = head[x]++;
+    }
   }
   return order;
 }
@@ -299,7 +316,7 @@ int upload_instance(const Problem& P, const Layout& L, char* ws, const double* X
     dom[4 * l + 2] = P.obs_ptr[l];
     dom[4 * l + 3] = P.obs_ptr[l + 1] - P.obs_ptr[l];
   }
-  order = domain_order(P, true);
+  order = domain_order(P, LETKF_ORDER_COST);
   put(blob, B, L.dom, dom.data(), dom.size());
   put(blob, B, L.order, order.data(), order.size());
   put(blob, B, L.est, P.est_act.data(), P.est_act.size());
@@ -493,16 +510,17 @@ static BatchHdr* dev_hdr(letkf_handle* h) { return (BatchHdr*)(h->ws + h->L.hdr)
 
 namespace letkf {
 
-int upload_order(letkf_handle* h, bool by_cost, hipStream_t s) {
-  const std::vector<int32_t> order = domain_order(h->P, by_cost);
+int upload_order(letkf_handle* h, int policy, hipStream_t s) {
+  const std::vector<int32_t> order = domain_order(h->P, policy);
   LETKF_HIP(hipMemcpyAsync(h->ws + h->L.order, order.data(), sizeof(int32_t) * order.size(),
                            hipMemcpyHostToDevice, s));
   LETKF_HIP(hipStreamSynchronize(s));  // `order` is a local
-  h->by_cost = by_cost;
+  h->order = policy;
   return LETKF_OK;
 }
 
-// Candidates: domain order {by decreasing cost, map order} x grid
+// Candidates: domain order {by decreasing cost, map order, map order in
+// per-XCD chunks} x grid
 // {ceil(k num_cu / 2), k = 1 .. 2 x (analysis workgroups per CU)} plus one
 // workgroup per item, each grid capped at the item count.  Every candidate is timed with HIP events over
 // `reps` analysis launches after one warm-up launch; each launch follows a
@@ -548,21 +566,22 @@ int tune_class(int cls, const InstDesc* tab, BatchHdr* hdr, int slope_rows, int 
     return LETKF_OK;
   };
   float best_us = 0.f, def_us = 0.f;
-  int best_grid = def_grid, best_cost = 1, cand = 0;
-  for (int by_cost = 1; by_cost >= 0 && !rc; --by_cost) {
+  int best_grid = def_grid, best_order = LETKF_ORDER_COST, cand = 0;
+  for (int policy : {LETKF_ORDER_COST, LETKF_ORDER_MAP, LETKF_ORDER_XCD}) {
+    if (rc) break;
     for (letkf_handle* h : insts)
-      if (!rc) rc = upload_order(h, by_cost != 0, s);
+      if (!rc) rc = upload_order(h, policy, s);
     for (int g : grids) {
       if (rc) break;
       float us = 0.f;
       if ((rc = time_one(g, &us))) break;
       ++cand;
-      if (by_cost && g == def_grid) def_us = us;
-      if (cand == 1 || us < best_us) { best_us = us; best_grid = g; best_cost = by_cost; }
+      if (policy == LETKF_ORDER_COST && g == def_grid) def_us = us;
+      if (cand == 1 || us < best_us) { best_us = us; best_grid = g; best_order = policy; }
     }
   }
   for (letkf_handle* h : insts)
-    if (!rc) rc = upload_order(h, best_cost != 0, s);
+    if (!rc) rc = upload_order(h, best_order, s);
   for (size_t i = 0; i < insts.size() && !rc; ++i) {
     if (hipMemcpyAsync(insts[i]->ws + insts[i]->L.state, &saved[i], sizeof(InstState), hipMemcpyHostToDevice, s) != hipSuccess)
       rc = fail(LETKF_EDEVICE, "state restore");
@@ -573,7 +592,7 @@ int tune_class(int cls, const InstDesc* tab, BatchHdr* hdr, int slope_rows, int 
   if (rc) return rc;
   if (res) {
     res->grid = best_grid;
-    res->by_cost = best_cost;
+    res->order = best_order;
     res->blocks_per_cu = bpc;
     res->candidates = cand;
     res->best_us = best_us;
@@ -874,9 +893,9 @@ int letkf_autotune(letkf_handle* h, int32_t reps, letkf_tuning* out, void* strea
 int letkf_set_tuning(letkf_handle* h, const letkf_tuning* t, void* stream) {
   int rc = check_plain(h);
   if (rc) return rc;
-  if (!t || t->grid < 1 || t->grid > 65535 || (t->by_cost != 0 && t->by_cost != 1))
-    return fail(LETKF_EINVAL, "tuning: grid must be in [1, 65535] and by_cost 0 or 1");
-  if ((rc = upload_order(h, t->by_cost != 0, (hipStream_t)stream))) return rc;
+  if (!t || t->grid < 1 || t->grid > 65535 || t->order < LETKF_ORDER_MAP || t->order > LETKF_ORDER_XCD)
+    return fail(LETKF_EINVAL, "tuning: grid must be in [1, 65535] and order one of LETKF_ORDER_*");
+  if ((rc = upload_order(h, t->order, (hipStream_t)stream))) return rc;
   h->ana_grid = std::min(t->grid, std::max(h->P.n_dom, 1));
   if (h->graph_exec) {
     (void)hipGraphExecDestroy(h->graph_exec);

@@ -629,13 +629,13 @@ int letkf_server_autotune(letkf_server* s, int32_t reps, letkf_tuning* out) {
 int letkf_server_set_tuning(letkf_server* s, int32_t cls, const letkf_tuning* t) {
   if (!s) return fail(LETKF_EINVAL, "null server");
   if (cls < 0 || cls >= kNumClasses) return fail(LETKF_EINVAL, "class must be in [0, 12)");
-  if (!t || t->grid < 1 || t->grid > 65535 || (t->by_cost != 0 && t->by_cost != 1))
-    return fail(LETKF_EINVAL, "tuning: grid must be in [1, 65535] and by_cost 0 or 1");
+  if (!t || t->grid < 1 || t->grid > 65535 || t->order < LETKF_ORDER_MAP || t->order > LETKF_ORDER_XCD)
+    return fail(LETKF_EINVAL, "tuning: grid must be in [1, 65535] and order one of LETKF_ORDER_*");
   std::unique_lock<std::mutex> lk(s->mu);
   if (s->pending > 0 || s->inflight > 0) return fail(LETKF_EAGAIN, "server has frames queued or in flight");
   for (letkf_handle* h : s->inst)
     if (h && h->cls == cls) {
-      int rc = upload_order(h, t->by_cost != 0, s->upload);
+      int rc = upload_order(h, t->order, s->upload);
       if (rc) return rc;
     }
   s->cls_grid[cls] = t->grid;

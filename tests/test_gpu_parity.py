@@ -318,8 +318,8 @@ def test_graph_replay_equals_eager_steps(pistons):
     graph.close()
 
 
-@pytest.mark.parametrize("grid,by_cost", [(1, False), (7, True), (128, False)])
-def test_persistent_grid_and_order_leave_frames_unchanged(grid, by_cost):
+@pytest.mark.parametrize("grid,order", [(1, 0), (7, 1), (128, 2), (375, 2)])
+def test_persistent_grid_and_order_leave_frames_unchanged(grid, order):
     """The persistent analysis kernel launched with fewer workgroups than
     domains (they claim the rest through the work counter), in either domain
     order, gives the same frames bit for bit as the default launch on the
@@ -328,7 +328,7 @@ def test_persistent_grid_and_order_leave_frames_unchanged(grid, by_cost):
     pr = Problem.from_case(case)
     ref = Filter(pr, case.X0, precision=FP64)
     f = Filter(pr, case.X0, precision=FP64)
-    f.set_tuning(grid, by_cost)
+    f.set_tuning(grid, order)
     for k in range(2):
         y = case.slopes(k)
         assert np.array_equal(ref.step(y), f.step(y)), k

@@ -44,7 +44,7 @@ def _run_server(cases, frames=FRAMES, drain_each=False, budget=1 << 30, graphs=F
         assert all(1 <= t["grid"] and t["candidates"] >= 2 for t in choice.values()), choice
     if grid is not None:                 # persistent analysis with `grid` workgroups, map order
         for cls in range(12):
-            srv.set_tuning(cls, grid, by_cost=False)
+            srv.set_tuning(cls, grid, order=L.ORDER_XCD if grid > 1 else L.ORDER_MAP)
     ys = [[c.slopes(k) for k in range(frames)] for c, _ in cases]
     preds = [[np.empty(c.n_act) for _ in range(frames)] for c, _ in cases]
     for k in range(frames):
