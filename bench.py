@@ -72,6 +72,48 @@ def analysis_flops(m: int, dmap, sweeps_total: int, solves: int, frames: int) ->
     return frames * fixed + sweeps_total * dots + (sweeps_total - solves) * rots
 
 
+def run_phases(case, W, ys):
+    """Per-phase cycles of every domain's analysis workgroup (shader-clock
+    stamps of a debug instance, FP64, one frame after W warm-up frames) and
+    the bytes each phase moves, for the bandwidth view of the analysis
+    kernel: gather + C/b reads the domain's slope rows of Y' (8m bytes each)
+    plus d and r (16 bytes per observation); the update reads the domain's
+    state rows of X' and writes as many rows of Z (8m bytes each).  The
+    clock is calibrated from the kernel's HIP-event time (the slowest
+    domain's cycles over the launch's duration)."""
+    import torch
+
+    from paper_1310_5954_amd import FP64, Filter, Problem
+    f = Filter(Problem.from_case(case), case.X0, precision=FP64, device="cuda:0", debug=True)
+    for k in range(W):
+        f.step(ys[k], pred=False)
+    f.kernel_times(True)
+    f.step(ys[W], pred=False)
+    torch.cuda.synchronize()
+    ms, _ = f.kernel_times(False)
+    m, dm = case.m, case.dmap
+    names = ("gather_C", "cholesky", "jacobi", "transform", "update")
+    cyc = np.array([[f.debug_domain(l)["cycles"][n] for n in names] for l in range(dm.n_domains)])
+    f.close()
+    total = cyc.sum(axis=1)
+    clock_hz = total.max() / (ms[1] * 1e-3)
+    s_obs = 2 * np.diff(dm.obs_ptr).astype(float)
+    n_rows = 2 * np.diff(dm.est_ptr).astype(float)
+    bytes_gather = s_obs * (8 * m + 16)
+    bytes_update = n_rows * 8 * m * 2
+    out = dict(domains=int(dm.n_domains), analysis_ms=round(ms[1], 4), clock_ghz=round(clock_hz / 1e9, 3),
+               cycles_mean={n: round(float(cyc[:, i].mean())) for i, n in enumerate(names)},
+               share={n: round(float(cyc[:, i].sum() / cyc.sum()), 4) for i, n in enumerate(names)})
+    for name, i, b in (("gather_C", 0, bytes_gather), ("update", 4, bytes_update)):
+        t = cyc[:, i] / clock_hz
+        # every domain's gather starts with the launch, so the gathers overlap: aggregate = bytes / longest gather
+        out[name] = dict(bytes_total=int(b.sum()), per_domain_gbs_mean=round(float(np.mean(b / t) / 1e9), 2),
+                         aggregate_gbs=round(float(b.sum() / t.max() / 1e9), 1) if i == 0 else None,
+                         aggregate_frac_of_hbm=round(float(b.sum() / t.max() / 1e9 / PEAK_HBM_GBS), 4)
+                         if i == 0 else None)
+    return out
+
+
 def cpu_baseline(case, seconds: float = 15.0):
     """The FP64 oracle on the host, one thread, on the first frames of the
     same workload until `seconds` have passed (at least two frames)."""
@@ -394,6 +436,8 @@ def main() -> int:
                     help="skip autotuning the analysis launch shapes (default grid and order)")
     ap.add_argument("--server-graphs", type=int, default=0, choices=[0, 1],
                     help="1: server batches replayed from captured hipGraphs; 0: launched one by one")
+    ap.add_argument("--phases", action="store_true",
+                    help="only report per-phase cycles and bytes of the FP64 analysis (debug stamps), one frame")
     ap.add_argument("--copy-ref", action="store_true",
                     help="only run a plain 512 MiB device-to-device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -435,6 +479,9 @@ def main() -> int:
     ys_host = np.stack([case.slopes(k) for k in range(n_frames)])
     ys = torch.tensor(ys_host, dtype=torch.float64, device="cuda:0")
 
+    if args.phases:
+        print(json.dumps(dict(phases=run_phases(case, W, ys), library=build_id())), flush=True)
+        return 0
     if args.serving_only:
         lat = run_serving(case, prec, B, K, W, ys, depth=1)
         print(json.dumps(dict(metric=METRIC, value=round(lat["fps"], 2), unit="frames/s", n_gpus=1, steps=K,
