@@ -37,6 +37,7 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP64_TFLOPS = 78.6   # MI355X vector FP64 (256 CU x 2.4 GHz x 128 flop/clk)
 PEAK_HBM_GBS = 8000.0
+FP64_ = 0        # precision code of the FP64 path (the library's LETKF_FP64)
 
 METRIC = "frames/s + p50/p99 frame latency (µs), LETKF 84×84 subaps m=64"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_analysis_fp64_84x84_m64_traffic.txt")
@@ -114,6 +115,54 @@ def run_phases(case, W, ys):
     return out
 
 
+def big_analysis_flops(m: int, p_obs: int, n_rows: int, sweeps: float) -> float:
+    """Algorithmic FP64 flops of one global-domain analysis with m members,
+    p_obs observations and n_rows state rows: C (symmetric) m(m+1) p, b 2mp,
+    Cholesky m^3/3, per Jacobi sweep 2m^2 + m^2(m-1) for the dots and 3m^2(m-1)
+    for the rotations (all sweeps but the last), wbar 8m^2, T 2m^3, update
+    2 n m^2 + 2 n m."""
+    fixed = m * (m + 1) * p_obs + 2 * m * p_obs + m ** 3 / 3 + 8 * m * m + 2 * m ** 3 + 2 * n_rows * m * m + 2 * n_rows * m
+    return fixed + sweeps * (2 * m * m + m * m * (m - 1)) + (sweeps - 1) * 3 * m * m * (m - 1)
+
+
+def run_global(K, W, NL, with_cpu: bool):
+    """The global ETKF of Sec. 3.1 at its m = 197: one domain over a 32x32
+    circular pupil (877 actuators, 812 subapertures), plain FP64 path (the
+    m > 128 launch sequence)."""
+    import torch
+
+    from paper_1310_5954_amd import build_id
+    from workload.configs import build_case
+    cfg = dict(build_case(2).cfg)
+    cfg.update(lenslets=32, frames=W + K + NL)
+    case = build_case(cfg, m=197, global_map=True)
+    ys = torch.tensor(np.stack([case.slopes(k) for k in range(W + K + NL)]), dtype=torch.float64, device="cuda:0")
+    plain = run_plain(case, FP64_, K, W, NL, ys, tune=False)
+    p_obs = 2 * case.n_sub
+    sweeps = plain["sweeps"] / max(plain["solves"], 1)
+    flops = big_analysis_flops(case.m, p_obs, 2 * case.n_act, sweeps)
+    ana_ms = plain["kernel_ms"][1]
+    achieved = flops / (ana_ms * 1e-3) / 1e12
+    out = dict(metric="frames/s + p50/p99 frame latency (µs), global ETKF 32×32 subaps m=197",
+               value=round(plain["fps"], 2), unit="frames/s", n_gpus=1, steps=K, warmup=W,
+               ms_per_step=round(1e3 / plain["fps"], 4), higher_is_better=True, scaling="weak", vs_baseline=None,
+               dtype="f64", data="synthetic",
+               config=dict(workload=f"32x32 circular SH pupil, {case.n_act} actuators, {case.n_sub} subapertures, "
+                                    f"m=197, one global domain; one frame = analysis + AR(2) forecast",
+                           path="plain FP64, m > 128 launch sequence"),
+               p50_us=round(plain["p50_us"], 1), p99_us=round(plain["p99_us"], 1),
+               kernel_ms=dict(slopes=round(plain["kernel_ms"][0], 4), analysis=round(ana_ms, 4),
+                              merge_forecast=round(plain["kernel_ms"][2], 4)),
+               jacobi_sweeps_mean=round(sweeps, 3),
+               roofline=dict(bound="alu", achieved=round(achieved, 4), peak=PEAK_FP64_TFLOPS, unit="TFLOP/s",
+                             frac=round(achieved / PEAK_FP64_TFLOPS, 5), traffic=None,
+                             kernel="the m > 128 analysis launch sequence (one domain: at most 7 workgroups per Jacobi round)"),
+               library=build_id())
+    if with_cpu:
+        out["cpu_baseline"] = cpu_baseline(case)
+    return out
+
+
 def cpu_baseline(case, seconds: float = 15.0):
     """The FP64 oracle on the host, one thread, on the first frames of the
     same workload until `seconds` have passed (at least two frames)."""
@@ -145,13 +194,13 @@ TUNE = True      # autotune the analysis launch of every filter / server class f
 GRAPHS = False   # server batches replayed from captured graphs (--server-graphs 1); measured slower here
 
 
-def run_plain(case, prec, K, W, NL, ys):
+def run_plain(case, prec, K, W, NL, ys, tune=True):
     """Plain per-frame path on one instance: throughput, latency, kernel times."""
     import torch
 
     from paper_1310_5954_amd import Filter, Problem
     f = Filter(Problem.from_case(case), case.X0, precision=prec, device="cuda:0", pistons=PISTONS)
-    tuning = f.autotune() if TUNE else None
+    tuning = f.autotune() if (TUNE and tune) else None
     for k in range(W):
         f.step(ys[k], pred=False)
     torch.cuda.synchronize()
@@ -424,8 +473,9 @@ def main() -> int:
                     help="instead of the headline run: six mixed instances with Poisson arrivals for SECONDS")
     ap.add_argument("--rate-scale", type=float, default=1.0, help="--mix: multiplies every arrival rate")
     ap.add_argument("--window-us", type=int, default=100, help="server batching window (microseconds)")
-    ap.add_argument("--workload", type=int, default=84, choices=[84, 128],
-                    help="84: 84x84 subapertures, m = 64 (headline); 128: 128x128, m = 128")
+    ap.add_argument("--workload", type=int, default=84, choices=[84, 128, 32],
+                    help="84: 84x84 subapertures, m = 64 (headline); 128: 128x128, m = 128; "
+                         "32: global ETKF, 32x32 subapertures, m = 197 (plain FP64 only)")
     ap.add_argument("--partitions", type=int, default=1, choices=[1, 2],
                     help="2: the window partition plus one staggered by half a stride, averaged (Sec. 5)")
     ap.add_argument("--pistons", action="store_true",
@@ -461,6 +511,10 @@ def main() -> int:
     PISTONS = args.pistons
     TUNE = not args.no_tune
     GRAPHS = bool(args.server_graphs)
+    if args.workload == 32:
+        print(json.dumps(run_global(args.steps, args.warmup, args.latency_frames, not args.no_cpu_baseline)),
+              flush=True)
+        return 0
     if args.mix > 0:
         print(json.dumps(run_mix(args.mix, args.rate_scale, args.window_us)), flush=True)
         return 0

@@ -11,7 +11,10 @@
 namespace letkf {
 
 constexpr int kMaxBatch = 64;   // frames per batch
-constexpr int kNumClasses = 12; // 4 padded sizes (16, 32, 64, 128) x 3 precisions
+// classes 0..11: 4 padded sizes (16, 32, 64, 128) x 3 precisions (index
+// precision x 4 + size); class 12: 129..256 members, FP64 only
+constexpr int kNumClasses = 13;
+constexpr int kBigClass = 12;
 
 struct InstState {           // mutated on the device by the forecast kernel
   int32_t cur;               // ring slot holding phi_k (the other holds phi_{k-1})
@@ -51,6 +54,10 @@ struct InstDesc {
   const double* pist_coef;   // [terms]: its coefficient (1, or 1 - k_j for the domain's own row)
   double* pist_r;            // [n_dom][2][m] overlap mismatch of each domain, instant, member
   double* pist_c;            // [n_dom][2][m] pistons added before the merge
+  double* bigA;              // m > 128: [n_dom][256][256] A (row-major), then T
+  double* bigB;              // m > 128: [n_dom][256][256] L, then B = L J, then U (column-major)
+  double* bigv;              // m > 128: [n_dom][5][256] b, wbar, lambda, spare
+  int32_t* bigf;             // m > 128: [n_dom][4] converged, rounds that rotated, sweeps, spare
   double* dbg;               // [n_dom][2*m*m + m] C, lambda, T (NULL unless debug)
   int32_t* dbg_sweeps;       // [n_dom]
   InstState* st;
@@ -78,6 +85,7 @@ struct BatchHdr {
 };
 
 inline int class_of(int padded_m, int prec) {
+  if (padded_m > 128) return kBigClass;  // validated to be FP64
   int s = padded_m <= 16 ? 0 : padded_m <= 32 ? 1 : padded_m <= 64 ? 2 : 3;
   return prec * 4 + s;
 }

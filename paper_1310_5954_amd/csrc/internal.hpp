@@ -28,6 +28,7 @@ struct Layout {
   size_t desc, state, hdr, ens, Yp, d, Z, y, amean, pmean;
   size_t a1, a2, rowptr, col, val, dom, order, est, obs_row, obs_r, mptr, mrow, mw, mdom, pist_op;
   size_t pist_r, pist_c, pist_ptr, pist_row, pist_coef;
+  size_t bigA, bigB, bigv, bigf;   // m > 128 only
   size_t dbg, dbg_sweeps;
   size_t static_begin, static_end;  // [a1, end of tables) uploaded at create
   size_t total;
@@ -109,6 +110,7 @@ struct letkf_handle {
   hipGraphExec_t graph_exec = nullptr;
   // analysis launch: persistent grid and domain order (letkf_autotune)
   int ana_grid = 0;
+  int max_rows = 0;            // most state rows of a domain (2 e), for the m > 128 launch sequence
   int order = LETKF_ORDER_COST;
   // serving
   letkf_server* server = nullptr;

@@ -1252,6 +1252,489 @@ __global__ __launch_bounds__(256) void k_analysis(const InstDesc* __restrict__ t
 }
 
 // ----------------------------------------------------------------------------
+// a4-a8 for ensembles of 129..256 members (padded to 256, FP64).  A domain's
+// 256 x 256 matrices (512 KB each) do not fit in LDS, so its analysis is a
+// sequence of launches over scratch in the instance workspace (A, B and a few
+// vectors per domain, which stay in L2 between launches):
+//   k_big_rhs     b = Y'^T diag(r) d; clears the domain's Jacobi flags
+//   k_big_gram    A = (m-1)/rho I + Y'^T diag(r) Y', by 64 x 64 tiles
+//   k_big_chol    A = L L^T, right-looking, one workgroup per domain
+//   k_big_round   one round of the blocked one-sided Jacobi (below)
+//   k_big_sweep   end of a sweep: a domain is done when no round rotated
+//   k_big_eig     lambda, U, wbar (one refinement step through the exact A)
+//   k_big_T       T = U diag(sqrt((m-1)/lambda)) U^T + wbar 1^T, by tiles
+//   k_big_update  Z = xbar 1^T + X' T, by 64 x 64 tiles
+// The Jacobi is the one-sided method of the m <= 128 kernel on the columns of
+// L (L J = U Sigma), visited by blocks: the columns form NB blocks of 16 (NB
+// even; columns past m are unit vectors that never rotate).  A sweep is NB - 1
+// rounds of a round-robin tournament between the blocks (circle method, block
+// 0 fixed); in a round every pair of blocks is one workgroup that holds its 32
+// columns in LDS and rotates the 256 pairs between them in 16 steps of 16
+// disjoint pairs (the first round also the pairs inside each block), so every
+// pair of columns is visited once per sweep.  Launch boundaries order the
+// rounds; a converged domain's later launches return at once.
+// ----------------------------------------------------------------------------
+constexpr int kBigM = 256;
+constexpr int kBigLd = kBigM + 8;     // LDS column stride in k_big_round
+constexpr int kBigMaxSweeps = 24;
+
+struct BigDom {
+  const InstDesc* I;
+  int l, est_off, e, obs_off, s;
+  double* A;
+  double* B;
+  double* v;
+  int32_t* f;
+};
+
+__device__ __forceinline__ BigDom big_dom(const InstDesc* __restrict__ tab, const ClassBatch& cb, int item) {
+  BigDom d;
+  const int eb = find_entry(cb.dom_off, cb.n, item);
+  d.I = &tab[cb.inst[eb]];
+  d.l = item - cb.dom_off[eb];
+  d.est_off = d.I->dom[4 * d.l];
+  d.e = d.I->dom[4 * d.l + 1];
+  d.obs_off = d.I->dom[4 * d.l + 2];
+  d.s = d.I->dom[4 * d.l + 3];
+  d.A = d.I->bigA + (size_t)d.l * kBigM * kBigM;
+  d.B = d.I->bigB + (size_t)d.l * kBigM * kBigM;
+  d.v = d.I->bigv + (size_t)d.l * 5 * kBigM;
+  d.f = d.I->bigf + 4 * d.l;
+  return d;
+}
+
+__device__ __forceinline__ double* big_dbg(const BigDom& D) {
+  const int m = D.I->m;
+  return D.I->dbg ? D.I->dbg + (size_t)D.l * (2 * m * m + m + 8) : nullptr;
+}
+
+__global__ __launch_bounds__(256) void k_big_rhs(const InstDesc* __restrict__ tab, const BatchHdr* __restrict__ hdr,
+                                                 int cls) {
+  const ClassBatch& cb = hdr->cls[cls];
+  if ((int)blockIdx.x >= cb.dom_off[cb.n]) return;
+  const BigDom D = big_dom(tab, cb, blockIdx.x);
+  const InstDesc& I = *D.I;
+  const int m = I.m, j = threadIdx.x, nobs = 2 * D.s;
+  const double* Yp = (const double*)I.Yp;
+  if (j == 0) {
+    D.f[0] = 0;
+    D.f[1] = 0;
+    D.f[2] = 0;
+  }
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  if (j < m) {
+    int q = 0;
+    for (; q + 4 <= nobs; q += 4)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int o = 2 * D.obs_off + q + u, row = I.obs_row[o];
+        acc[u] = fma(I.obs_r[o] * I.d[row], Yp[(size_t)row * m + j], acc[u]);
+      }
+    for (; q < nobs; ++q) {
+      const int o = 2 * D.obs_off + q, row = I.obs_row[o];
+      acc[0] = fma(I.obs_r[o] * I.d[row], Yp[(size_t)row * m + j], acc[0]);
+    }
+  }
+  D.v[j] = j < m ? (acc[0] + acc[1]) + (acc[2] + acc[3]) : 0.0;
+}
+
+// grid (10, items): the upper tiles (ti <= tj) of the 4 x 4 grid of 64 x 64
+// tiles; each thread owns 4 x 4 entries, observations staged 32 at a time.
+__global__ __launch_bounds__(256) void k_big_gram(const InstDesc* __restrict__ tab, const BatchHdr* __restrict__ hdr,
+                                                  int cls) {
+  __shared__ double Ya[32][64], Yb[32][64];
+  const ClassBatch& cb = hdr->cls[cls];
+  if ((int)blockIdx.y >= cb.dom_off[cb.n]) return;
+  int t = blockIdx.x, ti = 0;
+  while (t >= 4 - ti) { t -= 4 - ti; ++ti; }
+  const int tj = ti + t, i0 = 64 * ti, j0 = 64 * tj;
+  const BigDom D = big_dom(tab, cb, blockIdx.y);
+  const InstDesc& I = *D.I;
+  const int m = I.m, tid = threadIdx.x, tx = tid % 16, ty = tid / 16, nobs = 2 * D.s;
+  const double* Yp = (const double*)I.Yp;
+  double acc[4][4];
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y) acc[x][y] = 0.0;
+  for (int q0 = 0; q0 < nobs; q0 += 32) {
+    for (int idx = tid; idx < 32 * 64; idx += 256) {
+      const int qq = idx / 64, c = idx % 64, q = q0 + qq;
+      double a = 0.0, b = 0.0;
+      if (q < nobs) {
+        const int o = 2 * D.obs_off + q;
+        const size_t row = (size_t)I.obs_row[o] * m;
+        if (i0 + c < m) a = Yp[row + i0 + c];
+        if (j0 + c < m) b = I.obs_r[o] * Yp[row + j0 + c];
+      }
+      Ya[qq][c] = a;
+      Yb[qq][c] = b;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int qq = 0; qq < 32; ++qq) {
+      double a[4], b[4];
+#pragma unroll
+      for (int x = 0; x < 4; ++x) a[x] = Ya[qq][ty + 16 * x];
+#pragma unroll
+      for (int y = 0; y < 4; ++y) b[y] = Yb[qq][tx + 16 * y];
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) acc[x][y] = fma(a[x], b[y], acc[x][y]);
+    }
+    __syncthreads();
+  }
+  double* dbg = big_dbg(D);
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y) {
+      const int i = i0 + ty + 16 * x, j = j0 + tx + 16 * y;
+      if (i > j) continue;  // one writer per symmetric pair (deterministic)
+      double v;
+      if (i < m && j < m) {
+        v = acc[x][y] + (i == j ? I.a_diag : 0.0);
+        if (dbg) {
+          dbg[(size_t)i * m + j] = acc[x][y];
+          dbg[(size_t)j * m + i] = acc[x][y];
+        }
+      } else {
+        v = i == j ? 1.0 : 0.0;  // padded members: identity
+      }
+      D.A[(size_t)i * kBigM + j] = v;
+      D.A[(size_t)j * kBigM + i] = v;
+    }
+}
+
+// Thread r owns row r of L (column-major B): per column k it reads the pivot
+// column from LDS, writes its entry of column k and updates its entries of the
+// trailing columns (coalesced across threads for each column).
+__global__ __launch_bounds__(256) void k_big_chol(const InstDesc* __restrict__ tab, const BatchHdr* __restrict__ hdr,
+                                                  int cls) {
+  __shared__ double pc[kBigM];
+  const ClassBatch& cb = hdr->cls[cls];
+  if ((int)blockIdx.x >= cb.dom_off[cb.n]) return;
+  const BigDom D = big_dom(tab, cb, blockIdx.x);
+  const int m = D.I->m, r = threadIdx.x;
+  for (int c = 0; c < kBigM; ++c) {
+    double v;
+    if (c < m) v = (r >= c && r < m) ? D.A[(size_t)c * kBigM + r] : 0.0;  // A symmetric
+    else v = r == c ? 1.0 : 0.0;
+    D.B[(size_t)c * kBigM + r] = v;
+  }
+  __syncthreads();
+  for (int k = 0; k < m; ++k) {
+    if (r >= k && r < m) pc[r] = D.B[(size_t)k * kBigM + r];
+    __syncthreads();
+    const double sk = sqrt(pc[k]);
+    const double inv = 1.0 / sk;
+    if (r >= k && r < m) {
+      const double lr = r == k ? sk : pc[r] * inv;
+      D.B[(size_t)k * kBigM + r] = lr;
+      if (r > k) {
+#pragma unroll 4
+        for (int c = k + 1; c <= r; ++c) D.B[(size_t)c * kBigM + r] -= lr * (pc[c] * inv);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// grid (nb / 2, items): the workgroup of block pair blockIdx.x in round `round`.
+__global__ __launch_bounds__(256) void k_big_round(const InstDesc* __restrict__ tab, const BatchHdr* __restrict__ hdr,
+                                                   int cls, int nb, int round) {
+  __shared__ double col[32 * kBigLd];
+  __shared__ double nrm[32];
+  const ClassBatch& cb = hdr->cls[cls];
+  if ((int)blockIdx.y >= cb.dom_off[cb.n]) return;
+  const BigDom D = big_dom(tab, cb, blockIdx.y);
+  if (D.f[0]) return;  // converged: uniform over the workgroup
+  const int m = D.I->m, tid = threadIdx.x, w = blockIdx.x, n1 = nb - 1;
+  const int a = w == 0 ? 0 : 1 + (round + w) % n1;
+  const int b = w == 0 ? 1 + round % n1 : 1 + (round + n1 - w) % n1;
+  // LDS column k: block a's column k (k < 16), block b's column k - 16
+  for (int idx = tid; idx < 32 * kBigM; idx += 256) {
+    const int k = idx / kBigM, r = idx % kBigM;
+    const int c = 16 * (k < 16 ? a : b) + (k & 15);
+    col[k * kBigLd + r] = D.B[(size_t)c * kBigM + r];
+  }
+  __syncthreads();
+  {
+    const int k = tid / 8, part = tid % 8;
+    double ss = 0.0;
+    for (int r = part; r < kBigM; r += 8) {
+      const double v = col[k * kBigLd + r];
+      ss = fma(v, v, ss);
+    }
+    ss = group_sum<8>(ss);
+    if (part == 0) nrm[k] = ss;
+  }
+  __syncthreads();
+  const double tol = (double)m * 1.1102230246251565e-16;
+  const double tol2 = tol * tol;
+  const int p = tid / 16, sub = tid % 16;  // pair slot, lane within the pair
+  bool rotated = false;
+  auto step = [&](int ci, int cj) {
+    double xi[16], xj[16];
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+      xi[t] = col[ci * kBigLd + sub + 16 * t];
+      xj[t] = col[cj * kBigLd + sub + 16 * t];
+    }
+    double g0 = 0.0, g1 = 0.0;
+#pragma unroll
+    for (int t = 0; t < 16; t += 2) {
+      g0 = fma(xi[t], xj[t], g0);
+      g1 = fma(xi[t + 1], xj[t + 1], g1);
+    }
+    const double gsum = group_sum<16>(g0 + g1);
+    const double al = nrm[ci], be = nrm[cj];  // the pairs of a step are disjoint
+    if (gsum * gsum > tol2 * (al * be)) {
+      const double dd = be - al, g2 = 2.0 * gsum;
+      const double q2 = fma(dd, dd, g2 * g2);
+      const double den = fma(q2, __builtin_amdgcn_rsq(q2), fabs(dd));
+      const double t = copysign(1.0, dd) * g2 * __builtin_amdgcn_rcp(den);
+      const double c = rsqrt_1_2(fma(t, t, 1.0));
+      const double sn = c * t;
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const double x = xi[u];
+        col[ci * kBigLd + sub + 16 * u] = c * x - sn * xj[u];
+        col[cj * kBigLd + sub + 16 * u] = sn * x + c * xj[u];
+      }
+      if (sub == 0) {
+        nrm[ci] = al - t * gsum;
+        nrm[cj] = be + t * gsum;
+      }
+      rotated = true;
+    }
+    __syncthreads();
+  };
+  if (round == 0) {
+    // pairs inside each block, (i, i ^ k): slots 0..7 block a, 8..15 block b
+    const int base = p < 8 ? 0 : 16, q = p & 7;
+    for (int k = 1; k < 16; ++k) {
+      const int hk = 31 - __clz(k);
+      const int i = ((q >> hk) << (hk + 1)) | (q & ((1 << hk) - 1));
+      step(base + i, base + (i ^ k));
+    }
+  }
+  for (int st = 0; st < 16; ++st) step(p, 16 + ((p + st) & 15));
+  if (__syncthreads_or(rotated)) {
+    for (int idx = tid; idx < 32 * kBigM; idx += 256) {
+      const int k = idx / kBigM, r = idx % kBigM;
+      const int c = 16 * (k < 16 ? a : b) + (k & 15);
+      D.B[(size_t)c * kBigM + r] = col[k * kBigLd + r];
+    }
+    if (tid == 0) atomicAdd(&D.f[1], 1);
+  }
+}
+
+__global__ __launch_bounds__(64) void k_big_sweep(const InstDesc* __restrict__ tab, const BatchHdr* __restrict__ hdr,
+                                                  int cls) {
+  const ClassBatch& cb = hdr->cls[cls];
+  const int item = blockIdx.x * 64 + threadIdx.x;
+  if (item >= cb.dom_off[cb.n]) return;
+  const BigDom D = big_dom(tab, cb, item);
+  if (D.f[0]) return;
+  D.f[2] += 1;
+  if (D.f[1] == 0) {
+    D.f[0] = 1;
+  } else if (D.f[2] >= kBigMaxSweeps) {
+    D.f[0] = 2;
+    atomicAdd(&D.I->st->unconverged, 1);
+  }
+  D.f[1] = 0;
+}
+
+// Thread c: lambda_c and U_c = B_c / sigma_c; then wbar = U Lambda^-1 U^T b
+// and one refinement step wbar += U Lambda^-1 U^T (b - A wbar) with the exact A.
+__global__ __launch_bounds__(256) void k_big_eig(const InstDesc* __restrict__ tab, const BatchHdr* __restrict__ hdr,
+                                                 int cls) {
+  __shared__ double bs[kBigM], zs[kBigM], wsh[kBigM];
+  const ClassBatch& cb = hdr->cls[cls];
+  if ((int)blockIdx.x >= cb.dom_off[cb.n]) return;
+  const BigDom D = big_dom(tab, cb, blockIdx.x);
+  const InstDesc& I = *D.I;
+  const int m = I.m, c = threadIdx.x;
+  double* Bc = D.B + (size_t)c * kBigM;
+  double lc = 1.0;
+  if (c < m) {
+    double ss = 0.0;
+    for (int r = 0; r < m; ++r) ss = fma(Bc[r], Bc[r], ss);
+    lc = ss;
+    const double inv = 1.0 / sqrt(ss);
+    for (int r = 0; r < m; ++r) Bc[r] *= inv;
+  }
+  D.v[2 * kBigM + c] = lc;
+  bs[c] = D.v[c];
+  __syncthreads();
+  auto project = [&](const double* rhs) {  // zs = Lambda^-1 U^T rhs
+    double z = 0.0;
+    if (c < m)
+      for (int r = 0; r < m; ++r) z = fma(Bc[r], rhs[r], z);
+    zs[c] = c < m ? z / lc : 0.0;
+    __syncthreads();
+  };
+  auto expand = [&](int r) {  // (U zs)[r]
+    double w = 0.0;
+    if (r < m)
+      for (int k = 0; k < m; ++k) w = fma(D.B[(size_t)k * kBigM + r], zs[k], w);
+    return w;
+  };
+  project(bs);
+  const int r = threadIdx.x;
+  wsh[r] = r < m ? expand(r) : 0.0;
+  __syncthreads();
+  double res = 0.0;
+  if (r < m) {
+    double t = 0.0;
+    for (int j = 0; j < m; ++j) t = fma(D.A[(size_t)j * kBigM + r], wsh[j], t);
+    res = bs[r] - t;
+  }
+  __syncthreads();
+  bs[r] = res;
+  __syncthreads();
+  project(bs);
+  D.v[kBigM + r] = r < m ? wsh[r] + expand(r) : 0.0;
+  double* dbg = big_dbg(D);
+  if (dbg && c < m) dbg[(size_t)m * m + c] = lc;
+  if (threadIdx.x == 0) {
+    const int sweeps = D.f[2];
+    if (I.dbg_sweeps) I.dbg_sweeps[D.l] = sweeps;
+    atomicAdd(&I.st->sweeps, (unsigned long long)sweeps);
+    atomicAdd(&I.st->solves, 1ull);
+  }
+}
+
+// grid (16, items): 64 x 64 tile (blockIdx.x / 4, blockIdx.x % 4) of T, written
+// over A (row-major); U columns staged 32 at a time.
+__global__ __launch_bounds__(256) void k_big_T(const InstDesc* __restrict__ tab, const BatchHdr* __restrict__ hdr,
+                                               int cls) {
+  __shared__ double Ua[32][64], Ub[32][64];
+  __shared__ double sc[kBigM];
+  const ClassBatch& cb = hdr->cls[cls];
+  if ((int)blockIdx.y >= cb.dom_off[cb.n]) return;
+  const BigDom D = big_dom(tab, cb, blockIdx.y);
+  const int m = D.I->m, tid = threadIdx.x, tx = tid % 16, ty = tid / 16;
+  const int i0 = 64 * (blockIdx.x / 4), j0 = 64 * (blockIdx.x % 4);
+  if (i0 >= m || j0 >= m) return;
+  sc[tid] = tid < m ? sqrt((double)(m - 1) / D.v[2 * kBigM + tid]) : 0.0;
+  __syncthreads();
+  double acc[4][4];
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y) acc[x][y] = 0.0;
+  for (int c0 = 0; c0 < m; c0 += 32) {
+    for (int idx = tid; idx < 32 * 64; idx += 256) {
+      const int cc = idx / 64, q = idx % 64, c = c0 + cc;
+      const double* Uc = D.B + (size_t)c * kBigM;
+      Ua[cc][q] = (c < m && i0 + q < m) ? Uc[i0 + q] * sc[c] : 0.0;
+      Ub[cc][q] = (c < m && j0 + q < m) ? Uc[j0 + q] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int cc = 0; cc < 32; ++cc) {
+      double a[4], b[4];
+#pragma unroll
+      for (int x = 0; x < 4; ++x) a[x] = Ua[cc][ty + 16 * x];
+#pragma unroll
+      for (int y = 0; y < 4; ++y) b[y] = Ub[cc][tx + 16 * y];
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) acc[x][y] = fma(a[x], b[y], acc[x][y]);
+    }
+    __syncthreads();
+  }
+  double* dbg = big_dbg(D);
+  const double* wbar = D.v + kBigM;
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y) {
+      const int i = i0 + ty + 16 * x, j = j0 + tx + 16 * y;
+      if (i < m && j < m) {
+        const double tv = acc[x][y] + wbar[i];
+        D.A[(size_t)i * kBigM + j] = tv;
+        if (dbg) dbg[(size_t)m * m + m + (size_t)i * m + j] = tv;
+      }
+    }
+}
+
+// grid (row tiles, member tiles, items): Z rows q0..q0+63 of the domain (both
+// instants), members j0..j0+63; X' staged 32 members at a time.
+__global__ __launch_bounds__(256) void k_big_update(const InstDesc* __restrict__ tab, const BatchHdr* __restrict__ hdr,
+                                                    int cls) {
+  __shared__ double Xs[64][33], Ts[32][64], xb[64];
+  const ClassBatch& cb = hdr->cls[cls];
+  if ((int)blockIdx.z >= cb.dom_off[cb.n]) return;
+  const BigDom D = big_dom(tab, cb, blockIdx.z);
+  const InstDesc& I = *D.I;
+  const int m = I.m, rows = 2 * D.e, tid = threadIdx.x, tx = tid % 16, ty = tid / 16;
+  const int q0 = 64 * blockIdx.x, j0 = 64 * blockIdx.y;
+  if (q0 >= rows || j0 >= m) return;
+  const int cur = I.st->cur;
+  const double* ens = (const double*)I.ens;
+  const size_t slot = (size_t)I.n_act * m;
+  auto row_ptr = [&](int q) {  // ensemble row of the domain's state row q
+    const int inst = q < D.e ? cur : (cur ^ 1);
+    const int act = I.est_act[D.est_off + (q < D.e ? q : q - D.e)];
+    return ens + (size_t)inst * slot + (size_t)act * m;
+  };
+  {
+    const int rr = tid / 4, part = tid % 4, q = q0 + rr;
+    double sum = 0.0;
+    if (q < rows) {
+      const double* x = row_ptr(q);
+      for (int j = part; j < m; j += 4) sum += x[j];
+    }
+    sum = group_sum<4>(sum);
+    if (part == 0) xb[rr] = sum / (double)m;
+  }
+  __syncthreads();
+  double acc[4][4];
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y) acc[x][y] = 0.0;
+  for (int k0 = 0; k0 < m; k0 += 32) {
+    for (int idx = tid; idx < 64 * 32; idx += 256) {
+      const int rr = idx / 32, kk = idx % 32, q = q0 + rr, k = k0 + kk;
+      Xs[rr][kk] = (q < rows && k < m) ? row_ptr(q)[k] - xb[rr] : 0.0;
+    }
+    for (int idx = tid; idx < 32 * 64; idx += 256) {
+      const int kk = idx / 64, cc = idx % 64, k = k0 + kk, j = j0 + cc;
+      Ts[kk][cc] = (k < m && j < m) ? D.A[(size_t)k * kBigM + j] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int kk = 0; kk < 32; ++kk) {
+      double a[4], b[4];
+#pragma unroll
+      for (int x = 0; x < 4; ++x) a[x] = Xs[ty + 16 * x][kk];
+#pragma unroll
+      for (int y = 0; y < 4; ++y) b[y] = Ts[kk][tx + 16 * y];
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) acc[x][y] = fma(a[x], b[y], acc[x][y]);
+    }
+    __syncthreads();
+  }
+  double* Z = (double*)I.Z + (size_t)2 * D.est_off * m;
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y) {
+      const int rr = ty + 16 * x, q = q0 + rr, j = j0 + tx + 16 * y;
+      if (q < rows && j < m) Z[(size_t)q * m + j] = xb[rr] + acc[x][y];
+    }
+}
+
+// ----------------------------------------------------------------------------
 // launchers
 // ----------------------------------------------------------------------------
 // Row and item kernels loop grid-stride, so their grids are capped: a launch
@@ -1279,7 +1762,9 @@ static void launch_slopes_t(int rows, const InstDesc* tab, BatchHdr* hdr, int cl
 #define LETKF_DISPATCH(FN, cls, ...)                                          \
   do {                                                                        \
     const int prec_ = (cls) / 4, sz_ = (cls) % 4;                             \
-    if (prec_ == 0) {                                                         \
+    if ((cls) == kBigClass) {                                                 \
+      FN<double, 256>(__VA_ARGS__);                                           \
+    } else if (prec_ == 0) {                                                  \
       if (sz_ == 0) FN<double, 16>(__VA_ARGS__);                              \
       else if (sz_ == 1) FN<double, 32>(__VA_ARGS__);                         \
       else if (sz_ == 2) FN<double, 64>(__VA_ARGS__);                         \
@@ -1320,7 +1805,7 @@ void launch_slopes(int cls, int rows, const InstDesc* tab, BatchHdr* hdr, hipStr
 void launch_pistons(int cls, int items, const InstDesc* tab, BatchHdr* hdr, hipStream_t s) {
   const int grid = min(items, kItemGridCap);
   if (grid <= 0) return;
-  if (cls / 4 == 0) hipLaunchKernelGGL(k_piston_rhs<double>, dim3(grid), dim3(256), 0, s, tab, hdr, cls);
+  if (cls / 4 == 0 || cls == kBigClass) hipLaunchKernelGGL(k_piston_rhs<double>, dim3(grid), dim3(256), 0, s, tab, hdr, cls);
   else hipLaunchKernelGGL(k_piston_rhs<float>, dim3(grid), dim3(256), 0, s, tab, hdr, cls);
   hipLaunchKernelGGL(k_piston_solve, dim3(grid), dim3(256), 0, s, tab, hdr, cls);
 }
@@ -1329,14 +1814,32 @@ void launch_rows(int cls, int mode, int rows, const InstDesc* tab, BatchHdr* hdr
   LETKF_DISPATCH(launch_rows_t, cls, mode, rows, tab, hdr, cls, s);
 }
 
+void launch_big_analysis(int items, int rows_max, int m_max, const InstDesc* tab, BatchHdr* hdr, hipStream_t s) {
+  if (items <= 0) return;
+  const int cls = kBigClass, nb = 2 * ((m_max + 31) / 32);
+  hipLaunchKernelGGL(k_big_rhs, dim3(items), dim3(256), 0, s, tab, hdr, cls);
+  hipLaunchKernelGGL(k_big_gram, dim3(10, items), dim3(256), 0, s, tab, hdr, cls);
+  hipLaunchKernelGGL(k_big_chol, dim3(items), dim3(256), 0, s, tab, hdr, cls);
+  for (int sw = 0; sw < kBigMaxSweeps; ++sw) {
+    for (int r = 0; r < nb - 1; ++r)
+      hipLaunchKernelGGL(k_big_round, dim3(nb / 2, items), dim3(256), 0, s, tab, hdr, cls, nb, r);
+    hipLaunchKernelGGL(k_big_sweep, dim3((items + 63) / 64), dim3(64), 0, s, tab, hdr, cls);
+  }
+  hipLaunchKernelGGL(k_big_eig, dim3(items), dim3(256), 0, s, tab, hdr, cls);
+  hipLaunchKernelGGL(k_big_T, dim3(16, items), dim3(256), 0, s, tab, hdr, cls);
+  hipLaunchKernelGGL(k_big_update, dim3((rows_max + 63) / 64, (m_max + 63) / 64, items), dim3(256), 0, s, tab, hdr,
+                     cls);
+}
+
 void launch_analysis(int cls, int grid, const InstDesc* tab, BatchHdr* hdr, hipStream_t s) {
-  if (grid <= 0) return;
+  if (grid <= 0 || cls == kBigClass) return;  // the m > 128 class runs launch_big_analysis
 #define LETKF_LAUNCH_ANA(K) hipLaunchKernelGGL(K, dim3(grid), dim3(256), 0, s, tab, hdr, cls)
   LETKF_ANA_KERNEL(cls, LETKF_LAUNCH_ANA);
 #undef LETKF_LAUNCH_ANA
 }
 
 int analysis_blocks_per_cu(int cls) {
+  if (cls == kBigClass) return 1;
   int n = 0;
   hipError_t e = hipSuccess;
 #define LETKF_OCC(K) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, K, 256, 0)

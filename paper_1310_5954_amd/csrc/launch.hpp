@@ -23,5 +23,9 @@ void launch_pistons(int cls, int domain_items, const InstDesc* tab, BatchHdr* hd
 void launch_analysis(int cls, int grid, const InstDesc* tab, BatchHdr* hdr, hipStream_t s);
 // Analysis workgroups of the class one CU holds at once (LDS and registers).
 int analysis_blocks_per_cu(int cls);
+// The analysis of the m > 128 class (FP64): a fixed sequence of launches over
+// the domains' scratch (rows_max: most state rows of a domain, m_max: most
+// members of an instance in the batch).
+void launch_big_analysis(int items, int rows_max, int m_max, const InstDesc* tab, BatchHdr* hdr, hipStream_t s);
 
 }  // namespace letkf

@@ -36,7 +36,10 @@ int validate(const letkf_dims* dims, const letkf_model* model, const letkf_domai
              int precision, uint32_t flags, Problem& P) {
   if (!dims || !model || !map) return fail(LETKF_EINVAL, "null dims/model/map");
   if (dims->n_act < 1 || dims->n_sub < 1) return fail(LETKF_EINVAL, "n_act and n_sub must be >= 1");
-  if (dims->m < 2 || dims->m > 128) return fail(LETKF_EINVAL, "m must be in [2, 128]");
+  if (dims->m < 2 || dims->m > 256) return fail(LETKF_EINVAL, "m must be in [2, 256]");
+  if (dims->m > 128 && precision != LETKF_FP64) return fail(LETKF_EINVAL, "m > 128 needs LETKF_FP64");
+  if (dims->m > 128 && (flags & LETKF_FLAG_PISTONS))
+    return fail(LETKF_EINVAL, "LETKF_FLAG_PISTONS needs m <= 128");
   if (precision != LETKF_FP64 && precision != LETKF_FP32 && precision != LETKF_BF16)
     return fail(LETKF_EINVAL, "unknown precision");
   if (flags & ~(LETKF_FLAG_DEBUG | LETKF_FLAG_PISTONS | LETKF_FLAG_GRAPH)) return fail(LETKF_EINVAL, "unknown flags");
@@ -162,6 +165,14 @@ Layout make_layout(const Problem& P) {
     L.pist_c = take((size_t)P.n_dom * 2 * m * 8);
   } else {
     L.pist_r = L.pist_c = 0;
+  }
+  L.bigA = L.bigB = L.bigv = L.bigf = 0;
+  if (padded_members(P.m) > 128) {
+    const size_t mm = 256 * 256;
+    L.bigA = take((size_t)P.n_dom * mm * 8);
+    L.bigB = take((size_t)P.n_dom * mm * 8);
+    L.bigv = take((size_t)P.n_dom * 5 * 256 * 8);
+    L.bigf = take((size_t)P.n_dom * 4 * 4);
   }
   if (P.flags & LETKF_FLAG_DEBUG) {
     L.dbg = take((size_t)P.n_dom * (2 * m * m + m + 8) * 8);
@@ -406,6 +417,12 @@ int upload_instance(const Problem& P, const Layout& L, char* ws, const double* X
     D.pist_r = (double*)(ws + L.pist_r);
     D.pist_c = (double*)(ws + L.pist_c);
   }
+  if (L.bigA) {
+    D.bigA = (double*)(ws + L.bigA);
+    D.bigB = (double*)(ws + L.bigB);
+    D.bigv = (double*)(ws + L.bigv);
+    D.bigf = (int32_t*)(ws + L.bigf);
+  }
   D.dbg = L.dbg ? (double*)(ws + L.dbg) : nullptr;
   D.dbg_sweeps = L.dbg_sweeps ? (int32_t*)(ws + L.dbg_sweeps) : nullptr;
   D.st = (InstState*)(ws + L.state);
@@ -507,6 +524,15 @@ static int mark(letkf_handle* h, int k, hipStream_t s) {
   return LETKF_OK;
 }
 static BatchHdr* dev_hdr(letkf_handle* h) { return (BatchHdr*)(h->ws + h->L.hdr); }
+
+// The domain analysis of the plain path: the persistent kernel with the
+// tuned grid, or the launch sequence of the m > 128 class.
+static void launch_domain_analysis(letkf_handle* h, hipStream_t s) {
+  if (h->cls == letkf::kBigClass)
+    letkf::launch_big_analysis(h->P.n_dom, h->max_rows, h->P.m, dev_desc(h), dev_hdr(h), s);
+  else
+    letkf::launch_analysis(h->cls, h->ana_grid, dev_desc(h), dev_hdr(h), s);
+}
 
 namespace letkf {
 
@@ -643,6 +669,8 @@ int letkf_create(const letkf_dims* dims, const letkf_model* model, const letkf_d
     if (hipDeviceGetAttribute(&num_cu, hipDeviceAttributeMultiprocessorCount, h->device) != hipSuccess || num_cu < 1)
       rc = fail(LETKF_EDEVICE, "hipDeviceGetAttribute");
     h->ana_grid = std::min(h->P.n_dom, analysis_blocks_per_cu(h->cls) * num_cu);
+    for (int l = 0; l < h->P.n_dom; ++l)
+      h->max_rows = std::max(h->max_rows, 2 * (h->P.est_ptr[l + 1] - h->P.est_ptr[l]));
   }
   if (!rc && hipHostMalloc((void**)&h->h_y, sizeof(double) * h->P.p()) != hipSuccess) rc = fail(LETKF_EDEVICE, "hipHostMalloc");
   if (!rc && hipHostMalloc((void**)&h->h_out, sizeof(double) * h->P.n_act) != hipSuccess) rc = fail(LETKF_EDEVICE, "hipHostMalloc");
@@ -699,7 +727,7 @@ int letkf_analyse(letkf_handle* h, const double* y, int y_on_device, double* mea
   if ((rc = mark(h, 0, s))) return rc;
   launch_slopes(h->cls, h->P.p(), dev_desc(h), dev_hdr(h), s);
   if ((rc = mark(h, 1, s))) return rc;
-  launch_analysis(h->cls, h->ana_grid, dev_desc(h), dev_hdr(h), s);
+  launch_domain_analysis(h, s);
   if (h->P.flags & LETKF_FLAG_PISTONS) launch_pistons(h->cls, h->P.n_dom, dev_desc(h), dev_hdr(h), s);
   if ((rc = mark(h, 2, s))) return rc;
   launch_rows(h->cls, 0, h->P.n_act, dev_desc(h), dev_hdr(h), s);
@@ -725,7 +753,7 @@ int letkf_forecast(letkf_handle* h, void* stream) {
 // state advance), all reading the frame's state from the device.
 static void launch_frame(letkf_handle* h, hipStream_t s) {
   launch_slopes(h->cls, h->P.p(), dev_desc(h), dev_hdr(h), s);
-  launch_analysis(h->cls, h->ana_grid, dev_desc(h), dev_hdr(h), s);
+  launch_domain_analysis(h, s);
   if (h->P.flags & LETKF_FLAG_PISTONS) launch_pistons(h->cls, h->P.n_dom, dev_desc(h), dev_hdr(h), s);
   launch_rows(h->cls, 2, h->P.n_act, dev_desc(h), dev_hdr(h), s);
 }
@@ -765,7 +793,7 @@ int letkf_step(letkf_handle* h, const double* y, int y_on_device, double* pred_o
   if ((rc = mark(h, 0, s))) return rc;
   launch_slopes(h->cls, h->P.p(), dev_desc(h), dev_hdr(h), s);
   if ((rc = mark(h, 1, s))) return rc;
-  launch_analysis(h->cls, h->ana_grid, dev_desc(h), dev_hdr(h), s);
+  launch_domain_analysis(h, s);
   if (h->P.flags & LETKF_FLAG_PISTONS) launch_pistons(h->cls, h->P.n_dom, dev_desc(h), dev_hdr(h), s);
   if ((rc = mark(h, 2, s))) return rc;
   launch_rows(h->cls, 2, h->P.n_act, dev_desc(h), dev_hdr(h), s);
@@ -876,6 +904,7 @@ int letkf_kernel_times(letkf_handle* h, int enable, double* ms_out, uint64_t* fr
 int letkf_autotune(letkf_handle* h, int32_t reps, letkf_tuning* out, void* stream) {
   int rc = check_plain(h);
   if (rc) return rc;
+  if (h->cls == kBigClass) return fail(LETKF_ESTATE, "the launch sequence of m > 128 has no tunable shape");
   int num_cu = 0;
   LETKF_HIP(hipDeviceGetAttribute(&num_cu, hipDeviceAttributeMultiprocessorCount, h->device));
   int grid = h->ana_grid;
@@ -893,6 +922,7 @@ int letkf_autotune(letkf_handle* h, int32_t reps, letkf_tuning* out, void* strea
 int letkf_set_tuning(letkf_handle* h, const letkf_tuning* t, void* stream) {
   int rc = check_plain(h);
   if (rc) return rc;
+  if (h->cls == kBigClass) return fail(LETKF_ESTATE, "the launch sequence of m > 128 has no tunable shape");
   if (!t || t->grid < 1 || t->grid > 65535 || t->order < LETKF_ORDER_MAP || t->order > LETKF_ORDER_XCD)
     return fail(LETKF_EINVAL, "tuning: grid must be in [1, 65535] and order one of LETKF_ORDER_*");
   if ((rc = upload_order(h, t->order, (hipStream_t)stream))) return rc;

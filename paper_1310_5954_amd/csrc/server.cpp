@@ -443,6 +443,7 @@ int letkf_server_add(letkf_server* s, const letkf_dims* dims, const letkf_model*
   auto* h = new letkf_handle();
   int rc = validate(dims, model, map, precision, flags, h->P);
   if (rc) { delete h; return rc; }
+  if (h->P.m > 128) { delete h; return fail(LETKF_EINVAL, "m > 128 runs on the plain path only"); }
   if (!X0) { delete h; return fail(LETKF_EINVAL, "null X0"); }
   for (size_t i = 0; i < 2 * (size_t)h->P.n_act * h->P.m; ++i)
     if (!std::isfinite(X0[i])) { delete h; return fail(LETKF_ENUMERIC, "non-finite X0"); }
@@ -588,7 +589,7 @@ int letkf_server_autotune(letkf_server* s, int32_t reps, letkf_tuning* out) {
   if (s->pending > 0 || s->inflight > 0) return fail(LETKF_EAGAIN, "server has frames queued or in flight");
   const int slot = 0;
   hipStream_t st = s->stream[slot];
-  for (int c = 0; c < kNumClasses; ++c) {
+  for (int c = 0; c < kBigClass; ++c) {  // the 12 tunable classes (no m > 128 instance is admitted)
     if (out) out[c] = letkf_tuning{};
     BatchHdr& H = *s->h_hdr[slot];
     std::memset(&H, 0, sizeof(H));
@@ -628,7 +629,7 @@ int letkf_server_autotune(letkf_server* s, int32_t reps, letkf_tuning* out) {
 
 int letkf_server_set_tuning(letkf_server* s, int32_t cls, const letkf_tuning* t) {
   if (!s) return fail(LETKF_EINVAL, "null server");
-  if (cls < 0 || cls >= kNumClasses) return fail(LETKF_EINVAL, "class must be in [0, 12)");
+  if (cls < 0 || cls >= kBigClass) return fail(LETKF_EINVAL, "class must be in [0, 12)");
   if (!t || t->grid < 1 || t->grid > 65535 || t->order < LETKF_ORDER_MAP || t->order > LETKF_ORDER_XCD)
     return fail(LETKF_EINVAL, "tuning: grid must be in [1, 65535] and order one of LETKF_ORDER_*");
   std::unique_lock<std::mutex> lk(s->mu);

@@ -50,7 +50,7 @@ def test_workspace_size_grows_with_precision_and_debug():
 
 @pytest.mark.parametrize("over,needle", [
     (dict(m=1), "m must be"),
-    (dict(m=129), "m must be"),
+    (dict(m=257), "m must be"),
     (dict(n_act=0), "n_act"),
     (dict(sigma_v=-1.0), "sigma_v"),
     (dict(inflation=0.0), "inflation"),
@@ -61,6 +61,24 @@ def test_invalid_dims_and_model_rejected(over, needle):
     rc = L.lib().letkf_workspace_size(C.byref(pr.dims), C.byref(pr.model), C.byref(pr.map), L.FP64, 0, C.byref(b))
     assert rc == L.EINVAL
     assert needle in L.lib().letkf_last_error().decode()
+
+
+def test_large_ensembles_fp64_only():
+    """m in 129..256 is accepted in FP64 only (the multi-launch analysis), with
+    scratch for two 256 x 256 FP64 matrices per domain, and without pistons."""
+    b = C.c_size_t()
+    pr128, pr200 = _problem(m=128), _problem(m=200)
+    args = lambda pr: (C.byref(pr.dims), C.byref(pr.model), C.byref(pr.map))
+    assert L.lib().letkf_workspace_size(*args(pr128), L.FP64, 0, C.byref(b)) == L.OK
+    s128 = b.value
+    assert L.lib().letkf_workspace_size(*args(pr200), L.FP64, 0, C.byref(b)) == L.OK
+    n_dom = pr200.map.n_domains
+    assert b.value - s128 >= n_dom * 2 * 256 * 256 * 8
+    for prec in (L.FP32, L.BF16):
+        assert L.lib().letkf_workspace_size(*args(pr200), prec, 0, C.byref(b)) == L.EINVAL
+        assert "needs LETKF_FP64" in L.lib().letkf_last_error().decode()
+    assert L.lib().letkf_workspace_size(*args(pr200), L.FP64, L.FLAG_PISTONS, C.byref(b)) == L.EINVAL
+    assert "m <= 128" in L.lib().letkf_last_error().decode()
 
 
 def test_invalid_map_rejected():

@@ -366,3 +366,51 @@ def test_autotune_keeps_state_and_frames():
     ref.close()
     f.close()
 
+
+@pytest.mark.parametrize("m", [129, 197, 256])
+def test_large_ensembles_fp64(m):
+    """m in 129..256 runs the multi-launch analysis (tiled C, Cholesky held in
+    L2, one-sided Jacobi over 16-column blocks in tournament rounds across
+    workgroups, tiled T and update).  On the 15x15 pupil a domain has at most
+    72 observations, so A keeps an eigenvalue (m-1)/rho of multiplicity
+    > m - 73: a large degenerate cluster."""
+    case = build_case(1, m=m)
+    X, k = oracle_spin_up(case, 1)
+    _check_step(case, X, k, FP64, debug=True)
+
+
+def test_global_etkf_m197_fp64():
+    """The global ETKF at the m = 197 of Sec. 3.1: one domain over the 32x32
+    pupil (877 actuators, 812 subapertures), FP64."""
+    cfg = dict(build_case(2).cfg)
+    cfg.update(lenslets=32)
+    case = build_case(cfg, m=197, global_map=True)
+    assert case.n_act == 877 and case.n_sub == 812
+    _check_step(case, case.X0, 0, FP64, debug=True)
+
+
+def test_large_ensemble_steps_and_graph_replay():
+    """letkf_step and its captured graph on the m > 128 path: equal bit for
+    bit over 3 frames, and each frame within 1e-10 of the oracle."""
+    case = build_case(1, m=150)
+    pr = Problem.from_case(case)
+    D = sparse_D(case)
+    eager = Filter(pr, case.X0, precision=FP64)
+    graph = Filter(pr, case.X0, precision=FP64, graph=True)
+    for k in range(3):
+        Xin, _ = eager.get_state()
+        y = case.slopes(k)
+        a, b = eager.step(y, pred=True), graph.step(y, pred=True)
+        assert np.array_equal(a, b), k
+        Xe, _ = eager.get_state()
+        Xg, _ = graph.get_state()
+        assert np.array_equal(Xe, Xg), k
+        Xa_o = oracle.analysis(Xin, y, D, case.dmap, case.r_inv)
+        Xf_o = oracle.forecast(Xa_o, case.a1, case.a2, case.sigma_v, case.philox_seed, k)
+        assert rel(Xe, Xf_o) < 1e-10, (k, rel(Xe, Xf_o))
+    assert eager.unconverged() == 0
+    with pytest.raises(LetkfError):
+        eager.autotune()
+    eager.close()
+    graph.close()
+
