@@ -163,6 +163,51 @@ def run_global(K, W, NL, with_cpu: bool):
     return out
 
 
+K_BAND = (0.5 / 2.2) ** 2   # phase variance at 2.2 um from the 500 nm of r0 (phase scales as 1 / wavelength)
+
+
+def run_closed_loop(ms, frames: int, burn_in: int) -> dict:
+    """The closed loop of Sec. 3 (workload.closed_loop) on a 32x32 pupil
+    (877 actuators) with 5x5-actuator domains (stride 3, halo 2, taper),
+    the plain FP64 filter for each ensemble size in `ms`; coherent energy
+    against m, with the open loop and the truth-fed controller's floor."""
+    from paper_1310_5954_amd import FP64, Filter, Problem, build_id
+    from workload.closed_loop import ClosedLoop
+    from workload.configs import build_case
+    rows = []
+    floor = None
+    for m in ms:
+        cfg = dict(build_case(2).cfg)
+        cfg.update(lenslets=32, frames=frames + 2)
+        case = build_case(cfg, m=m)
+        cl = ClosedLoop(case)
+        if floor is None:
+            floor = cl.run(cl.perfect_step(), frames, burn_in)
+        f = Filter(Problem.from_case(case), case.X0, precision=FP64, device="cuda:0")
+
+        def step(y):
+            f.step(y, pred=False)
+            return f.last_means()
+        t0 = time.perf_counter()
+        r = cl.run(step, frames, burn_in)
+        dt = time.perf_counter() - t0
+        f.close()
+        rows.append(dict(m=m, coherent_energy=r["coherent_energy"], residual_var_rad2=round(r["residual_var"], 4),
+                         coherent_energy_2200nm=round(float(np.exp(-r["residual_var"] * K_BAND)), 5),
+                         loop_frames_per_s=round(frames / dt, 1)))
+        print(f"[bench] closed loop m={m}: residual {r['residual_var']:.3f} rad^2, E {r['coherent_energy']:.3e}",
+              file=sys.stderr, flush=True)
+    return dict(closed_loop=dict(workload=f"32x32 circular SH pupil, {case.n_act} actuators, {case.dmap.n_domains} "
+                                          "5x5-actuator domains, FP64 plain path, 2-frame delay, DM coupling 0.3",
+                                 frames=frames, burn_in=burn_in,
+                                 open_loop_var_rad2=round(r["open_loop_var"], 3),
+                                 truth_fed_floor_var_rad2=round(floor["residual_var"], 4),
+                                 truth_fed_floor_coherent_energy=floor["coherent_energy"],
+                                 truth_fed_floor_coherent_energy_2200nm=round(float(np.exp(-floor["residual_var"] * K_BAND)), 5),
+                                 note="phases are at the 500 nm of r0; *_2200nm scales the variance by (0.5/2.2)^2",
+                                 by_m=rows), library=build_id())
+
+
 def cpu_baseline(case, seconds: float = 15.0):
     """The FP64 oracle on the host, one thread, on the first frames of the
     same workload until `seconds` have passed (at least two frames)."""
@@ -486,6 +531,8 @@ def main() -> int:
                     help="skip autotuning the analysis launch shapes (default grid and order)")
     ap.add_argument("--server-graphs", type=int, default=0, choices=[0, 1],
                     help="1: server batches replayed from captured hipGraphs; 0: launched one by one")
+    ap.add_argument("--closed-loop", action="store_true",
+                    help="only the closed-loop coherent energy against m (32x32 pupil, FP64), 300 frames each")
     ap.add_argument("--phases", action="store_true",
                     help="only report per-phase cycles and bytes of the FP64 analysis (debug stamps), one frame")
     ap.add_argument("--copy-ref", action="store_true",
@@ -511,6 +558,9 @@ def main() -> int:
     PISTONS = args.pistons
     TUNE = not args.no_tune
     GRAPHS = bool(args.server_graphs)
+    if args.closed_loop:
+        print(json.dumps(run_closed_loop((8, 16, 32, 64, 128), 300, 100)), flush=True)
+        return 0
     if args.workload == 32:
         print(json.dumps(run_global(args.steps, args.warmup, args.latency_frames, not args.no_cpu_baseline)),
               flush=True)

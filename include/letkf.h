@@ -189,6 +189,14 @@ int letkf_debug_domain(letkf_handle* h, int32_t domain, double* C_out, double* l
  * (0 when all converged); waits for the stream. */
 int letkf_unconverged_domains(letkf_handle* h, int32_t* count, void* stream);
 
+/* The means the last plain-path frame wrote (host [n_act] each, either may
+ * be NULL): amean_out the analysis mean of phi_k (letkf_analyse or
+ * letkf_step), pmean_out the prediction mean of phi_{k+1} (letkf_forecast or
+ * letkf_step).  A two-frame-delay controller extrapolates with both, e.g.
+ * phi_{k+2|k} = a1 pmean + a2 amean (eq. (1) applied to the means).  Waits
+ * for the stream. */
+int letkf_last_means(letkf_handle* h, double* amean_out, double* pmean_out, void* stream);
+
 /* Kernel timing of the plain path: while enabled, analyse/forecast/step
  * record HIP events on their stream around each kernel.  enable = 1 clears
  * and starts, 0 stops.  ms_out (nullable, [3]) receives the accumulated

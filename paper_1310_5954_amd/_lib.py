@@ -80,6 +80,7 @@ def _sig(lib):
     lib.letkf_autotune.argtypes = [P, C.c_int32, C.POINTER(Tuning), P]
     lib.letkf_server_autotune.argtypes = [P, C.c_int32, C.POINTER(Tuning)]
     lib.letkf_set_tuning.argtypes = [P, C.POINTER(Tuning), P]
+    lib.letkf_last_means.argtypes = [P, pd, pd, P]
     lib.letkf_server_set_tuning.argtypes = [P, C.c_int32, C.POINTER(Tuning)]
     lib.letkf_server_create.argtypes = [P, C.c_size_t, C.c_int32, C.c_uint32, C.POINTER(P)]
     lib.letkf_server_add.argtypes = [P, C.POINTER(Dims), C.POINTER(Model), C.POINTER(DomainMapC), C.c_int,
@@ -102,7 +103,8 @@ def _sig(lib):
     for name in ("letkf_workspace_size", "letkf_create", "letkf_destroy", "letkf_analyse", "letkf_forecast",
                  "letkf_step", "letkf_get_state", "letkf_set_state", "letkf_debug_domain",
                  "letkf_unconverged_domains", "letkf_kernel_times", "letkf_sweep_stats", "letkf_autotune",
-                 "letkf_server_autotune", "letkf_set_tuning", "letkf_server_set_tuning", "letkf_server_create", "letkf_server_add", "letkf_server_remove",
+                 "letkf_server_autotune", "letkf_set_tuning", "letkf_server_set_tuning", "letkf_last_means",
+                 "letkf_server_create", "letkf_server_add", "letkf_server_remove",
                  "letkf_submit_frame", "letkf_submit_frame_device", "letkf_server_drain", "letkf_server_set_window", "letkf_server_stats", "letkf_server_destroy"):
         getattr(lib, name).restype = C.c_int
 

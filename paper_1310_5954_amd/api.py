@@ -186,6 +186,14 @@ class Filter:
                     "letkf_autotune")
         return t.as_dict()
 
+    def last_means(self):
+        """(analysis mean of phi_k, prediction mean of phi_{k+1}) of the last frame."""
+        a, p = np.empty(self.problem.n_act), np.empty(self.problem.n_act)
+        with torch.cuda.device(self.device):
+            L.check(L.lib().letkf_last_means(self.handle, a.ctypes.data_as(_pd), p.ctypes.data_as(_pd),
+                                             _stream(self.device)), "letkf_last_means")
+        return a, p
+
     def set_tuning(self, grid: int, order: int = L.ORDER_COST):
         """Applies a launch shape chosen earlier (letkf_set_tuning; order: L.ORDER_*)."""
         t = L.Tuning(grid=int(grid), order=int(order))

@@ -869,6 +869,20 @@ int letkf_debug_domain(letkf_handle* h, int32_t domain, double* C_out, double* l
   return LETKF_OK;
 }
 
+int letkf_last_means(letkf_handle* h, double* amean_out, double* pmean_out, void* stream) {
+  int rc = check_plain(h);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  const size_t bytes = sizeof(double) * h->P.n_act;
+  if (amean_out) LETKF_HIP(hipMemcpyAsync(h->h_out, h->ws + h->L.amean, bytes, hipMemcpyDeviceToHost, s));
+  LETKF_HIP(hipStreamSynchronize(s));
+  if (amean_out) std::memcpy(amean_out, h->h_out, bytes);
+  if (pmean_out) LETKF_HIP(hipMemcpyAsync(h->h_out, h->ws + h->L.pmean, bytes, hipMemcpyDeviceToHost, s));
+  LETKF_HIP(hipStreamSynchronize(s));
+  if (pmean_out) std::memcpy(pmean_out, h->h_out, bytes);
+  return LETKF_OK;
+}
+
 int letkf_unconverged_domains(letkf_handle* h, int32_t* count, void* stream) {
   hipStream_t s;
   int rc = access_stream(h, stream, &s);

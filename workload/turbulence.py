@@ -73,11 +73,16 @@ class FrozenFlow:
         return float(sp) * t
 
     def phase(self, t: float) -> np.ndarray:
-        out = np.zeros(len(self.act_xy))
+        return self.phase_at(self.act_xy, t)
+
+    def phase_at(self, xy: np.ndarray, t: float) -> np.ndarray:
+        """The same screens read at other metric points (inside the pupil)."""
+        xy = np.asarray(xy, float)
+        out = np.zeros(len(xy))
         for L in self.layers:
             s = self.position(L, t)
             dx, dy = s * np.cos(L["angle"]), s * np.sin(L["angle"])
-            out += sample_bilinear(L["screen"], self.delta, self.act_xy[:, 0] + dx, self.act_xy[:, 1] + dy)
+            out += sample_bilinear(L["screen"], self.delta, xy[:, 0] + dx, xy[:, 1] + dy)
         return out
 
 
