@@ -1308,34 +1308,39 @@ __device__ __forceinline__ double* big_dbg(const BigDom& D) {
   return D.I->dbg ? D.I->dbg + (size_t)D.l * (2 * m * m + m + 8) : nullptr;
 }
 
-__global__ __launch_bounds__(256) void k_big_rhs(const InstDesc* __restrict__ tab, const BatchHdr* __restrict__ hdr,
-                                                 int cls) {
+// 1024 threads: member j = t % 256 of observation quarter t / 256, summed in LDS.
+__global__ __launch_bounds__(1024) void k_big_rhs(const InstDesc* __restrict__ tab, const BatchHdr* __restrict__ hdr,
+                                                  int cls) {
+  __shared__ double part_sum[4][kBigM];
   const ClassBatch& cb = hdr->cls[cls];
   if ((int)blockIdx.x >= cb.dom_off[cb.n]) return;
   const BigDom D = big_dom(tab, cb, blockIdx.x);
   const InstDesc& I = *D.I;
-  const int m = I.m, j = threadIdx.x, nobs = 2 * D.s;
+  const int m = I.m, j = threadIdx.x % kBigM, part = threadIdx.x / kBigM, nobs = 2 * D.s;
   const double* Yp = (const double*)I.Yp;
-  if (j == 0) {
+  if (threadIdx.x == 0) {
     D.f[0] = 0;
     D.f[1] = 0;
     D.f[2] = 0;
   }
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  double acc[2] = {0.0, 0.0};
   if (j < m) {
-    int q = 0;
-    for (; q + 4 <= nobs; q += 4)
+    int q = part;
+    for (; q + 4 < nobs; q += 8)
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int o = 2 * D.obs_off + q + u, row = I.obs_row[o];
+      for (int u = 0; u < 2; ++u) {
+        const int o = 2 * D.obs_off + q + 4 * u, row = I.obs_row[o];
         acc[u] = fma(I.obs_r[o] * I.d[row], Yp[(size_t)row * m + j], acc[u]);
       }
-    for (; q < nobs; ++q) {
+    for (; q < nobs; q += 4) {
       const int o = 2 * D.obs_off + q, row = I.obs_row[o];
       acc[0] = fma(I.obs_r[o] * I.d[row], Yp[(size_t)row * m + j], acc[0]);
     }
   }
-  D.v[j] = j < m ? (acc[0] + acc[1]) + (acc[2] + acc[3]) : 0.0;
+  part_sum[part][j] = acc[0] + acc[1];
+  __syncthreads();
+  if (part == 0)
+    D.v[j] = j < m ? (part_sum[0][j] + part_sum[1][j]) + (part_sum[2][j] + part_sum[3][j]) : 0.0;
 }
 
 // grid (10, items): the upper tiles (ti <= tj) of the 4 x 4 grid of 64 x 64
@@ -1407,17 +1412,18 @@ __global__ __launch_bounds__(256) void k_big_gram(const InstDesc* __restrict__ t
     }
 }
 
-// Thread r owns row r of L (column-major B): per column k it reads the pivot
-// column from LDS, writes its entry of column k and updates its entries of the
-// trailing columns (coalesced across threads for each column).
-__global__ __launch_bounds__(256) void k_big_chol(const InstDesc* __restrict__ tab, const BatchHdr* __restrict__ hdr,
-                                                  int cls) {
+// 1024 threads: thread t owns row r = t % 256 of L (column-major B) and every
+// fourth trailing column from t / 256 on: per column k it reads the pivot
+// column from LDS, writes its entry of column k and updates its entries of
+// the trailing columns (coalesced across threads for each column).
+__global__ __launch_bounds__(1024) void k_big_chol(const InstDesc* __restrict__ tab, const BatchHdr* __restrict__ hdr,
+                                                   int cls) {
   __shared__ double pc[kBigM];
   const ClassBatch& cb = hdr->cls[cls];
   if ((int)blockIdx.x >= cb.dom_off[cb.n]) return;
   const BigDom D = big_dom(tab, cb, blockIdx.x);
-  const int m = D.I->m, r = threadIdx.x;
-  for (int c = 0; c < kBigM; ++c) {
+  const int m = D.I->m, r = threadIdx.x % kBigM, part = threadIdx.x / kBigM;
+  for (int c = part; c < kBigM; c += 4) {
     double v;
     if (c < m) v = (r >= c && r < m) ? D.A[(size_t)c * kBigM + r] : 0.0;  // A symmetric
     else v = r == c ? 1.0 : 0.0;
@@ -1425,16 +1431,16 @@ __global__ __launch_bounds__(256) void k_big_chol(const InstDesc* __restrict__ t
   }
   __syncthreads();
   for (int k = 0; k < m; ++k) {
-    if (r >= k && r < m) pc[r] = D.B[(size_t)k * kBigM + r];
+    if (part == 0 && r >= k && r < m) pc[r] = D.B[(size_t)k * kBigM + r];
     __syncthreads();
     const double sk = sqrt(pc[k]);
     const double inv = 1.0 / sk;
     if (r >= k && r < m) {
       const double lr = r == k ? sk : pc[r] * inv;
-      D.B[(size_t)k * kBigM + r] = lr;
+      if (part == 0) D.B[(size_t)k * kBigM + r] = lr;
       if (r > k) {
 #pragma unroll 4
-        for (int c = k + 1; c <= r; ++c) D.B[(size_t)c * kBigM + r] -= lr * (pc[c] * inv);
+        for (int c = k + 1 + part; c <= r; c += 4) D.B[(size_t)c * kBigM + r] -= lr * (pc[c] * inv);
       }
     }
     __syncthreads();
@@ -1817,9 +1823,9 @@ void launch_rows(int cls, int mode, int rows, const InstDesc* tab, BatchHdr* hdr
 void launch_big_analysis(int items, int rows_max, int m_max, const InstDesc* tab, BatchHdr* hdr, hipStream_t s) {
   if (items <= 0) return;
   const int cls = kBigClass, nb = 2 * ((m_max + 31) / 32);
-  hipLaunchKernelGGL(k_big_rhs, dim3(items), dim3(256), 0, s, tab, hdr, cls);
+  hipLaunchKernelGGL(k_big_rhs, dim3(items), dim3(1024), 0, s, tab, hdr, cls);
   hipLaunchKernelGGL(k_big_gram, dim3(10, items), dim3(256), 0, s, tab, hdr, cls);
-  hipLaunchKernelGGL(k_big_chol, dim3(items), dim3(256), 0, s, tab, hdr, cls);
+  hipLaunchKernelGGL(k_big_chol, dim3(items), dim3(1024), 0, s, tab, hdr, cls);
   for (int sw = 0; sw < kBigMaxSweeps; ++sw) {
     for (int r = 0; r < nb - 1; ++r)
       hipLaunchKernelGGL(k_big_round, dim3(nb / 2, items), dim3(256), 0, s, tab, hdr, cls, nb, r);
