@@ -1526,7 +1526,52 @@ __global__ __launch_bounds__(256) void k_big_round(const InstDesc* __restrict__ 
       step(base + i, base + (i ^ k));
     }
   }
-  for (int st = 0; st < 16; ++st) step(p, 16 + ((p + st) & 15));
+  // the 256 pairs between the blocks: slot p keeps block a's column p (and its
+  // norm) in registers and meets block b's columns p, p + 1, ... (mod 16)
+  {
+    double xi[16];
+#pragma unroll
+    for (int t = 0; t < 16; ++t) xi[t] = col[p * kBigLd + sub + 16 * t];
+    double al = nrm[p];
+    bool moved = false;
+    for (int st = 0; st < 16; ++st) {
+      const int cj = 16 + ((p + st) & 15);
+      double xj[16];
+#pragma unroll
+      for (int t = 0; t < 16; ++t) xj[t] = col[cj * kBigLd + sub + 16 * t];
+      double g0 = 0.0, g1 = 0.0;
+#pragma unroll
+      for (int t = 0; t < 16; t += 2) {
+        g0 = fma(xi[t], xj[t], g0);
+        g1 = fma(xi[t + 1], xj[t + 1], g1);
+      }
+      const double gsum = group_sum<16>(g0 + g1);
+      const double be = nrm[cj];
+      if (gsum * gsum > tol2 * (al * be)) {
+        const double dd = be - al, g2 = 2.0 * gsum;
+        const double q2 = fma(dd, dd, g2 * g2);
+        const double den = fma(q2, __builtin_amdgcn_rsq(q2), fabs(dd));
+        const double t = copysign(1.0, dd) * g2 * __builtin_amdgcn_rcp(den);
+        const double c = rsqrt_1_2(fma(t, t, 1.0));
+        const double sn = c * t;
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+          const double x = xi[u];
+          xi[u] = c * x - sn * xj[u];
+          col[cj * kBigLd + sub + 16 * u] = sn * x + c * xj[u];
+        }
+        al -= t * gsum;
+        if (sub == 0) nrm[cj] = be + t * gsum;
+        moved = true;
+      }
+      __syncthreads();
+    }
+    if (moved) {
+      rotated = true;
+#pragma unroll
+      for (int t = 0; t < 16; ++t) col[p * kBigLd + sub + 16 * t] = xi[t];
+    }
+  }
   if (__syncthreads_or(rotated)) {
     for (int idx = tid; idx < 32 * kBigM; idx += 256) {
       const int k = idx / kBigM, r = idx % kBigM;
