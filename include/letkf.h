@@ -47,8 +47,11 @@
  *     variable (rows 0..n_act-1 = phi_k, n_act..n-1 = phi_{k-1}), column =
  *     member.
  *   - stream: a hipStream_t passed as void* (NULL = the default stream).
- *   - Limits: 2 <= m <= 128; n_act, n_sub >= 1; every domain has >= 1
- *     actuator.  Violations return LETKF_EINVAL before any device work.
+ *   - Limits: 2 <= m <= 256 (above 128: LETKF_FP64 only, no
+ *     LETKF_FLAG_PISTONS, plain path only; the analysis is then a sequence of
+ *     launches over per-domain scratch, the global ETKF of Sec. 3.1);
+ *     n_act, n_sub >= 1; every domain has >= 1 actuator.  Violations return
+ *     LETKF_EINVAL before any device work.
  *   - A handle is used by one thread at a time.
  */
 #ifndef LETKF_H
@@ -106,7 +109,7 @@ typedef struct letkf_server letkf_server;
 typedef struct letkf_dims {
   int32_t n_act;  /* valid actuators (state n = 2 n_act) */
   int32_t n_sub;  /* valid subapertures (slopes p = 2 n_sub) */
-  int32_t m;      /* ensemble members, 2..128 */
+  int32_t m;      /* ensemble members, 2..256 (above 128: FP64 only) */
 } letkf_dims;
 
 typedef struct letkf_model {
