@@ -237,6 +237,7 @@ def cpu_baseline(case, seconds: float = 15.0):
 PISTONS = False  # set from --pistons
 TUNE = True      # autotune the analysis launch of every filter / server class first (--no-tune: defaults)
 GRAPHS = False   # server batches replayed from captured graphs (--server-graphs 1); measured slower here
+MAX_BATCH = 64   # frames per server batch (--max-batch)
 
 
 def run_plain(case, prec, K, W, NL, ys, tune=True):
@@ -374,7 +375,7 @@ def run_serving(case, prec, B, K, W, ys, depth=1):
             state["done"] += 1
             cv.notify_all()
 
-    srv = Server(budget, on_done=on_done, graphs=GRAPHS)
+    srv = Server(budget, on_done=on_done, graphs=GRAPHS, max_batch=MAX_BATCH)
     insts = [srv.add(pr, np.roll(case.X0, i, axis=1), prec, pistons=PISTONS) for i in range(B)]
     tuning = list(srv.autotune().values())[0] if TUNE else None
     torch.cuda.synchronize()
@@ -527,6 +528,7 @@ def main() -> int:
                     help="remove the differential pistons between domains before the merge (Sec. 3.2)")
     ap.add_argument("--serving-only", action="store_true",
                     help="skip the plain-path runs (for profiling the serving kernels); no roofline line")
+    ap.add_argument("--max-batch", type=int, default=64, help="server: most frames in one batch")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip autotuning the analysis launch shapes (default grid and order)")
     ap.add_argument("--server-graphs", type=int, default=0, choices=[0, 1],
@@ -554,10 +556,11 @@ def main() -> int:
         print(json.dumps(dict(copy_ref_bytes_read=nbytes, copy_ref_bytes_written=nbytes, dispatches=5)))
         return 0
 
-    global PISTONS, TUNE, GRAPHS
+    global PISTONS, TUNE, GRAPHS, MAX_BATCH
     PISTONS = args.pistons
     TUNE = not args.no_tune
     GRAPHS = bool(args.server_graphs)
+    MAX_BATCH = args.max_batch
     if args.closed_loop:
         print(json.dumps(run_closed_loop((8, 16, 32, 64, 128), 300, 100)), flush=True)
         return 0

@@ -39,27 +39,6 @@ __device__ __forceinline__ double philox_normal(uint64_t seed, uint64_t frame, u
   return sqrt(-2.0 * log(u1)) * cospi(2.0 * u2);
 }
 
-// Sum of v over the MP lanes of a member row (MP <= 64: one wavefront segment;
-// MP = 128: two wavefronts combined through LDS).  Every thread participates.
-template <int MP>
-__device__ __forceinline__ double row_sum(double v, double* red) {
-  constexpr int W = MP < 64 ? MP : 64;
-#pragma unroll
-  for (int off = W / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  if constexpr (MP > 64) {
-    const int t = threadIdx.x;
-    if ((t & 63) == 0) red[t >> 6] = v;
-    __syncthreads();
-    const int base = (t / MP) * (MP / 64);
-    double s = 0.0;
-#pragma unroll
-    for (int w = 0; w < MP / 64; ++w) s += red[base + w];
-    __syncthreads();
-    v = s;
-  }
-  return v;
-}
-
 // Cross-lane moves of a double with DPP (VALU, no LDS round trip).
 template <int CTRL>
 __device__ __forceinline__ double dpp_f64(double v) {
@@ -80,6 +59,29 @@ __device__ __forceinline__ double group_sum(double v) {
   if constexpr (G >= 8) v += dpp_f64<0x141>(v);  // row_half_mirror
   if constexpr (G >= 16) v += dpp_f64<0x140>(v); // row_mirror
   static_assert(G <= 16, "group_sum supports up to 16 lanes");
+  return v;
+}
+
+// Sum of v over the MP lanes of a member row (MP <= 64: one wavefront segment;
+// MP >= 128: wavefronts combined through LDS).  Every thread participates.
+// Within 16 lanes by DPP (group_sum), across 16-lane rows by lane shuffles.
+template <int MP>
+__device__ __forceinline__ double row_sum(double v, double* red) {
+  constexpr int W = MP < 64 ? MP : 64;
+  v = group_sum<(W < 16 ? W : 16)>(v);
+#pragma unroll
+  for (int off = 16; off < W; off <<= 1) v += __shfl_xor(v, off, 64);
+  if constexpr (MP > 64) {
+    const int t = threadIdx.x;
+    if ((t & 63) == 0) red[t >> 6] = v;
+    __syncthreads();
+    const int base = (t / MP) * (MP / 64);
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < MP / 64; ++w) s += red[base + w];
+    __syncthreads();
+    v = s;
+  }
   return v;
 }
 
