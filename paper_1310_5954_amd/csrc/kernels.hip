@@ -450,26 +450,36 @@ __device__ void gather_C_fp64_mfma(AnaSmem<M>& sm, const InstDesc& I, int obs_of
   double bpart = 0.0;
   const double* Yp = (const double*)I.Yp;
   const int nobs = 2 * s;
-  for (int q0 = 0; q0 < nobs; q0 += KCH) {
-    const int kc = min(KCH, nobs - q0);
-    if (tid < KCH) {
-      double r = 0.0, dd = 0.0;
-      if (tid < kc) {
-        r = I.obs_r[2 * obs_off + q0 + tid];
-        dd = I.d[I.obs_row[2 * obs_off + q0 + tid]];
+  // Thread (kk0 = tid / M, j = tid % M) stages observations kk0 + e NT / M of
+  // every chunk for member j.  The next chunk's rows are loaded into registers
+  // before the current chunk's MFMAs, so their latency overlaps the products.
+  constexpr int EPT = KCH * M / NT;
+  static_assert(KCH * M % NT == 0, "whole chunks per thread");
+  // M >= 64: a wavefront's lanes share kk0, so the observation's row, r and d are scalar loads
+  const int kk0 = M >= 64 ? __builtin_amdgcn_readfirstlane(tid / M) : tid / M, j = tid % M;
+  double yv[EPT], rv[EPT], dv[EPT];
+  auto fetch = [&](int q0) {
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      const int q = q0 + kk0 + e * (NT / M);
+      yv[e] = rv[e] = dv[e] = 0.0;
+      if (q < nobs && j < m) {
+        const int o = 2 * obs_off + q, row = I.obs_row[o];
+        rv[e] = I.obs_r[o];
+        dv[e] = I.d[row];
+        yv[e] = Yp[(size_t)row * m + j];
       }
-      sm.rc[tid] = sqrt(r);
-      sm.dc[tid] = r * dd;
+    }
+  };
+  fetch(0);
+  for (int q0 = 0; q0 < nobs; q0 += KCH) {
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      bpart = fma(rv[e] * dv[e], yv[e], bpart);
+      At[j * LDK + kk0 + e * (NT / M)] = sqrt(rv[e]) * yv[e];
     }
     __syncthreads();
-    for (int idx = tid; idx < KCH * M; idx += NT) {
-      const int kk = idx / M, j = idx % M;
-      double y = 0.0;
-      if (kk < kc && j < m) y = Yp[(size_t)I.obs_row[2 * obs_off + q0 + kk] * m + j];
-      bpart = fma(sm.dc[kk], y, bpart);
-      At[j * LDK + kk] = sm.rc[kk] * y;
-    }
-    __syncthreads();
+    if (q0 + KCH < nobs) fetch(q0 + KCH);
     if (wave_on) {
 #pragma unroll
       for (int ks = 0; ks < KCH / 4; ++ks) {
@@ -538,33 +548,46 @@ __device__ void gather_C_mfma(AnaSmem<M>& sm, const InstDesc& I, int obs_off, in
   constexpr int LDB = C::LDB;
   if constexpr (P == 1)
     for (int idx = tid; idx < M * LDB; idx += NT) sm.Bm[idx] = 0.0;
-  for (int q0 = 0; q0 < nobs; q0 += KCH) {
-    const int kc = min(KCH, nobs - q0);
-    if (tid < KCH) {
-      double r = 0.0, dd = 0.0;
-      if (tid < kc) {
-        r = I.obs_r[2 * obs_off + q0 + tid];
-        dd = I.d[I.obs_row[2 * obs_off + q0 + tid]];
+  // Thread (kk0 = tid / M, j = tid % M) stages observations kk0 + e NT / M of
+  // every chunk for member j; the next chunk's rows are loaded into registers
+  // before the current chunk's MFMAs, so their latency overlaps the products.
+  constexpr int EPT = KCH * M / NT;
+  static_assert(KCH * M % NT == 0, "whole chunks per thread");
+  const int kk0 = M >= 64 ? __builtin_amdgcn_readfirstlane(tid / M) : tid / M, j = tid % M;
+  float yv[EPT];
+  double rv[EPT], dv[EPT];
+  auto fetch = [&](int q0) {
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      const int q = q0 + kk0 + e * (NT / M);
+      yv[e] = 0.f;
+      rv[e] = dv[e] = 0.0;
+      if (q < nobs && j < m) {
+        const int o = 2 * obs_off + q, row = I.obs_row[o];
+        rv[e] = I.obs_r[o];
+        dv[e] = I.d[row];
+        yv[e] = Yp[(size_t)row * m + j];
       }
-      sm.rc[tid] = sqrt(r);
-      sm.dc[tid] = r * dd;
     }
-    __syncthreads();
-    for (int idx = tid; idx < KCH * M; idx += NT) {
-      const int kk = idx / M, j = idx % M;
-      double y = 0.0;
-      if (kk < kc && j < m) y = Yp[(size_t)I.obs_row[2 * obs_off + q0 + kk] * m + j];
-      bpart += sm.dc[kk] * y;
-      if constexpr (P == 1) ((float*)sm.stage)[j * C::LDKF + kk] = (float)(sm.rc[kk] * y);
+  };
+  fetch(0);
+  for (int q0 = 0; q0 < nobs; q0 += KCH) {
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      const int kk = kk0 + e * (NT / M);
+      const double y = (double)yv[e];
+      bpart += (rv[e] * dv[e]) * y;
+      if constexpr (P == 1) ((float*)sm.stage)[j * C::LDKF + kk] = (float)(sqrt(rv[e]) * y);
       else {
         // split BF16: x = hi + lo with hi = bf16(x), lo = bf16(x - hi)
-        const float xf = (float)(sm.rc[kk] * y);
+        const float xf = (float)(sqrt(rv[e]) * y);
         const __bf16 hi = (__bf16)xf;
         ((__bf16*)sm.stage)[j * C::LDKB + kk] = hi;
         ((__bf16*)sm.stage)[M * C::LDKB + j * C::LDKB + kk] = (__bf16)(xf - (float)hi);
       }
     }
     __syncthreads();
+    if (q0 + KCH < nobs) fetch(q0 + KCH);
     if (wave_on) {
       if constexpr (P == 1) {
         const float* At = (const float*)sm.stage;
