@@ -931,15 +931,26 @@ __device__ void refine_wbar(AnaSmem<M>& sm, const InstDesc& I, int obs_off, int 
   const double* Yp = (const double*)I.Yp;
   const int nobs = 2 * s;
   double cw = 0.0;  // (Y'^T diag(r) Y' wbar)[tid] for tid < M
+  // thread (qq0 = tid / M, jj = tid % M) stages rows qq0 + e NT / M of each
+  // chunk; the next chunk is loaded into registers while this one is used
+  constexpr int EPT = KC * M / NT;
+  static_assert(KC * M % NT == 0, "whole chunks per thread");
+  const int qq0 = M >= 64 ? __builtin_amdgcn_readfirstlane(tid / M) : tid / M, jj = tid % M;
+  double xv[EPT];
+  auto fetch = [&](int q0) {
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      const int q = q0 + qq0 + e * (NT / M);
+      xv[e] = (q < nobs && jj < m) ? Yp[(size_t)I.obs_row[2 * obs_off + q] * m + jj] : 0.0;
+    }
+  };
+  fetch(0);
   for (int q0 = 0; q0 < nobs; q0 += KC) {
     const int kc = min(KC, nobs - q0);
-    for (int idx = tid; idx < KC * M; idx += NT) {
-      const int qq = idx / M, j = idx % M;
-      double v = 0.0;
-      if (qq < kc && j < m) v = Yp[(size_t)I.obs_row[2 * obs_off + q0 + qq] * m + j];
-      Xc[idx] = v;
-    }
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) Xc[(qq0 + e * (NT / M)) * M + jj] = xv[e];
     __syncthreads();
+    if (q0 + KC < nobs) fetch(q0 + KC);
     {
       const int qq = tid / TPR, part = tid % TPR;
       double v = 0.0;
@@ -1092,34 +1103,50 @@ __device__ void transform(AnaSmem<M>& sm, const InstDesc& I, int obs_off, int s,
   __syncthreads();
 }
 
-// Loads `kc` state rows of the domain (both instants) into a KCH x M chunk
-// (zero padded) and their member means into sm.rc.
-template <int M, int KCH, typename T, typename S>
-__device__ void load_rows(AnaSmem<M>& sm, S* X, const InstDesc& I, int est_off, int e, int cur, int q0, int kc) {
-  constexpr int NT = AnaCfg<M>::NT;
-  const int m = I.m, tid = phase_tid();
-  const T* ens = (const T*)I.ens;
-  const size_t slot = (size_t)I.n_act * m;
-  for (int idx = tid; idx < KCH * M; idx += NT) {
-    const int qq = idx / M, j = idx % M;
-    T v = (T)0;
-    if (qq < kc && j < m) {
-      const int q = q0 + qq;
-      const int inst = q < e ? cur : (cur ^ 1);
-      const int act = I.est_act[est_off + (q < e ? q : q - e)];
-      v = ens[(size_t)inst * slot + (size_t)act * m + j];
-    }
-    X[idx] = (S)v;
+// A chunk of KCH state rows of the domain (both instants), rows q0 .. q0 +
+// KCH - 1: fetch() loads each thread's EPT values into registers (issued
+// before the previous chunk's products, so the loads overlap them), store()
+// writes the zero-padded chunk to LDS and the rows' member means to sm.rc.
+template <int M, int KCH, typename T>
+struct RowChunk {
+  static constexpr int NT = AnaCfg<M>::NT, EPT = KCH * M / NT;
+  static_assert(KCH * M % NT == 0, "whole chunks per thread");
+  T v[EPT];
+  int qq0, jj;
+  __device__ RowChunk() {
+    const int tid = phase_tid();
+    qq0 = M >= 64 ? __builtin_amdgcn_readfirstlane(tid / M) : tid / M;  // wavefront-uniform for M >= 64
+    jj = tid % M;
   }
-  __syncthreads();
-  constexpr int TPR = NT / KCH;  // threads per row for the means (8 or 16)
-  const int row = tid / TPR, part = tid % TPR;
-  double sum = 0.0;
-  for (int j = part; j < m; j += TPR) sum += (double)X[row * M + j];
-  sum = group_sum<TPR>(sum);
-  if (part == 0) sm.rc[row] = sum / (double)m;
-  __syncthreads();
-}
+  __device__ void fetch(const InstDesc& I, int est_off, int e, int cur, int q0) {
+    const int m = I.m;
+    const T* ens = (const T*)I.ens;
+    const size_t slot = (size_t)I.n_act * m;
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) {
+      const int q = q0 + qq0 + u * (NT / M);
+      v[u] = (T)0;
+      if (q < 2 * e && jj < m) {
+        const int inst = q < e ? cur : (cur ^ 1);
+        const int act = I.est_act[est_off + (q < e ? q : q - e)];
+        v[u] = ens[(size_t)inst * slot + (size_t)act * m + jj];
+      }
+    }
+  }
+  template <typename S>
+  __device__ void store(AnaSmem<M>& sm, S* X, int m) {
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) X[(qq0 + u * (NT / M)) * M + jj] = (S)v[u];
+    __syncthreads();
+    constexpr int TPR = NT / KCH;  // threads per row for the means (8 or 16)
+    const int tid = phase_tid(), row = tid / TPR, part = tid % TPR;
+    double sum = 0.0;
+    for (int j = part; j < m; j += TPR) sum += (double)X[row * M + j];
+    sum = group_sum<TPR>(sum);
+    if (part == 0) sm.rc[row] = sum / (double)m;
+    __syncthreads();
+  }
+};
 
 // ---- a8 on the FP64 path: Z = xbar 1^T + X' T with FP64 MFMA ----------------
 // Chunks of 16 state rows (both instants) are staged with their member means;
@@ -1133,9 +1160,12 @@ __device__ void update_fp64(AnaSmem<M>& sm, const InstDesc& I, int est_off, int 
   const int m = I.m, tid = phase_tid(), w = tid / 64, lane = tid % 64;
   double* Xd = (double*)sm.stage;
   double* Z = (double*)I.Z + (size_t)2 * est_off * m;
+  RowChunk<M, KR, double> rows;
+  rows.fetch(I, est_off, e, cur, 0);
   for (int q0 = 0; q0 < 2 * e; q0 += KR) {
     const int kc = min(KR, 2 * e - q0);
-    load_rows<M, KR, double>(sm, Xd, I, est_off, e, cur, q0, kc);
+    rows.store(sm, Xd, m);
+    if (q0 + KR < 2 * e) rows.fetch(I, est_off, e, cur, q0 + KR);
     for (int cb = w; cb < CB; cb += 4) {
       const int arow = lane % 16;
       const double xb = sm.rc[arow];
@@ -1169,9 +1199,12 @@ __device__ void update_mfma(AnaSmem<M>& sm, const InstDesc& I, int est_off, int 
   const int m = I.m, tid = phase_tid(), w = tid / 64, lane = tid % 64;
   float* Xf = (float*)sm.stage;
   float* Z = (float*)I.Z + (size_t)2 * est_off * m;
+  RowChunk<M, KR, float> rows;
+  rows.fetch(I, est_off, e, cur, 0);
   for (int q0 = 0; q0 < 2 * e; q0 += KR) {
     const int kc = min(KR, 2 * e - q0);
-    load_rows<M, KR, float>(sm, Xf, I, est_off, e, cur, q0, kc);
+    rows.store(sm, Xf, m);
+    if (q0 + KR < 2 * e) rows.fetch(I, est_off, e, cur, q0 + KR);
     for (int t = w; t < NTILE; t += 4) {
       const int rb = t / CB, cb = t % CB;
       const int arow = rb * 16 + lane % 16;
