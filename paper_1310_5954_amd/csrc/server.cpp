@@ -140,6 +140,13 @@ struct letkf_server {
   int launch_batch(Batch& b);
   int graph_for(int slot, const GraphKey& k, hipGraphExec_t* out);
   void drop_graphs();
+  // nothing queued, being launched or in flight (caller holds mu)
+  bool idle() const {
+    if (pending > 0 || inflight > 0) return false;
+    for (bool b : slot_busy)
+      if (b) return false;
+    return true;
+  }
 };
 
 static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -586,7 +593,7 @@ int letkf_server_stats(letkf_server* s, uint64_t* frames, uint64_t* batches, uin
 int letkf_server_autotune(letkf_server* s, int32_t reps, letkf_tuning* out) {
   if (!s) return fail(LETKF_EINVAL, "null server");
   std::unique_lock<std::mutex> lk(s->mu);  // held throughout: nothing is launched meanwhile
-  if (s->pending > 0 || s->inflight > 0) return fail(LETKF_EAGAIN, "server has frames queued or in flight");
+  if (!s->idle()) return fail(LETKF_EAGAIN, "server has frames queued, being launched or in flight");
   const int slot = 0;
   hipStream_t st = s->stream[slot];
   for (int c = 0; c < kBigClass; ++c) {  // the 12 tunable classes (no m > 128 instance is admitted)
@@ -633,7 +640,7 @@ int letkf_server_set_tuning(letkf_server* s, int32_t cls, const letkf_tuning* t)
   if (!t || t->grid < 1 || t->grid > 65535 || t->order < LETKF_ORDER_MAP || t->order > LETKF_ORDER_XCD)
     return fail(LETKF_EINVAL, "tuning: grid must be in [1, 65535] and order one of LETKF_ORDER_*");
   std::unique_lock<std::mutex> lk(s->mu);
-  if (s->pending > 0 || s->inflight > 0) return fail(LETKF_EAGAIN, "server has frames queued or in flight");
+  if (!s->idle()) return fail(LETKF_EAGAIN, "server has frames queued, being launched or in flight");
   for (letkf_handle* h : s->inst)
     if (h && h->cls == cls) {
       int rc = upload_order(h, t->order, s->upload);
