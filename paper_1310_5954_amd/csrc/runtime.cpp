@@ -608,11 +608,14 @@ int tune_class(int cls, const InstDesc* tab, BatchHdr* hdr, int slope_rows, int 
   }
   for (letkf_handle* h : insts)
     if (!rc) rc = upload_order(h, best_order, s);
-  for (size_t i = 0; i < insts.size() && !rc; ++i) {
-    if (hipMemcpyAsync(insts[i]->ws + insts[i]->L.state, &saved[i], sizeof(InstState), hipMemcpyHostToDevice, s) != hipSuccess)
-      rc = fail(LETKF_EDEVICE, "state restore");
-  }
-  if (!rc && hipStreamSynchronize(s) != hipSuccess) rc = fail(LETKF_EDEVICE, "hipStreamSynchronize");
+  // the states are put back whatever happened above
+  int rrc = LETKF_OK;
+  for (size_t i = 0; i < insts.size(); ++i)
+    if (hipMemcpyAsync(insts[i]->ws + insts[i]->L.state, &saved[i], sizeof(InstState), hipMemcpyHostToDevice, s) !=
+        hipSuccess)
+      rrc = fail(LETKF_EDEVICE, "state restore");
+  if (hipStreamSynchronize(s) != hipSuccess) rrc = fail(LETKF_EDEVICE, "hipStreamSynchronize");
+  if (!rc) rc = rrc;
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
   if (rc) return rc;
