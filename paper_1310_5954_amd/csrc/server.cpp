@@ -115,6 +115,7 @@ struct letkf_server {
   hipEvent_t done_ev[kSlots] = {};
   bool slot_busy[kSlots] = {};     // launched or being launched
   bool slot_has[kSlots] = {};      // slot_batch[k] is waiting for its completion thread
+  int slot_cls[kSlots] = {};       // class of the batch last launched on slot k
   Batch slot_batch[kSlots];
 
   std::mutex mu;
@@ -287,6 +288,23 @@ void letkf_server::scheduler_loop() {
       else cv_work.wait_until(lk, deadline);
       continue;
     }
+    // The slots' streams share the process's hardware queues in turn (slot k
+    // and slot k + kSlots / 2 on one queue, as created), and a queue runs its
+    // kernels in order: a batch behind a long one on the same queue waits for
+    // it.  Prefer a slot whose queue partner is idle, then one whose partner
+    // runs the same class.
+    {
+      int pick = -1;
+      for (int pass = 0; pass < 3 && pick < 0; ++pass)
+        for (int k = 0; k < kSlots && pick < 0; ++k) {
+          if (slot_busy[k]) continue;
+          const int mate = (k + kSlots / 2) % kSlots;
+          if (pass == 0 && !slot_busy[mate]) pick = k;
+          if (pass == 1 && slot_cls[mate] == best) pick = k;
+          if (pass == 2) pick = k;
+        }
+      s = pick;
+    }
     // one frame per ready instance of the class, round robin from rr
     Batch b;
     b.slot = s;
@@ -315,6 +333,7 @@ void letkf_server::scheduler_loop() {
     rr = (rr + 1) % std::max(n, 1);
     if (b.frames.empty()) continue;
     slot_busy[s] = true;
+    slot_cls[s] = best;
     lk.unlock();
     int rc = launch_batch(b);
     lk.lock();
