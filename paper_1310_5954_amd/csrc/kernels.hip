@@ -810,7 +810,7 @@ __device__ bool gram_converged(AnaSmem<M>& sm, double tol2) {
 // partners in that group, so its pair slot keeps it in registers for the
 // whole group and only the partner column goes through LDS each step.
 template <int P, int M>
-__device__ int jacobi(AnaSmem<M>& sm) {
+__device__ int jacobi(AnaSmem<M>& sm, int m) {
   using C = AnaCfg<M>;
   constexpr int NT = C::NT, LDB = C::LDB, TPP = C::TPP;
   const int tid = phase_tid();
@@ -835,10 +835,38 @@ __device__ int jacobi(AnaSmem<M>& sm) {
     {
       constexpr int TPC = NT / M;  // threads per column for the norms
       const int c = tid / TPC, part = tid % TPC;
-      double ss = 0.0;
-      for (int r = part; r < M; r += TPC) { const double v = sm.Bm[c * LDB + r]; ss += v * v; }
-      ss = group_sum<TPC>(ss);
-      if (part == 0) sm.nrm[c] = ss;
+      if constexpr (M <= 64) {
+        // de Rijk's ordering: every sweep starts with the m columns sorted by
+        // decreasing norm (the padded unit columns stay at m..M-1), which
+        // saves about one sweep in twelve on the ELT domains (CPU replay)
+        double v[M / TPC];
+        double ss = 0.0;
+#pragma unroll
+        for (int k = 0; k < M / TPC; ++k) {
+          v[k] = sm.Bm[c * LDB + part + TPC * k];
+          ss = fma(v[k], v[k], ss);
+        }
+        ss = group_sum<TPC>(ss);
+        if (part == 0) sm.nrm[c] = ss;
+        __syncthreads();
+        int rank = c;
+        if (c < m) {
+          rank = 0;
+          for (int c2 = 0; c2 < m; ++c2) {
+            const double n2 = sm.nrm[c2];
+            rank += (n2 > ss || (n2 == ss && c2 < c)) ? 1 : 0;
+          }
+        }
+        __syncthreads();  // every rank is taken from the old order before the columns move
+#pragma unroll
+        for (int k = 0; k < M / TPC; ++k) sm.Bm[rank * LDB + part + TPC * k] = v[k];
+        if (part == 0) sm.nrm[rank] = ss;
+      } else {
+        double ss = 0.0;
+        for (int r = part; r < M; r += TPC) { const double v = sm.Bm[c * LDB + r]; ss += v * v; }
+        ss = group_sum<TPC>(ss);
+        if (part == 0) sm.nrm[c] = ss;
+      }
     }
     if (tid == 0) sm.s_rot = 0;
     __syncthreads();
@@ -1270,7 +1298,7 @@ __device__ void analyse_item(AnaSmem<M>& sm, const InstDesc* __restrict__ tab, c
   if constexpr (AnaCfg<M>::TM <= 4) cholesky<M>(sm);
   else cholesky_lds<M>(sm);
   stamp(2);
-  const int sweeps = jacobi<P, M>(sm);
+  const int sweeps = jacobi<P, M>(sm, m);
   stamp(3);
   transform<P, M>(sm, I, obs_off, s, dbg);
   stamp(4);
