@@ -835,38 +835,34 @@ __device__ int jacobi(AnaSmem<M>& sm, int m) {
     {
       constexpr int TPC = NT / M;  // threads per column for the norms
       const int c = tid / TPC, part = tid % TPC;
-      if constexpr (M <= 64) {
-        // de Rijk's ordering: every sweep starts with the m columns sorted by
-        // decreasing norm (the padded unit columns stay at m..M-1), which
-        // saves about one sweep in twelve on the ELT domains (CPU replay)
-        double v[M / TPC];
-        double ss = 0.0;
-#pragma unroll
-        for (int k = 0; k < M / TPC; ++k) {
-          v[k] = sm.Bm[c * LDB + part + TPC * k];
-          ss = fma(v[k], v[k], ss);
+      // de Rijk's ordering: every sweep starts with the m columns sorted by
+      // decreasing norm (the padded unit columns stay at m..M-1), which saves
+      // about one sweep in twelve on the ELT domains (CPU replay).  The columns
+      // move in passes of at most 16 values per thread.
+      constexpr int PER = M / TPC, CH = PER < 16 ? PER : 16;
+      double ss = 0.0;
+      for (int r = part; r < M; r += TPC) { const double v = sm.Bm[c * LDB + r]; ss = fma(v, v, ss); }
+      ss = group_sum<TPC>(ss);
+      if (part == 0) sm.nrm[c] = ss;
+      __syncthreads();
+      int rank = c;
+      if (c < m) {
+        rank = 0;
+        for (int c2 = 0; c2 < m; ++c2) {
+          const double n2 = sm.nrm[c2];
+          rank += (n2 > ss || (n2 == ss && c2 < c)) ? 1 : 0;
         }
-        ss = group_sum<TPC>(ss);
-        if (part == 0) sm.nrm[c] = ss;
-        __syncthreads();
-        int rank = c;
-        if (c < m) {
-          rank = 0;
-          for (int c2 = 0; c2 < m; ++c2) {
-            const double n2 = sm.nrm[c2];
-            rank += (n2 > ss || (n2 == ss && c2 < c)) ? 1 : 0;
-          }
-        }
-        __syncthreads();  // every rank is taken from the old order before the columns move
-#pragma unroll
-        for (int k = 0; k < M / TPC; ++k) sm.Bm[rank * LDB + part + TPC * k] = v[k];
-        if (part == 0) sm.nrm[rank] = ss;
-      } else {
-        double ss = 0.0;
-        for (int r = part; r < M; r += TPC) { const double v = sm.Bm[c * LDB + r]; ss += v * v; }
-        ss = group_sum<TPC>(ss);
-        if (part == 0) sm.nrm[c] = ss;
       }
+      for (int k0 = 0; k0 < PER; k0 += CH) {
+        double v[CH];
+#pragma unroll
+        for (int k = 0; k < CH; ++k) v[k] = sm.Bm[c * LDB + part + TPC * (k0 + k)];
+        __syncthreads();  // this pass's rows are read everywhere before any column moves
+#pragma unroll
+        for (int k = 0; k < CH; ++k) sm.Bm[rank * LDB + part + TPC * (k0 + k)] = v[k];
+        __syncthreads();
+      }
+      if (part == 0) sm.nrm[rank] = ss;
     }
     if (tid == 0) sm.s_rot = 0;
     __syncthreads();
