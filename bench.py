@@ -43,17 +43,19 @@ METRIC = "frames/s + p50/p99 frame latency (µs), LETKF 84×84 subaps m=64"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_analysis_fp64_84x84_m64_traffic.txt")
 
 
-def measured_traffic(kernels: str):
+def measured_traffic(kernels: str, tuning):
     """HBM bytes per k_analysis launch from the committed rocprofv3 counter
-    summary (FETCH_SIZE x fetch scale + WRITE_SIZE x write scale), or None when
-    the summary was taken on another build of the device code."""
+    summary (FETCH_SIZE x fetch scale + WRITE_SIZE x write scale) for the
+    launch shape (domain order, grid) this run chose, or None when the summary
+    was taken on another build of the device code or has no such shape."""
     try:
         kv = dict(line.split(":", 1) for line in open(TRAFFIC_FILE) if ":" in line and not line.startswith("#"))
     except OSError:
         return None
-    if kv.get("kernels", "").strip() != kernels:
+    if kv.get("kernels", "").strip() != kernels or not tuning:
         return None
-    return float(kv["traffic_bytes_per_launch"])
+    v = kv.get(f"traffic_bytes_per_launch.{tuning['order']}.{tuning['grid']}")
+    return float(v) if v is not None else None
 
 
 def analysis_flops(m: int, dmap, sweeps_total: int, solves: int, frames: int) -> float:
@@ -606,7 +608,7 @@ def main() -> int:
     achieved = flops / (ana_ms * 1e-3) / 1e12
     roofline = dict(bound="alu", achieved=round(achieved, 3), peak=PEAK_FP64_TFLOPS, unit="TFLOP/s",
                     frac=round(achieved / PEAK_FP64_TFLOPS, 4),
-                    traffic=measured_traffic(kernel_hash()) if args.workload == 84 else None,
+                    traffic=measured_traffic(kernel_hash(), plain["tuning"]) if args.workload == 84 else None,
                     kernel=f"k_analysis<FP64, m={case.m}> (vector FP64: Cholesky + one-sided Jacobi dominate)")
     plain_out = dict(frames_per_s=round(plain["fps"], 2), p50_us=round(plain["p50_us"], 1),
                      p99_us=round(plain["p99_us"], 1),

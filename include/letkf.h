@@ -232,7 +232,9 @@ typedef struct letkf_tuning {
  * 2 x blocks_per_cu, or one per domain; capped at the domain count) and the
  * order in which the domains are claimed (LETKF_ORDER_*).  Each
  * candidate is timed over `reps` launches (1..100) after one warm-up, with
- * HIP events on `stream`; the choice is kept by the handle (a captured
+ * HIP events on `stream`.  The fastest candidate is chosen, except that the
+ * best LETKF_ORDER_XCD candidate wins when it is within 2 % of it (it reads
+ * less from HBM for the same time); the choice is kept by the handle (a captured
  * LETKF_FLAG_GRAPH frame is re-captured).  The instance's state (ensemble,
  * frame and sweep counters) is unchanged; letkf_debug_domain reads the
  * tuning runs' intermediates until the next analysis.  Results of later

@@ -837,32 +837,38 @@ __device__ int jacobi(AnaSmem<M>& sm, int m) {
       const int c = tid / TPC, part = tid % TPC;
       // de Rijk's ordering: every sweep starts with the m columns sorted by
       // decreasing norm (the padded unit columns stay at m..M-1), which saves
-      // about one sweep in twelve on the ELT domains (CPU replay).  The columns
-      // move in passes of at most 16 values per thread.
+      // about one sweep in twelve on the ELT domains (CPU replay).  A column's
+      // rank is counted by its TPC threads over interleaved norms; the columns
+      // move, in passes of at most 16 values per thread, only when the order
+      // changed (late sweeps mostly keep it).
       constexpr int PER = M / TPC, CH = PER < 16 ? PER : 16;
       double ss = 0.0;
       for (int r = part; r < M; r += TPC) { const double v = sm.Bm[c * LDB + r]; ss = fma(v, v, ss); }
       ss = group_sum<TPC>(ss);
       if (part == 0) sm.nrm[c] = ss;
       __syncthreads();
-      int rank = c;
-      if (c < m) {
-        rank = 0;
-        for (int c2 = 0; c2 < m; ++c2) {
+      double ahead = 0.0;  // columns ahead of c among this thread's share (exact small integers)
+      if (c < m)
+        for (int c2 = part; c2 < m; c2 += TPC) {
           const double n2 = sm.nrm[c2];
-          rank += (n2 > ss || (n2 == ss && c2 < c)) ? 1 : 0;
+          ahead += (n2 > ss || (n2 == ss && c2 < c)) ? 1.0 : 0.0;
         }
-      }
-      for (int k0 = 0; k0 < PER; k0 += CH) {
-        double v[CH];
+      ahead = group_sum<TPC>(ahead);
+      const int rank = c < m ? (int)ahead : c;
+      if (__syncthreads_or(rank != c)) {
+        for (int k0 = 0; k0 < PER; k0 += CH) {
+          double v[CH];
 #pragma unroll
-        for (int k = 0; k < CH; ++k) v[k] = sm.Bm[c * LDB + part + TPC * (k0 + k)];
-        __syncthreads();  // this pass's rows are read everywhere before any column moves
+          for (int k = 0; k < CH; ++k) v[k] = sm.Bm[c * LDB + part + TPC * (k0 + k)];
+          // every read of this pass's rows (rows TPC k0 .. TPC (k0 + CH) - 1, which no
+          // other pass touches) is done before any column moves; the sweep reads
+          // the moved columns after the barrier that follows
+          __syncthreads();
 #pragma unroll
-        for (int k = 0; k < CH; ++k) sm.Bm[rank * LDB + part + TPC * (k0 + k)] = v[k];
-        __syncthreads();
+          for (int k = 0; k < CH; ++k) sm.Bm[rank * LDB + part + TPC * (k0 + k)] = v[k];
+        }
+        if (part == 0) sm.nrm[rank] = ss;
       }
-      if (part == 0) sm.nrm[rank] = ss;
     }
     if (tid == 0) sm.s_rot = 0;
     __syncthreads();

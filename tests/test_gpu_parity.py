@@ -356,7 +356,9 @@ def test_autotune_keeps_state_and_frames():
     t = f.autotune(reps=2)
     n_dom = case.dmap.n_domains
     assert t["candidates"] >= 2 and 1 <= t["grid"] <= n_dom and t["best_us"] > 0, t
-    assert t["best_us"] <= t["default_us"] + 1e-3, t
+    # the fastest candidate, or the per-XCD order's best within 2 % of it
+    slack = 1.02 if t["order"] == "xcd" else 1.0
+    assert t["best_us"] <= slack * t["default_us"] + 1e-3, t
     X1, f1 = f.get_state()
     assert f1 == f0 and np.array_equal(X0, X1) and f.sweep_stats() == sw0
     for k in range(1, 4):
