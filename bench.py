@@ -77,7 +77,9 @@ def analysis_flops(m: int, dmap, sweeps_total: int, solves: int, frames: int) ->
 
 def run_phases(case, W, ys):
     """Per-phase cycles of every domain's analysis workgroup (shader-clock
-    stamps of a debug instance, FP64, one frame after W warm-up frames) and
+    stamps of a debug instance, FP64, one frame after W warm-up frames and
+    six frames whose per-domain sweep counts are kept), where each domain ran
+    (CU, sharing it with other domains or not), and
     the bytes each phase moves, for the bandwidth view of the analysis
     kernel: gather + C/b reads the domain's slope rows of Y' (8m bytes each)
     plus d and r (16 bytes per observation); the update reads the domain's
@@ -90,13 +92,23 @@ def run_phases(case, W, ys):
     f = Filter(Problem.from_case(case), case.X0, precision=FP64, device="cuda:0", debug=True)
     for k in range(W):
         f.step(ys[k], pred=False)
+    m, dm = case.m, case.dmap
+    # sweeps of every domain over the frames before the measured one (how well a
+    # frame's sweep counts predict the next frame's)
+    F = min(6, len(ys) - W - 1)
+    sweep_frames = []
+    for k in range(F):
+        f.step(ys[W + k], pred=False)
+        sweep_frames.append([f.debug_domain(l)["sweeps"] for l in range(dm.n_domains)])
     f.kernel_times(True)
-    f.step(ys[W], pred=False)
+    f.step(ys[W + F], pred=False)
     torch.cuda.synchronize()
     ms, _ = f.kernel_times(False)
-    m, dm = case.m, case.dmap
     names = ("gather_C", "cholesky", "jacobi", "transform", "update")
-    cyc = np.array([[f.debug_domain(l)["cycles"][n] for n in names] for l in range(dm.n_domains)])
+    dbg = [f.debug_domain(l) for l in range(dm.n_domains)]
+    cyc = np.array([[d["cycles"][n] for n in names] for d in dbg])
+    sweeps = np.array([d["sweeps"] for d in dbg])
+    place = [f.debug_placement(l) for l in range(dm.n_domains)]
     f.close()
     total = cyc.sum(axis=1)
     clock_hz = total.max() / (ms[1] * 1e-3)
@@ -107,6 +119,42 @@ def run_phases(case, W, ys):
     out = dict(domains=int(dm.n_domains), analysis_ms=round(ms[1], 4), clock_ghz=round(clock_hz / 1e9, 3),
                cycles_mean={n: round(float(cyc[:, i].mean())) for i, n in enumerate(names)},
                share={n: round(float(cyc[:, i].sum() / cyc.sum()), 4) for i, n in enumerate(names)})
+    # placement: the CU each domain ran on and how many other domains shared it while it ran
+    cu_key = [(p["xcd"], p["se"], p["sh"], p["cu"]) for p in place]
+    t0 = np.array([p["start_clock"] for p in place])
+    t1 = t0 + total
+    shared = np.array([sum(1 for k in range(len(place)) if k != l and cu_key[k] == cu_key[l]
+                           and t0[k] < t1[l] and t0[l] < t1[k]) for l in range(len(place))])
+    per_cu = {}
+    for k in cu_key:
+        per_cu[k] = per_cu.get(k, 0) + 1
+    hist = {}
+    for v in per_cu.values():
+        hist[v] = hist.get(v, 0) + 1
+    slow = int(np.argmax(total))
+    out["placement"] = dict(
+        cus_used=len(per_cu), domains_per_cu={str(k): v for k, v in sorted(hist.items())},
+        cycles_by_sharing={str(k): dict(domains=int((shared == k).sum()),
+                                        cycles_mean=round(float(total[shared == k].mean())),
+                                        sweeps_mean=round(float(sweeps[shared == k].mean()), 2))
+                           for k in sorted(set(shared.tolist()))},
+        cycles_per_sweep_jacobi=round(float((cyc[:, 2] / np.maximum(sweeps, 1)).mean())),
+        sweeps_hist={str(k): int((sweeps == k).sum()) for k in sorted(set(sweeps.tolist()))},
+        slowest=dict(domain=slow, cycles=round(float(total[slow])), sweeps=int(sweeps[slow]),
+                     sharing=int(shared[slow])),
+        # which workgroup indices ran alone on their CU (one item each at this grid)
+        alone_workgroups=_ranges(sorted(p["workgroup"] for p, sh in zip(place, shared) if sh == 0)))
+    sf = np.array(sweep_frames + [sweeps.tolist()], dtype=float)
+    same = float(np.mean(sf[1:] == sf[:-1]))
+    top = []
+    for k in range(len(sf) - 1):
+        a, b = np.argsort(-sf[k], kind="stable")[:16], set(np.argsort(-sf[k + 1], kind="stable")[:48].tolist())
+        top.append(np.mean([x in b for x in a]))
+    out["sweep_stability"] = dict(
+        frames=len(sf), same_as_previous_frame=round(same, 3),
+        corr_with_previous=round(float(np.mean([np.corrcoef(sf[k], sf[k + 1])[0, 1] for k in range(len(sf) - 1)])), 3),
+        top16_in_next_top48=round(float(np.mean(top)), 3),
+        mean_over_frames_vs_last=round(float(np.corrcoef(sf[:-1].mean(axis=0), sf[-1])[0, 1]), 3))
     for name, i, b in (("gather_C", 0, bytes_gather), ("update", 4, bytes_update)):
         t = cyc[:, i] / clock_hz
         # every domain's gather starts with the launch, so the gathers overlap: aggregate = bytes / longest gather
@@ -114,6 +162,17 @@ def run_phases(case, W, ys):
                          aggregate_gbs=round(float(b.sum() / t.max() / 1e9), 1) if i == 0 else None,
                          aggregate_frac_of_hbm=round(float(b.sum() / t.max() / 1e9 / PEAK_HBM_GBS), 4)
                          if i == 0 else None)
+    return out
+
+
+def _ranges(xs):
+    """[a, b] runs of consecutive integers in a sorted list."""
+    out = []
+    for x in xs:
+        if out and x == out[-1][1] + 1:
+            out[-1][1] = x
+        else:
+            out.append([x, x])
     return out
 
 
@@ -249,9 +308,11 @@ def run_plain(case, prec, K, W, NL, ys, tune=True):
 
     from paper_1310_5954_amd import Filter, Problem
     f = Filter(Problem.from_case(case), case.X0, precision=prec, device="cuda:0", pistons=PISTONS)
-    tuning = f.autotune() if (TUNE and tune) else None
     for k in range(W):
         f.step(ys[k], pred=False)
+    # tuned on the live ensemble after the warm-up frames (the balanced order
+    # places the domains by their sweeps so far); state and counters unchanged
+    tuning = f.autotune() if (TUNE and tune) else None
     torch.cuda.synchronize()
     sw0, so0 = f.sweep_stats()
     f.kernel_times(True)
@@ -284,9 +345,11 @@ def run_plain_graph(case, K, W, NL, ys):
 
     from paper_1310_5954_amd import FP64, Filter, Problem
     f = Filter(Problem.from_case(case), case.X0, precision=FP64, device="cuda:0", pistons=PISTONS, graph=True)
+    for k in range(W // 2):
+        f.step(ys[k], pred=False)
     if TUNE:
         f.autotune()
-    for k in range(W):
+    for k in range(W // 2, W):  # the frame graph is captured again after tuning
         f.step(ys[k], pred=False)
     torch.cuda.synchronize()
     t0 = time.perf_counter()

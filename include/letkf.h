@@ -188,6 +188,17 @@ int letkf_set_state(letkf_handle* h, const double* X, uint64_t frame, void* stre
 int letkf_debug_domain(letkf_handle* h, int32_t domain, double* C_out, double* lam_out,
                        double* T_out, int32_t* sweeps_out, double* cycles_out, void* stream);
 
+/* Where each domain's analysis ran in the last analysis (needs
+ * LETKF_FLAG_DEBUG; m <= 128): hw_id_out the workgroup's HW_ID register
+ * (shader engine, shader array, CU and SIMD fields, as the ISA defines
+ * them), xcc_id_out its XCC_ID register (the XCD), workgroup_out the
+ * index of the analysis workgroup that took it, start_clock_out the shader
+ * clock when it started (comparable within one XCD).  A tool for
+ * studying how the analysis workgroups are spread over the CUs.  Any output
+ * may be NULL.  Waits for the stream. */
+int letkf_debug_placement(letkf_handle* h, int32_t domain, uint32_t* hw_id_out, uint32_t* xcc_id_out,
+                          int32_t* workgroup_out, double* start_clock_out, void* stream);
+
 /* Number of domains whose eigensolver hit the sweep cap in the last analysis
  * (0 when all converged); waits for the stream. */
 int letkf_unconverged_domains(letkf_handle* h, int32_t* count, void* stream);
@@ -215,6 +226,13 @@ int letkf_kernel_times(letkf_handle* h, int enable, double* ms_out, uint64_t* fr
 #define LETKF_ORDER_COST 1  /* decreasing cost (actuators + subapertures): the default */
 #define LETKF_ORDER_XCD 2   /* the map's order cut into 8 contiguous chunks, position b from chunk b % 8: \
                                workgroup b runs on XCD b % 8, so neighbouring domains share an L2 */
+#define LETKF_ORDER_BALANCED 3 /* plain instances only, placed by measured cost: the Jacobi sweeps    \
+                                  of each domain so far (summed over every analysis of the instance). \
+                                  When every domain's workgroup is resident at once: LETKF_ORDER_XCD  \
+                                  with each XCD's domains re-placed among its CUs so that the costliest \
+                                  run alone on a CU or with the cheapest company; otherwise longest    \
+                                  first.  Computed when applied (letkf_autotune, letkf_set_tuning),    \
+                                  from the sweeps at that time */
 
 /* Result of an autotuning run of the domain-analysis launch. */
 typedef struct letkf_tuning {
@@ -233,10 +251,13 @@ typedef struct letkf_tuning {
  * order in which the domains are claimed (LETKF_ORDER_*).  Each
  * candidate is timed over `reps` launches (1..100) after one warm-up, with
  * HIP events on `stream`.  The fastest candidate is chosen, except that the
- * best LETKF_ORDER_XCD candidate wins when it is within 2 % of it (it reads
- * less from HBM for the same time); the choice is kept by the handle (a captured
- * LETKF_FLAG_GRAPH frame is re-captured).  The instance's state (ensemble,
- * frame and sweep counters) is unchanged; letkf_debug_domain reads the
+ * best LETKF_ORDER_XCD or LETKF_ORDER_BALANCED candidate wins when it is
+ * within 2 % of it (they read less from HBM for the same time); the choice is
+ * kept by the handle (a captured LETKF_FLAG_GRAPH frame is re-captured).  The
+ * balanced order is placed by the sweeps of the analyses so far including
+ * the tuning launches, which all analyse the current frame.  The instance's
+ * state (ensemble, frame and sweep counters, per-domain sweep sums) is
+ * unchanged; letkf_debug_domain reads the
  * tuning runs' intermediates until the next analysis.  Results of later
  * frames do not depend on the choice: every domain's analysis is computed
  * the same way whichever workgroup runs it.  `out` may be NULL.  Waits for
@@ -246,8 +267,10 @@ int letkf_autotune(letkf_handle* h, int32_t reps, letkf_tuning* out, void* strea
 /* Applies a launch shape chosen earlier (say a letkf_tuning kept from a
  * letkf_autotune run on the same GPU model and domain map): grid in
  * [1, 65535] workgroups (more than the domain count acts as the domain
- * count) and order (LETKF_ORDER_*); the other fields are ignored.  Waits for
- * the stream.  LETKF_EINVAL for out-of-range fields. */
+ * count) and order (LETKF_ORDER_*; LETKF_ORDER_BALANCED is placed by the
+ * sweeps of the analyses so far, so applying it again after some frames
+ * re-balances); the other fields are ignored.  Waits for the stream.
+ * LETKF_EINVAL for out-of-range fields. */
 int letkf_set_tuning(letkf_handle* h, const letkf_tuning* t, void* stream);
 
 /* Totals since create (or set_state): Jacobi sweeps over all domain solves,
@@ -300,7 +323,9 @@ int letkf_server_autotune(letkf_server* s, int32_t reps, letkf_tuning* out);
 /* Sets the analysis grid of class cls (index precision x 4 + size, as in
  * letkf_server_autotune's output) and the domain order of its admitted
  * instances (instances admitted later keep the default order).  Only while
- * idle (LETKF_EAGAIN otherwise); LETKF_EINVAL for out-of-range fields. */
+ * idle (LETKF_EAGAIN otherwise); LETKF_EINVAL for out-of-range fields and
+ * for LETKF_ORDER_BALANCED (a batch's workgroup placement depends on the
+ * batch). */
 int letkf_server_set_tuning(letkf_server* s, int32_t cls, const letkf_tuning* t);
 
 /* Bytes of a server's arena taken by its own instance table and staging

@@ -17,8 +17,8 @@ FLAG_DEBUG = 0x1
 FLAG_PISTONS = 0x2
 FLAG_GRAPH = 0x4
 SERVER_GRAPHS = 0x1
-ORDER_MAP, ORDER_COST, ORDER_XCD = 0, 1, 2
-ORDER_NAMES = {ORDER_MAP: "map", ORDER_COST: "cost", ORDER_XCD: "xcd"}
+ORDER_MAP, ORDER_COST, ORDER_XCD, ORDER_BALANCED = 0, 1, 2, 3
+ORDER_NAMES = {ORDER_MAP: "map", ORDER_COST: "cost", ORDER_XCD: "xcd", ORDER_BALANCED: "balanced"}
 
 
 class Dims(C.Structure):
@@ -74,6 +74,8 @@ def _sig(lib):
     lib.letkf_get_state.argtypes = [P, pd, C.POINTER(C.c_uint64), P]
     lib.letkf_set_state.argtypes = [P, pd, C.c_uint64, P]
     lib.letkf_debug_domain.argtypes = [P, C.c_int32, pd, pd, pd, C.POINTER(C.c_int32), pd, P]
+    lib.letkf_debug_placement.argtypes = [P, C.c_int32, C.POINTER(C.c_uint32), C.POINTER(C.c_uint32),
+                                          C.POINTER(C.c_int32), pd, P]
     lib.letkf_unconverged_domains.argtypes = [P, C.POINTER(C.c_int32), P]
     lib.letkf_kernel_times.argtypes = [P, C.c_int, pd, C.POINTER(C.c_uint64)]
     lib.letkf_sweep_stats.argtypes = [P, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64), P]
@@ -101,7 +103,7 @@ def _sig(lib):
     lib.letkf_build_id.argtypes = []
     lib.letkf_build_id.restype = C.c_char_p
     for name in ("letkf_workspace_size", "letkf_create", "letkf_destroy", "letkf_analyse", "letkf_forecast",
-                 "letkf_step", "letkf_get_state", "letkf_set_state", "letkf_debug_domain",
+                 "letkf_step", "letkf_get_state", "letkf_set_state", "letkf_debug_domain", "letkf_debug_placement",
                  "letkf_unconverged_domains", "letkf_kernel_times", "letkf_sweep_stats", "letkf_autotune",
                  "letkf_server_autotune", "letkf_set_tuning", "letkf_server_set_tuning", "letkf_last_means",
                  "letkf_server_create", "letkf_server_add", "letkf_server_remove",

@@ -162,6 +162,18 @@ class Filter:
         return dict(C=Cm, lam=lam, T=T, sweeps=int(sw.value),
                     cycles=dict(zip(("gather_C", "cholesky", "jacobi", "transform", "update"), cyc.tolist())))
 
+    def debug_placement(self, l: int) -> dict:
+        """Where domain l's analysis ran in the last analysis: XCD, shader
+        engine, shader array, CU and SIMD (decoded from HW_ID / XCC_ID) and its
+        start clock (letkf_debug_placement)."""
+        hw, xcc, wg, t0 = C.c_uint32(), C.c_uint32(), C.c_int32(), C.c_double()
+        with torch.cuda.device(self.device):
+            L.check(L.lib().letkf_debug_placement(self.handle, int(l), C.byref(hw), C.byref(xcc), C.byref(wg),
+                                                  C.byref(t0), _stream(self.device)), "letkf_debug_placement")
+        h = hw.value
+        return dict(xcd=xcc.value & 0xF, se=(h >> 13) & 0x7, sh=(h >> 12) & 1, cu=(h >> 8) & 0xF,
+                    simd=(h >> 4) & 0x3, workgroup=wg.value, start_clock=t0.value)
+
     def kernel_times(self, enable: bool):
         """Accumulated kernel milliseconds {slopes, analysis, merge/forecast} and
         the number of timed calls since the last enable; then (re)enables or stops."""

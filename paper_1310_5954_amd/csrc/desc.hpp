@@ -58,6 +58,7 @@ struct InstDesc {
   double* bigB;              // m > 128: [n_dom][256][256] L, then B = L J, then U (column-major)
   double* bigv;              // m > 128: [n_dom][5][256] b, wbar, lambda, spare
   int32_t* bigf;             // m > 128: [n_dom][4] converged, rounds that rotated, sweeps, spare
+  uint32_t* dom_sweeps;      // [n_dom] Jacobi sweeps of each domain, summed over every analysis
   double* dbg;               // [n_dom][2*m*m + m] C, lambda, T (NULL unless debug)
   int32_t* dbg_sweeps;       // [n_dom]
   InstState* st;
@@ -83,6 +84,11 @@ struct BatchHdr {
   int32_t out_off[kMaxBatch];
   ClassBatch cls[kNumClasses];
 };
+
+// Per-domain debug record (LETKF_FLAG_DEBUG): C [m*m], lambda [m], T [m*m],
+// then kDbgTail slots: shader-clock stamps at the 6 phase boundaries, HW_ID,
+// XCC_ID, the workgroup index that ran the domain.
+constexpr int kDbgTail = 16;
 
 inline int class_of(int padded_m, int prec) {
   if (padded_m > 128) return kBigClass;  // validated to be FP64

@@ -29,7 +29,7 @@ struct Layout {
   size_t a1, a2, rowptr, col, val, dom, order, est, obs_row, obs_r, mptr, mrow, mw, mdom, pist_op;
   size_t pist_r, pist_c, pist_ptr, pist_row, pist_coef;
   size_t bigA, bigB, bigv, bigf;   // m > 128 only
-  size_t dbg, dbg_sweeps;
+  size_t dom_sweeps, dbg, dbg_sweeps;
   size_t static_begin, static_end;  // [a1, end of tables) uploaded at create
   size_t total;
 };
@@ -75,14 +75,22 @@ constexpr int kXcds = 8;
 
 // The order in which an instance's domains become work items (LETKF_ORDER_*).
 std::vector<int32_t> domain_order(const Problem& P, int policy);
-// Writes the instance's domain order to its workspace on `s` and waits.
-int upload_order(letkf_handle* h, int policy, hipStream_t s);
+// The per-XCD order re-placed by cost (LETKF_ORDER_BALANCED), or decreasing
+// cost when more than `resident` domains (the workgroups resident at once);
+// cost[l] in Jacobi-sweep units.
+std::vector<int32_t> balanced_order(const Problem& P, const std::vector<double>& cost, int num_cu, int resident);
+// Writes the instance's domain order for `policy` (LETKF_ORDER_BALANCED: from
+// the domains' sweep sums so far) to its workspace on `s` and waits; `used`
+// (nullable) receives the order.
+int upload_order(letkf_handle* h, int policy, hipStream_t s, std::vector<int32_t>* used = nullptr);
+// Same for a given order (checked to be a permutation of the domains).
+int upload_order_vec(letkf_handle* h, const std::vector<int32_t>& order, int policy, hipStream_t s);
 
 // Autotuning of one class's analysis launch over the batch described by the
 // device header `hdr` (instances `insts`, whose domain orders it sets).
 // Fills `res` and returns the chosen grid in *grid_out.
 int tune_class(int cls, const InstDesc* tab, BatchHdr* hdr, int slope_rows, int items,
-               const std::vector<letkf_handle*>& insts, int num_cu, int reps, hipStream_t s,
+               const std::vector<letkf_handle*>& insts, int num_cu, int reps, bool balanced, hipStream_t s,
                letkf_tuning* res, int* grid_out);
 
 }  // namespace letkf

@@ -1286,12 +1286,17 @@ __device__ void analyse_item(AnaSmem<M>& sm, const InstDesc* __restrict__ tab, c
   const int obs_off = I.dom[4 * l + 2], s = I.dom[4 * l + 3];
   const int m = I.m;
   const int cur = I.st->cur;
-  double* dbg = I.dbg ? I.dbg + (size_t)l * (2 * m * m + m + 8) : nullptr;
+  double* dbg = I.dbg ? I.dbg + (size_t)l * (2 * m * m + m + kDbgTail) : nullptr;
   // debug: shader-clock stamps at the phase boundaries (after each phase's barrier)
   auto stamp = [&](int k) {
     if (dbg && threadIdx.x == 0) dbg[2 * m * m + m + k] = (double)clock64();
   };
   stamp(0);
+  if (dbg && threadIdx.x == 0) {  // debug: where the workgroup runs (HW_ID: SE, SH, CU, SIMD; XCC_ID)
+    dbg[2 * m * m + m + 6] = (double)__builtin_amdgcn_s_getreg(4 | (31 << 11));
+    dbg[2 * m * m + m + 7] = (double)__builtin_amdgcn_s_getreg(20 | (31 << 11));
+    dbg[2 * m * m + m + 8] = (double)blockIdx.x;
+  }
 
   if constexpr (P == 0 && M <= 64) gather_C_fp64_mfma<M>(sm, I, obs_off, s, dbg);
   else if constexpr (P == 0) gather_C_fp64<M>(sm, I, obs_off, s, dbg);
@@ -1306,6 +1311,7 @@ __device__ void analyse_item(AnaSmem<M>& sm, const InstDesc* __restrict__ tab, c
   stamp(4);
   if (threadIdx.x == 0) {
     if (I.dbg_sweeps) I.dbg_sweeps[l] = sweeps;
+    atomicAdd(&I.dom_sweeps[l], (unsigned)sweeps);
     if (sweeps >= C::MAX_SWEEPS) atomicAdd(&I.st->unconverged, 1);
     atomicAdd(&I.st->sweeps, (unsigned long long)sweeps);
     atomicAdd(&I.st->solves, 1ull);
@@ -1393,7 +1399,7 @@ __device__ __forceinline__ BigDom big_dom(const InstDesc* __restrict__ tab, cons
 
 __device__ __forceinline__ double* big_dbg(const BigDom& D) {
   const int m = D.I->m;
-  return D.I->dbg ? D.I->dbg + (size_t)D.l * (2 * m * m + m + 8) : nullptr;
+  return D.I->dbg ? D.I->dbg + (size_t)D.l * (2 * m * m + m + kDbgTail) : nullptr;
 }
 
 // 1024 threads: member j = t % 256 of observation quarter t / 256, summed in LDS.

@@ -174,8 +174,9 @@ Layout make_layout(const Problem& P) {
     L.bigv = take((size_t)P.n_dom * 5 * 256 * 8);
     L.bigf = take((size_t)P.n_dom * 4 * 4);
   }
+  L.dom_sweeps = take((size_t)P.n_dom * 4);
   if (P.flags & LETKF_FLAG_DEBUG) {
-    L.dbg = take((size_t)P.n_dom * (2 * m * m + m + 8) * 8);
+    L.dbg = take((size_t)P.n_dom * (2 * m * m + m + kDbgTail) * 8);
     L.dbg_sweeps = take((size_t)P.n_dom * 4);
   } else {
     L.dbg = L.dbg_sweeps = 0;
@@ -423,6 +424,7 @@ int upload_instance(const Problem& P, const Layout& L, char* ws, const double* X
     D.bigv = (double*)(ws + L.bigv);
     D.bigf = (int32_t*)(ws + L.bigf);
   }
+  D.dom_sweeps = (uint32_t*)(ws + L.dom_sweeps);
   D.dbg = L.dbg ? (double*)(ws + L.dbg) : nullptr;
   D.dbg_sweeps = L.dbg_sweeps ? (int32_t*)(ws + L.dbg_sweeps) : nullptr;
   D.st = (InstState*)(ws + L.state);
@@ -457,6 +459,7 @@ int upload_instance(const Problem& P, const Layout& L, char* ws, const double* X
   LETKF_HIP(hipMemcpyAsync(ws + L.state, &S, sizeof(S), hipMemcpyHostToDevice, stream));
   LETKF_HIP(hipMemcpyAsync(ws + L.hdr, &H, sizeof(H), hipMemcpyHostToDevice, stream));
   LETKF_HIP(hipMemcpyAsync(ws + L.ens, ens.data(), ens.size(), hipMemcpyHostToDevice, stream));
+  LETKF_HIP(hipMemsetAsync(ws + L.dom_sweeps, 0, sizeof(uint32_t) * P.n_dom, stream));
   if (L.dbg) LETKF_HIP(hipMemsetAsync(ws + L.dbg, 0, L.total - L.dbg, stream));
   // slopes read before the first frame is staged (letkf_autotune) are zeros, not stale memory
   LETKF_HIP(hipMemsetAsync(ws + L.y, 0, sizeof(double) * P.p(), stream));
@@ -536,8 +539,102 @@ static void launch_domain_analysis(letkf_handle* h, hipStream_t s) {
 
 namespace letkf {
 
-int upload_order(letkf_handle* h, int policy, hipStream_t s) {
-  const std::vector<int32_t> order = domain_order(h->P, policy);
+// The per-XCD order with the domains of each XCD re-placed among its CUs by
+// their measured cost.  With one workgroup per domain and every workgroup
+// resident at once, workgroup b runs on XCD b % 8 and shares its CU with
+// b +- num_cu (the dispatcher fills the CUs of an XCD breadth first; the
+// workgroup indices that ran alone were recorded on the 84x84 map).  A
+// domain's time grows by about 15 % of the other's while it shares a CU, so
+// the domains that take the most sweeps go where they run alone (or with the
+// cheapest company): greedy over decreasing cost, each to the CU of its XCD
+// whose estimated finish, max + 0.15 x (sum - max) of its domains' costs,
+// stays lowest, on a tie the CU that will hold the fewest domains (so the
+// costliest take the CUs nobody shares).  With more domains than workgroups
+// resident at once (`resident`), the workgroups claim the later domains as
+// they finish: then longest first (decreasing cost) balances the tail.
+// cost[l]: domain l's cost in Jacobi-sweep units.
+std::vector<int32_t> balanced_order(const Problem& P, const std::vector<double>& cost, int num_cu, int resident) {
+  const int n = P.n_dom;
+  if (n > resident) {
+    std::vector<int32_t> order(n);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+    return order;
+  }
+  std::vector<int32_t> order = domain_order(P, LETKF_ORDER_XCD);
+  if (num_cu < kXcds || num_cu % kXcds) return order;
+  constexpr double kShare = 0.15;
+  for (int x = 0; x < kXcds; ++x) {
+    // the CUs this XCD's positions fall on (position b: CU b % num_cu), their positions and domains
+    std::vector<std::vector<int>> cu_pos;
+    std::vector<int> slot_of(num_cu, -1);
+    std::vector<int32_t> doms;
+    for (int b = x; b < n; b += kXcds) {
+      int& sl = slot_of[b % num_cu];
+      if (sl < 0) {
+        sl = (int)cu_pos.size();
+        cu_pos.emplace_back();
+      }
+      cu_pos[sl].push_back(b);
+      doms.push_back(order[b]);
+    }
+    std::stable_sort(doms.begin(), doms.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+    const int ncu = (int)cu_pos.size();
+    std::vector<double> mx(ncu, 0.0), sum(ncu, 0.0);
+    std::vector<int> used(ncu, 0);
+    for (int32_t l : doms) {
+      int best = -1;
+      double best_est = 0.0;
+      for (int c = 0; c < ncu; ++c) {
+        if (used[c] == (int)cu_pos[c].size()) continue;
+        const double m2 = std::max(mx[c], cost[l]), s2 = sum[c] + cost[l];
+        const double est = m2 + kShare * (s2 - m2);
+        if (best < 0 || est < best_est - 1e-12 ||
+            (est <= best_est + 1e-12 && cu_pos[c].size() < cu_pos[best].size())) {
+          best = c;
+          best_est = est;
+        }
+      }
+      order[cu_pos[best][used[best]++]] = l;
+      mx[best] = std::max(mx[best], cost[l]);
+      sum[best] += cost[l];
+    }
+  }
+  return order;
+}
+
+int upload_order(letkf_handle* h, int policy, hipStream_t s, std::vector<int32_t>* used) {
+  std::vector<int32_t> order;
+  if (policy == LETKF_ORDER_BALANCED) {
+    // cost of a domain: its sweeps summed over the analyses so far, plus the
+    // rest of its analysis, about 3.5 sweeps' worth each time
+    const int n = h->P.n_dom;
+    std::vector<uint32_t> sw(n);
+    InstState st{};
+    LETKF_HIP(hipMemcpyAsync(sw.data(), h->ws + h->L.dom_sweeps, sizeof(uint32_t) * n, hipMemcpyDeviceToHost, s));
+    LETKF_HIP(hipMemcpyAsync(&st, h->ws + h->L.state, sizeof(st), hipMemcpyDeviceToHost, s));
+    LETKF_HIP(hipStreamSynchronize(s));
+    const double analyses = n > 0 ? (double)st.solves / n : 0.0;
+    std::vector<double> cost(n);
+    for (int l = 0; l < n; ++l) cost[l] = sw[l] + 3.5 * analyses;
+    int num_cu = 0;
+    LETKF_HIP(hipDeviceGetAttribute(&num_cu, hipDeviceAttributeMultiprocessorCount, h->device));
+    order = balanced_order(h->P, cost, num_cu, analysis_blocks_per_cu(h->cls) * num_cu);
+  } else {
+    order = domain_order(h->P, policy);
+  }
+  if (used) *used = order;
+  return upload_order_vec(h, order, policy, s);
+}
+
+int upload_order_vec(letkf_handle* h, const std::vector<int32_t>& order, int policy, hipStream_t s) {
+  // every domain exactly once: the analysis launch maps work items through it
+  std::vector<char> seen(order.size(), 0);
+  if ((int)order.size() != h->P.n_dom) return fail(LETKF_ESTATE, "internal: domain order of the wrong length");
+  for (int32_t l : order) {
+    if (l < 0 || l >= (int32_t)order.size() || seen[l]) return fail(LETKF_ESTATE, "internal: domain order is not a permutation");
+    seen[l] = 1;
+  }
   LETKF_HIP(hipMemcpyAsync(h->ws + h->L.order, order.data(), sizeof(int32_t) * order.size(),
                            hipMemcpyHostToDevice, s));
   LETKF_HIP(hipStreamSynchronize(s));  // `order` is a local
@@ -546,7 +643,8 @@ int upload_order(letkf_handle* h, int policy, hipStream_t s) {
 }
 
 // Candidates: domain order {by decreasing cost, map order, map order in
-// per-XCD chunks} x grid
+// per-XCD chunks, and with `balanced` the per-XCD chunks placed by measured
+// cost} x grid
 // {ceil(k num_cu / 2), k = 1 .. 2 x (analysis workgroups per CU)} plus one
 // workgroup per item, each grid capped at the item count.  Every candidate is timed with HIP events over
 // `reps` analysis launches after one warm-up launch; each launch follows a
@@ -555,10 +653,14 @@ int upload_order(letkf_handle* h, int policy, hipStream_t s) {
 // the runs are repeatable; the instances' states (ring slot, frame and sweep
 // counters) are saved before and restored after.  The per-XCD order keeps
 // neighbouring domains, which share observation and state rows, in one XCD's
-// L2 and so reads less from HBM (about half, measured on the 84x84 map); its
-// best candidate is kept unless another order's is faster by more than 2 %.
+// L2 and so reads less from HBM (about half, measured on the 84x84 map): the
+// best candidate of the per-XCD orders is kept unless another order's is
+// faster by more than 2 %.  The balanced order is placed by the sweeps of the
+// domains so far, the tuning launches included (which all analyse the current
+// frame, so its timing here favours it somewhat); the per-domain sweep sums
+// are restored afterwards like the states.
 int tune_class(int cls, const InstDesc* tab, BatchHdr* hdr, int slope_rows, int items,
-               const std::vector<letkf_handle*>& insts, int num_cu, int reps, hipStream_t s,
+               const std::vector<letkf_handle*>& insts, int num_cu, int reps, bool balanced, hipStream_t s,
                letkf_tuning* res, int* grid_out) {
   if (items <= 0 || insts.empty()) return fail(LETKF_EINVAL, "nothing to tune");
   reps = std::max(1, std::min(reps, 100));
@@ -571,8 +673,13 @@ int tune_class(int cls, const InstDesc* tab, BatchHdr* hdr, int slope_rows, int 
   const int def_grid = std::min(items, bpc * num_cu);
 
   std::vector<InstState> saved(insts.size());
-  for (size_t i = 0; i < insts.size(); ++i)
+  std::vector<std::vector<uint32_t>> saved_sw(insts.size());
+  for (size_t i = 0; i < insts.size(); ++i) {
     LETKF_HIP(hipMemcpyAsync(&saved[i], insts[i]->ws + insts[i]->L.state, sizeof(InstState), hipMemcpyDeviceToHost, s));
+    saved_sw[i].resize(insts[i]->P.n_dom);
+    LETKF_HIP(hipMemcpyAsync(saved_sw[i].data(), insts[i]->ws + insts[i]->L.dom_sweeps,
+                             sizeof(uint32_t) * saved_sw[i].size(), hipMemcpyDeviceToHost, s));
+  }
   LETKF_HIP(hipStreamSynchronize(s));
 
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -595,11 +702,14 @@ int tune_class(int cls, const InstDesc* tab, BatchHdr* hdr, int slope_rows, int 
     return LETKF_OK;
   };
   float best_us = 0.f, def_us = 0.f, xcd_us = 0.f;
-  int best_grid = def_grid, best_order = LETKF_ORDER_COST, xcd_grid = 0, cand = 0;
-  for (int policy : {LETKF_ORDER_COST, LETKF_ORDER_MAP, LETKF_ORDER_XCD}) {
+  int best_grid = def_grid, best_order = LETKF_ORDER_COST, xcd_grid = 0, xcd_order = LETKF_ORDER_XCD, cand = 0;
+  std::vector<int> policies = {LETKF_ORDER_COST, LETKF_ORDER_MAP, LETKF_ORDER_XCD};
+  if (balanced) policies.push_back(LETKF_ORDER_BALANCED);
+  std::vector<std::vector<int32_t>> bal(insts.size());  // the balanced orders as timed
+  for (int policy : policies) {
     if (rc) break;
-    for (letkf_handle* h : insts)
-      if (!rc) rc = upload_order(h, policy, s);
+    for (size_t i = 0; i < insts.size(); ++i)
+      if (!rc) rc = upload_order(insts[i], policy, s, policy == LETKF_ORDER_BALANCED ? &bal[i] : nullptr);
     for (int g : grids) {
       if (rc) break;
       float us = 0.f;
@@ -607,22 +717,30 @@ int tune_class(int cls, const InstDesc* tab, BatchHdr* hdr, int slope_rows, int 
       ++cand;
       if (policy == LETKF_ORDER_COST && g == def_grid) def_us = us;
       if (cand == 1 || us < best_us) { best_us = us; best_grid = g; best_order = policy; }
-      if (policy == LETKF_ORDER_XCD && (xcd_grid == 0 || us < xcd_us)) { xcd_us = us; xcd_grid = g; }
+      const bool local = policy == LETKF_ORDER_XCD || policy == LETKF_ORDER_BALANCED;
+      if (local && (xcd_grid == 0 || us < xcd_us)) { xcd_us = us; xcd_grid = g; xcd_order = policy; }
     }
   }
   if (!rc && xcd_grid > 0 && xcd_us <= 1.02f * best_us) {
     best_us = xcd_us;
     best_grid = xcd_grid;
-    best_order = LETKF_ORDER_XCD;
+    best_order = xcd_order;
   }
-  for (letkf_handle* h : insts)
-    if (!rc) rc = upload_order(h, best_order, s);
-  // the states are put back whatever happened above
+  for (size_t i = 0; i < insts.size(); ++i) {
+    if (rc) break;
+    if (best_order == LETKF_ORDER_BALANCED) rc = upload_order_vec(insts[i], bal[i], best_order, s);
+    else rc = upload_order(insts[i], best_order, s);
+  }
+  // the states and sweep sums are put back whatever happened above
   int rrc = LETKF_OK;
-  for (size_t i = 0; i < insts.size(); ++i)
+  for (size_t i = 0; i < insts.size(); ++i) {
     if (hipMemcpyAsync(insts[i]->ws + insts[i]->L.state, &saved[i], sizeof(InstState), hipMemcpyHostToDevice, s) !=
         hipSuccess)
       rrc = fail(LETKF_EDEVICE, "state restore");
+    if (hipMemcpyAsync(insts[i]->ws + insts[i]->L.dom_sweeps, saved_sw[i].data(), sizeof(uint32_t) * saved_sw[i].size(),
+                       hipMemcpyHostToDevice, s) != hipSuccess)
+      rrc = fail(LETKF_EDEVICE, "sweep sums restore");
+  }
   if (hipStreamSynchronize(s) != hipSuccess) rrc = fail(LETKF_EDEVICE, "hipStreamSynchronize");
   if (!rc) rc = rrc;
   if (e0) (void)hipEventDestroy(e0);
@@ -862,7 +980,7 @@ int letkf_debug_domain(letkf_handle* h, int32_t domain, double* C_out, double* l
   if (rc) return rc;
   if (!(h->P.flags & LETKF_FLAG_DEBUG)) return fail(LETKF_ESTATE, "handle created without LETKF_FLAG_DEBUG");
   if (domain < 0 || domain >= h->P.n_dom) return fail(LETKF_EINVAL, "domain out of range");
-  const size_t m = h->P.m, per = 2 * m * m + m + 8;
+  const size_t m = h->P.m, per = 2 * m * m + m + kDbgTail;
   std::vector<double> buf(per);
   int32_t sw = 0;
   LETKF_HIP(hipMemcpyAsync(buf.data(), h->ws + h->L.dbg + domain * per * 8, per * 8, hipMemcpyDeviceToHost, s));
@@ -878,6 +996,26 @@ int letkf_debug_domain(letkf_handle* h, int32_t domain, double* C_out, double* l
   if (sweeps_out) *sweeps_out = sw;
   if (cycles_out)
     for (int k = 0; k < 5; ++k) cycles_out[k] = buf[2 * m * m + m + k + 1] - buf[2 * m * m + m + k];
+  return LETKF_OK;
+}
+
+int letkf_debug_placement(letkf_handle* h, int32_t domain, uint32_t* hw_id_out, uint32_t* xcc_id_out,
+                          int32_t* workgroup_out, double* start_clock_out, void* stream) {
+  hipStream_t s;
+  int rc = access_stream(h, stream, &s);
+  if (rc) return rc;
+  if (!(h->P.flags & LETKF_FLAG_DEBUG)) return fail(LETKF_ESTATE, "handle created without LETKF_FLAG_DEBUG");
+  if (domain < 0 || domain >= h->P.n_dom) return fail(LETKF_EINVAL, "domain out of range");
+  if (h->P.m > 128) return fail(LETKF_EINVAL, "placement is recorded for ensembles of at most 128 members");
+  const size_t m = h->P.m, per = 2 * m * m + m + kDbgTail;
+  double v[9];
+  LETKF_HIP(hipMemcpyAsync(v, h->ws + h->L.dbg + (domain * per + 2 * m * m + m) * 8, sizeof(v),
+                           hipMemcpyDeviceToHost, s));
+  LETKF_HIP(hipStreamSynchronize(s));
+  if (hw_id_out) *hw_id_out = (uint32_t)v[6];
+  if (xcc_id_out) *xcc_id_out = (uint32_t)v[7];
+  if (workgroup_out) *workgroup_out = (int32_t)v[8];
+  if (start_clock_out) *start_clock_out = v[0];
   return LETKF_OK;
 }
 
@@ -934,7 +1072,7 @@ int letkf_autotune(letkf_handle* h, int32_t reps, letkf_tuning* out, void* strea
   int num_cu = 0;
   LETKF_HIP(hipDeviceGetAttribute(&num_cu, hipDeviceAttributeMultiprocessorCount, h->device));
   int grid = h->ana_grid;
-  if ((rc = tune_class(h->cls, dev_desc(h), dev_hdr(h), h->P.p(), h->P.n_dom, {h}, num_cu, reps,
+  if ((rc = tune_class(h->cls, dev_desc(h), dev_hdr(h), h->P.p(), h->P.n_dom, {h}, num_cu, reps, true,
                        (hipStream_t)stream, out, &grid)))
     return rc;
   h->ana_grid = grid;
@@ -949,7 +1087,7 @@ int letkf_set_tuning(letkf_handle* h, const letkf_tuning* t, void* stream) {
   int rc = check_plain(h);
   if (rc) return rc;
   if (h->cls == kBigClass) return fail(LETKF_ESTATE, "the launch sequence of m > 128 has no tunable shape");
-  if (!t || t->grid < 1 || t->grid > 65535 || t->order < LETKF_ORDER_MAP || t->order > LETKF_ORDER_XCD)
+  if (!t || t->grid < 1 || t->grid > 65535 || t->order < LETKF_ORDER_MAP || t->order > LETKF_ORDER_BALANCED)
     return fail(LETKF_EINVAL, "tuning: grid must be in [1, 65535] and order one of LETKF_ORDER_*");
   if ((rc = upload_order(h, t->order, (hipStream_t)stream))) return rc;
   h->ana_grid = std::min(t->grid, std::max(h->P.n_dom, 1));

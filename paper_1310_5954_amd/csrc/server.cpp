@@ -644,7 +644,7 @@ int letkf_server_autotune(letkf_server* s, int32_t reps, letkf_tuning* out) {
     LETKF_HIP(hipMemcpyAsync(s->dhdr(slot), &H, sizeof(H), hipMemcpyHostToDevice, st));
     LETKF_HIP(hipStreamSynchronize(st));  // H is reused for the next class
     int grid = 0;
-    int rc = tune_class(c, s->table(), s->dhdr(slot), cb.slope_off[cb.n], cb.dom_off[cb.n], insts, s->num_cu, reps,
+    int rc = tune_class(c, s->table(), s->dhdr(slot), cb.slope_off[cb.n], cb.dom_off[cb.n], insts, s->num_cu, reps, false,
                         st, out ? &out[c] : nullptr, &grid);
     if (rc) return rc;
     s->cls_grid[c] = grid;

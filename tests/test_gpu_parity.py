@@ -318,23 +318,26 @@ def test_graph_replay_equals_eager_steps(pistons):
     graph.close()
 
 
-@pytest.mark.parametrize("grid,order", [(1, 0), (7, 1), (128, 2), (375, 2)])
+@pytest.mark.parametrize("grid,order", [(1, 0), (7, 1), (128, 2), (375, 2), (375, 3), (200, 3)])
 def test_persistent_grid_and_order_leave_frames_unchanged(grid, order):
     """The persistent analysis kernel launched with fewer workgroups than
-    domains (they claim the rest through the work counter), in either domain
-    order, gives the same frames bit for bit as the default launch on the
-    84x84 / m = 64 workload (FP64)."""
+    domains (they claim the rest through the work counter), in any domain
+    order (the balanced one placed by the sweeps of a first frame), gives the
+    same frames bit for bit as the default launch on the 84x84 / m = 64
+    workload (FP64)."""
     case = build_case(3)
     pr = Problem.from_case(case)
     ref = Filter(pr, case.X0, precision=FP64)
     f = Filter(pr, case.X0, precision=FP64)
+    y = case.slopes(0)
+    assert np.array_equal(ref.step(y), f.step(y))
     f.set_tuning(grid, order)
-    for k in range(2):
+    for k in range(1, 3):
         y = case.slopes(k)
         assert np.array_equal(ref.step(y), f.step(y)), k
     Xr, fr = ref.get_state()
     Xf, ff = f.get_state()
-    assert fr == ff == 2 and np.array_equal(Xr, Xf)
+    assert fr == ff == 3 and np.array_equal(Xr, Xf)
     assert ref.sweep_stats() == f.sweep_stats()
     ref.close()
     f.close()
@@ -356,8 +359,8 @@ def test_autotune_keeps_state_and_frames():
     t = f.autotune(reps=2)
     n_dom = case.dmap.n_domains
     assert t["candidates"] >= 2 and 1 <= t["grid"] <= n_dom and t["best_us"] > 0, t
-    # the fastest candidate, or the per-XCD order's best within 2 % of it
-    slack = 1.02 if t["order"] == "xcd" else 1.0
+    # the fastest candidate, or the best of the per-XCD orders within 2 % of it
+    slack = 1.02 if t["order"] in ("xcd", "balanced") else 1.0
     assert t["best_us"] <= slack * t["default_us"] + 1e-3, t
     X1, f1 = f.get_state()
     assert f1 == f0 and np.array_equal(X0, X1) and f.sweep_stats() == sw0

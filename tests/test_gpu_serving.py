@@ -45,6 +45,9 @@ def _run_server(cases, frames=FRAMES, drain_each=False, budget=1 << 30, graphs=F
     if grid is not None:                 # persistent analysis with `grid` workgroups, map order
         for cls in range(12):
             srv.set_tuning(cls, grid, order=L.ORDER_XCD if grid > 1 else L.ORDER_MAP)
+        # the balanced order is for plain instances: a batch's placement depends on the batch
+        with pytest.raises(LetkfError):
+            srv.set_tuning(0, grid, order=L.ORDER_BALANCED)
     ys = [[c.slopes(k) for k in range(frames)] for c, _ in cases]
     preds = [[np.empty(c.n_act) for _ in range(frames)] for c, _ in cases]
     for k in range(frames):
