@@ -75,9 +75,10 @@ def analysis_flops(m: int, dmap, sweeps_total: int, solves: int, frames: int) ->
     return frames * fixed + sweeps_total * dots + (sweeps_total - solves) * rots
 
 
-def run_phases(case, W, ys):
+def run_phases(case, W, ys, prec=None):
     """Per-phase cycles of every domain's analysis workgroup (shader-clock
-    stamps of a debug instance, FP64, one frame after W warm-up frames and
+    stamps of a debug instance, FP64 unless `prec` (the plain path in that
+    precision), one frame after W warm-up frames and
     six frames whose per-domain sweep counts are kept), where each domain ran
     (CU, sharing it with other domains or not), and
     the bytes each phase moves, for the bandwidth view of the analysis
@@ -89,7 +90,7 @@ def run_phases(case, W, ys):
     import torch
 
     from paper_1310_5954_amd import FP64, Filter, Problem
-    f = Filter(Problem.from_case(case), case.X0, precision=FP64, device="cuda:0", debug=True)
+    f = Filter(Problem.from_case(case), case.X0, precision=FP64 if prec is None else prec, device="cuda:0", debug=True)
     for k in range(W):
         f.step(ys[k], pred=False)
     m, dm = case.m, case.dmap
@@ -109,6 +110,7 @@ def run_phases(case, W, ys):
     cyc = np.array([[d["cycles"][n] for n in names] for d in dbg])
     sweeps = np.array([d["sweeps"] for d in dbg])
     place = [f.debug_placement(l) for l in range(dm.n_domains)]
+    sub = np.array([list(f.debug_substeps(l).values()) for l in range(dm.n_domains)])
     f.close()
     total = cyc.sum(axis=1)
     clock_hz = total.max() / (ms[1] * 1e-3)
@@ -118,7 +120,9 @@ def run_phases(case, W, ys):
     bytes_update = n_rows * 8 * m * 2
     out = dict(domains=int(dm.n_domains), analysis_ms=round(ms[1], 4), clock_ghz=round(clock_hz / 1e9, 3),
                cycles_mean={n: round(float(cyc[:, i].mean())) for i, n in enumerate(names)},
-               share={n: round(float(cyc[:, i].sum() / cyc.sum()), 4) for i, n in enumerate(names)})
+               share={n: round(float(cyc[:, i].sum() / cyc.sum()), 4) for i, n in enumerate(names)},
+               transform_substeps_mean={n: round(float(sub[:, i].mean()))
+                                        for i, n in enumerate(("U", "wbar", "refine", "T"))})
     # placement: the CU each domain ran on and how many other domains shared it while it ran
     cu_key = [(p["xcd"], p["se"], p["sh"], p["cu"]) for p in place]
     t0 = np.array([p["start_clock"] for p in place])
@@ -575,6 +579,8 @@ def main() -> int:
     ap.add_argument("--instances", type=int, default=4)
     ap.add_argument("--precision", default="bf16", choices=["fp64", "fp32", "bf16"],
                     help="precision path of the serving form (the plain form is always FP64)")
+    ap.add_argument("--phases-precision", default="fp64", choices=["fp64", "fp32", "bf16"],
+                    help="--phases: precision path of the debug instance")
     ap.add_argument("--latency-frames", type=int, default=200)
     ap.add_argument("--plain-only", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -651,7 +657,9 @@ def main() -> int:
     ys = torch.tensor(ys_host, dtype=torch.float64, device="cuda:0")
 
     if args.phases:
-        print(json.dumps(dict(phases=run_phases(case, W, ys), library=build_id())), flush=True)
+        prec = None if args.phases_precision == "fp64" else dict(fp32=FP32, bf16=BF16)[args.phases_precision]
+        print(json.dumps(dict(phases=run_phases(case, W, ys, prec), precision=args.phases_precision,
+                              library=build_id())), flush=True)
         return 0
     if args.serving_only:
         lat = run_serving(case, prec, B, K, W, ys, depth=1)

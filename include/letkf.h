@@ -199,6 +199,12 @@ int letkf_debug_domain(letkf_handle* h, int32_t domain, double* C_out, double* l
 int letkf_debug_placement(letkf_handle* h, int32_t domain, uint32_t* hw_id_out, uint32_t* xcc_id_out,
                           int32_t* workgroup_out, double* start_clock_out, void* stream);
 
+/* Shader-clock cycles of the sub-steps of the wbar/W/T phase of a domain in
+ * the last analysis (needs LETKF_FLAG_DEBUG; m <= 128): cycles_out [4] =
+ * {lambda and U from the columns of L J, wbar = U Lambda^-1 U^T b, its
+ * refinement, T}.  Waits for the stream. */
+int letkf_debug_substeps(letkf_handle* h, int32_t domain, double* cycles_out, void* stream);
+
 /* Number of domains whose eigensolver hit the sweep cap in the last analysis
  * (0 when all converged); waits for the stream. */
 int letkf_unconverged_domains(letkf_handle* h, int32_t* count, void* stream);

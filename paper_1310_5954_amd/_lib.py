@@ -76,6 +76,7 @@ def _sig(lib):
     lib.letkf_debug_domain.argtypes = [P, C.c_int32, pd, pd, pd, C.POINTER(C.c_int32), pd, P]
     lib.letkf_debug_placement.argtypes = [P, C.c_int32, C.POINTER(C.c_uint32), C.POINTER(C.c_uint32),
                                           C.POINTER(C.c_int32), pd, P]
+    lib.letkf_debug_substeps.argtypes = [P, C.c_int32, pd, P]
     lib.letkf_unconverged_domains.argtypes = [P, C.POINTER(C.c_int32), P]
     lib.letkf_kernel_times.argtypes = [P, C.c_int, pd, C.POINTER(C.c_uint64)]
     lib.letkf_sweep_stats.argtypes = [P, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64), P]
@@ -103,7 +104,7 @@ def _sig(lib):
     lib.letkf_build_id.argtypes = []
     lib.letkf_build_id.restype = C.c_char_p
     for name in ("letkf_workspace_size", "letkf_create", "letkf_destroy", "letkf_analyse", "letkf_forecast",
-                 "letkf_step", "letkf_get_state", "letkf_set_state", "letkf_debug_domain", "letkf_debug_placement",
+                 "letkf_step", "letkf_get_state", "letkf_set_state", "letkf_debug_domain", "letkf_debug_placement", "letkf_debug_substeps",
                  "letkf_unconverged_domains", "letkf_kernel_times", "letkf_sweep_stats", "letkf_autotune",
                  "letkf_server_autotune", "letkf_set_tuning", "letkf_server_set_tuning", "letkf_last_means",
                  "letkf_server_create", "letkf_server_add", "letkf_server_remove",

@@ -174,6 +174,15 @@ class Filter:
         return dict(xcd=xcc.value & 0xF, se=(h >> 13) & 0x7, sh=(h >> 12) & 1, cu=(h >> 8) & 0xF,
                     simd=(h >> 4) & 0x3, workgroup=wg.value, start_clock=t0.value)
 
+    def debug_substeps(self, l: int) -> dict:
+        """Cycles of the sub-steps of domain l's wbar/W/T phase in the last
+        analysis (letkf_debug_substeps)."""
+        cyc = np.empty(4)
+        with torch.cuda.device(self.device):
+            L.check(L.lib().letkf_debug_substeps(self.handle, int(l), cyc.ctypes.data_as(_pd), _stream(self.device)),
+                    "letkf_debug_substeps")
+        return dict(zip(("U", "wbar", "refine", "T"), cyc.tolist()))
+
     def kernel_times(self, enable: bool):
         """Accumulated kernel milliseconds {slopes, analysis, merge/forecast} and
         the number of timed calls since the last enable; then (re)enables or stops."""

@@ -59,6 +59,7 @@ struct InstDesc {
   double* bigv;              // m > 128: [n_dom][5][256] b, wbar, lambda, spare
   int32_t* bigf;             // m > 128: [n_dom][4] converged, rounds that rotated, sweeps, spare
   uint32_t* dom_sweeps;      // [n_dom] Jacobi sweeps of each domain, summed over every analysis
+  double* Ascr;              // FP64, m <= 128: [n_dom][M*M] each domain's A (padded size M), for refining wbar
   double* dbg;               // [n_dom][2*m*m + m] C, lambda, T (NULL unless debug)
   int32_t* dbg_sweeps;       // [n_dom]
   InstState* st;
@@ -86,8 +87,9 @@ struct BatchHdr {
 };
 
 // Per-domain debug record (LETKF_FLAG_DEBUG): C [m*m], lambda [m], T [m*m],
-// then kDbgTail slots: shader-clock stamps at the 6 phase boundaries, HW_ID,
-// XCC_ID, the workgroup index that ran the domain.
+// then kDbgTail slots: 0-5 shader-clock stamps at the 6 phase boundaries,
+// 6 HW_ID, 7 XCC_ID, 8 the workgroup index that ran the domain, 10-12 stamps
+// inside the wbar/W/T phase (after U, after wbar, after its refinement).
 constexpr int kDbgTail = 16;
 
 inline int class_of(int padded_m, int prec) {

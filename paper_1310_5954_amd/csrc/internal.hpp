@@ -29,7 +29,7 @@ struct Layout {
   size_t a1, a2, rowptr, col, val, dom, order, est, obs_row, obs_r, mptr, mrow, mw, mdom, pist_op;
   size_t pist_r, pist_c, pist_ptr, pist_row, pist_coef;
   size_t bigA, bigB, bigv, bigf;   // m > 128 only
-  size_t dom_sweeps, dbg, dbg_sweeps;
+  size_t dom_sweeps, Ascr, dbg, dbg_sweeps;
   size_t static_begin, static_end;  // [a1, end of tables) uploaded at create
   size_t total;
 };

@@ -942,73 +942,77 @@ __device__ int jacobi(AnaSmem<M>& sm, int m) {
   return sweeps;
 }
 
+// Products with the M x M matrix in LDS (column c at Bm[c * LDB ..]), by
+// TPC = NT / M lanes per output reduced by DPP: lane group o = tid / TPC,
+// lane part = tid % TPC takes every TPC-th term (two accumulators), and every
+// lane of the group gets the sum.  With the column stride LDB the lanes of a
+// wavefront read distinct banks in both forms.
+// colsum: sum over r of Bm[o LDB + r] v[r]   (U^T v for U in the columns)
+template <int M>
+__device__ __forceinline__ double colsum(const AnaSmem<M>& sm, const double* v, int o, int part) {
+  using C = AnaCfg<M>;
+  constexpr int TPC = C::NT / M, PER = M / TPC, LDB = C::LDB;
+  double t0 = 0.0, t1 = 0.0;
+#pragma unroll 8
+  for (int k = 0; k < PER; k += 2) {
+    t0 = fma(sm.Bm[o * LDB + part + TPC * k], v[part + TPC * k], t0);
+    if (k + 1 < PER) t1 = fma(sm.Bm[o * LDB + part + TPC * (k + 1)], v[part + TPC * (k + 1)], t1);
+  }
+  return group_sum<TPC>(t0 + t1);
+}
+// rowsum: sum over c of Bm[c LDB + o] z[c]   (U z)
+template <int M>
+__device__ __forceinline__ double rowsum(const AnaSmem<M>& sm, const double* z, int o, int part) {
+  using C = AnaCfg<M>;
+  constexpr int TPC = C::NT / M, PER = M / TPC, LDB = C::LDB;
+  double t0 = 0.0, t1 = 0.0;
+#pragma unroll 8
+  for (int k = 0; k < PER; k += 2) {
+    t0 = fma(sm.Bm[(part + TPC * k) * LDB + o], z[part + TPC * k], t0);
+    if (k + 1 < PER) t1 = fma(sm.Bm[(part + TPC * (k + 1)) * LDB + o], z[part + TPC * (k + 1)], t1);
+  }
+  return group_sum<TPC>(t0 + t1);
+}
+
 // One step of iterative refinement of wbar = A^-1 b (FP64 path).  U from the
 // one-sided Jacobi carries rounding of order eps |L| in every column, which the
 // weights 1/lambda of U Lambda^-1 U^T b amplify for the small eigenvalues
 // (wbar relative errors ~1e-10 at m = 100 against ~1e-12 for W).  The
-// residual res = b - A wbar is therefore formed with the exact
-// A = (m-1)/rho I + Y'^T diag(r) Y', applied through the domain's observation
-// rows (staged in LDS chunks as in the gather), and wbar += U Lambda^-1 U^T res.
-// Uses pcol[0] (residual) and pcol[1] (projection), free after the Cholesky.
+// residual res = b - A wbar is therefore formed with A itself, as the gather
+// built it (Ag: the domain's copy of A = (m-1)/rho I + C taken before the
+// Cholesky, M x M, padded identity), not through the eigenvectors, and
+// wbar += U Lambda^-1 U^T res.  Uses pcol[0] (residual) and pcol[1].
 template <int M>
-__device__ void refine_wbar(AnaSmem<M>& sm, const InstDesc& I, int obs_off, int s) {
-  using C = AnaCfg<M>;
-  constexpr int NT = C::NT, KC = C::KC, LDB = C::LDB;
-  constexpr int TPR = NT / KC;  // threads per staged row for its dot product with wbar
-  static_assert(TPR <= 16 && KC <= 32, "row dot products reduce within 16 lanes");
-  double* Xc = (double*)sm.stage;
-  const int m = I.m, tid = phase_tid();
-  const double* Yp = (const double*)I.Yp;
-  const int nobs = 2 * s;
-  double cw = 0.0;  // (Y'^T diag(r) Y' wbar)[tid] for tid < M
-  // thread (qq0 = tid / M, jj = tid % M) stages rows qq0 + e NT / M of each
-  // chunk; the next chunk is loaded into registers while this one is used
-  constexpr int EPT = KC * M / NT;
-  static_assert(KC * M % NT == 0, "whole chunks per thread");
-  const int qq0 = M >= 64 ? __builtin_amdgcn_readfirstlane(tid / M) : tid / M, jj = tid % M;
-  double xv[EPT];
-  auto fetch = [&](int q0) {
-#pragma unroll
-    for (int e = 0; e < EPT; ++e) {
-      const int q = q0 + qq0 + e * (NT / M);
-      xv[e] = (q < nobs && jj < m) ? Yp[(size_t)I.obs_row[2 * obs_off + q] * m + jj] : 0.0;
-    }
-  };
-  fetch(0);
-  for (int q0 = 0; q0 < nobs; q0 += KC) {
-    const int kc = min(KC, nobs - q0);
-#pragma unroll
-    for (int e = 0; e < EPT; ++e) Xc[(qq0 + e * (NT / M)) * M + jj] = xv[e];
-    __syncthreads();
-    if (q0 + KC < nobs) fetch(q0 + KC);
-    {
-      const int qq = tid / TPR, part = tid % TPR;
-      double v = 0.0;
-#pragma unroll 2
-      for (int j = part; j < M; j += TPR) v = fma(Xc[qq * M + j], sm.wbar[j], v);
-      v = group_sum<TPR>(v);
-      if (part == 0) sm.rc[qq] = qq < kc ? I.obs_r[2 * obs_off + q0 + qq] * v : 0.0;
-    }
-    __syncthreads();
-    if (tid < M)
-      for (int qq = 0; qq < kc; ++qq) cw = fma(sm.rc[qq], Xc[qq * M + tid], cw);
-    __syncthreads();
-  }
+__device__ void refine_wbar(AnaSmem<M>& sm, const double* __restrict__ Ag, int m) {
+  constexpr int TPC = AnaCfg<M>::NT / M, PER = M / TPC;
+  const int tid = phase_tid(), o = tid / TPC, part = tid % TPC;
   double* res = sm.pcol[0];
   double* z = sm.pcol[1];
-  if (tid < M) res[tid] = tid < m ? sm.bvec[tid] - fma(I.a_diag, sm.wbar[tid], cw) : 0.0;
-  __syncthreads();
-  if (tid < M) {
-    double t = 0.0;
-#pragma unroll 4
-    for (int r = 0; r < M; ++r) t = fma(sm.Bm[tid * LDB + r], res[r], t);
-    z[tid] = tid < m ? t / sm.lam[tid] : 0.0;
+  __syncthreads();  // wbar complete
+  {
+    // (A wbar)_o: row o of the symmetric A, coalesced over the lanes of a group
+    const double* Ao = Ag + (size_t)o * M;
+    double a[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) a[k] = Ao[part + TPC * k];
+    double t0 = 0.0, t1 = 0.0;
+#pragma unroll
+    for (int k = 0; k < PER; k += 2) {
+      t0 = fma(a[k], sm.wbar[part + TPC * k], t0);
+      if (k + 1 < PER) t1 = fma(a[k + 1], sm.wbar[part + TPC * (k + 1)], t1);
+    }
+    const double t = group_sum<TPC>(t0 + t1);
+    if (part == 0) res[o] = o < m ? sm.bvec[o] - t : 0.0;
   }
   __syncthreads();
-  if (tid < M) {
-    double w = 0.0;
-    for (int c = 0; c < m; ++c) w = fma(sm.Bm[c * LDB + tid], z[c], w);
-    if (tid < m) sm.wbar[tid] += w;
+  {
+    const double t = colsum<M>(sm, res, o, part);
+    if (part == 0) z[o] = o < m ? t / sm.lam[o] : 0.0;
+  }
+  __syncthreads();
+  {
+    const double w = rowsum<M>(sm, z, o, part);
+    if (part == 0 && o < m) sm.wbar[o] += w;
   }
   __syncthreads();
 }
@@ -1024,35 +1028,29 @@ __device__ void refine_wbar(AnaSmem<M>& sm, const InstDesc& I, int obs_off, int 
 // wbar below 1e-8 and 2e-5 on the 15x15 (m = 100) and 84x84 workloads.
 template <int M>
 __device__ void refine_wbar_lj(AnaSmem<M>& sm, int m) {
-  constexpr int LDB = AnaCfg<M>::LDB;
-  const int tid = phase_tid();
+  constexpr int TPC = AnaCfg<M>::NT / M;
+  const int tid = phase_tid(), o = tid / TPC, part = tid % TPC;
   double* z = sm.pcol[0];
   double* res = sm.pcol[1];
-  __syncthreads();  // wbar was written by M threads (two wavefronts at M = 128)
-  if (tid < M) {
-    double t = 0.0;
-#pragma unroll 4
-    for (int r = 0; r < M; ++r) t = fma(sm.Bm[tid * LDB + r], sm.wbar[r], t);
-    z[tid] = tid < m ? sm.lam[tid] * t : 0.0;
+  __syncthreads();  // wbar complete
+  {
+    const double t = colsum<M>(sm, sm.wbar, o, part);
+    if (part == 0) z[o] = o < m ? sm.lam[o] * t : 0.0;
   }
   __syncthreads();
-  if (tid < M) {
-    double t = 0.0;
-    for (int c = 0; c < m; ++c) t = fma(sm.Bm[c * LDB + tid], z[c], t);
-    res[tid] = tid < m ? sm.bvec[tid] - t : 0.0;
+  {
+    const double t = rowsum<M>(sm, z, o, part);
+    if (part == 0) res[o] = o < m ? sm.bvec[o] - t : 0.0;
   }
   __syncthreads();
-  if (tid < M) {
-    double t = 0.0;
-#pragma unroll 4
-    for (int r = 0; r < M; ++r) t = fma(sm.Bm[tid * LDB + r], res[r], t);
-    z[tid] = tid < m ? t / sm.lam[tid] : 0.0;
+  {
+    const double t = colsum<M>(sm, res, o, part);
+    if (part == 0) z[o] = o < m ? t / sm.lam[o] : 0.0;
   }
   __syncthreads();
-  if (tid < M) {
-    double w = 0.0;
-    for (int c = 0; c < m; ++c) w = fma(sm.Bm[c * LDB + tid], z[c], w);
-    if (tid < m) sm.wbar[tid] += w;
+  {
+    const double w = rowsum<M>(sm, z, o, part);
+    if (part == 0 && o < m) sm.wbar[o] += w;
   }
   __syncthreads();
 }
@@ -1061,11 +1059,15 @@ __device__ void refine_wbar_lj(AnaSmem<M>& sm, int m) {
 // (from the converged columns sigma_i u_i of L J)
 // Leaves T row-major in Bm (T[k][j] at Bm[k*LDB + j], zero outside m x m).
 template <int P, int M>
-__device__ void transform(AnaSmem<M>& sm, const InstDesc& I, int obs_off, int s, double* dbg) {
+__device__ void transform(AnaSmem<M>& sm, const InstDesc& I, int l, double* dbg) {
   const int m = I.m;
   using C = AnaCfg<M>;
   constexpr int NT = C::NT, LDB = C::LDB, TM = C::TM;
   const int tid = phase_tid(), ti = tid / 16, tj = tid % 16;
+  // debug: shader-clock stamps inside this phase (after U, after wbar, after its refinement)
+  auto substamp = [&](int k) {
+    if (dbg && threadIdx.x == 0) dbg[2 * m * m + m + 10 + k] = (double)clock64();
+  };
   {
     constexpr int TPC = NT / M;
     const int c = tid / TPC, part = tid % TPC;
@@ -1074,33 +1076,38 @@ __device__ void transform(AnaSmem<M>& sm, const InstDesc& I, int obs_off, int s,
     ss = group_sum<TPC>(ss);
     if (part == 0) {
       sm.lam[c] = ss;          // columns of L J are sigma_i u_i and lambda_i = sigma_i^2
-      sm.nrm[c] = sqrt(ss);
+      sm.nrm[c] = 1.0 / sqrt(ss);
     }
   }
   __syncthreads();
   for (int idx = tid; idx < M * M; idx += NT) {
     const int c = idx / M, r = idx % M;
-    sm.Bm[c * LDB + r] /= sm.nrm[c];
+    sm.Bm[c * LDB + r] *= sm.nrm[c];
   }
   __syncthreads();
-  if (tid < M) {
-    double t = 0.0;
-    for (int r = 0; r < M; ++r) t += sm.Bm[tid * LDB + r] * sm.bvec[r];
-    sm.zv[tid] = tid < m ? t / sm.lam[tid] : 0.0;
-    sm.nrm[tid] = tid < m ? sqrt((double)(m - 1) / sm.lam[tid]) : 0.0;
+  substamp(0);
+  {
+    // wbar = U Lambda^-1 U^T b
+    constexpr int TPC = NT / M;
+    const int o = tid / TPC, part = tid % TPC;
+    const double t = colsum<M>(sm, sm.bvec, o, part);
+    if (part == 0) {
+      sm.zv[o] = o < m ? t / sm.lam[o] : 0.0;
+      sm.nrm[o] = o < m ? sqrt((double)(m - 1) / sm.lam[o]) : 0.0;
+    }
+    __syncthreads();
+    const double w = rowsum<M>(sm, sm.zv, o, part);
+    if (part == 0) sm.wbar[o] = o < m ? w : 0.0;
   }
   __syncthreads();
-  if (tid < M) {
-    double w = 0.0;
-    for (int c = 0; c < m; ++c) w += sm.Bm[c * LDB + tid] * sm.zv[c];
-    sm.wbar[tid] = tid < m ? w : 0.0;
-  }
+  substamp(1);
   if constexpr (P == 0) {
-    refine_wbar<M>(sm, I, obs_off, s);
+    refine_wbar<M>(sm, I.Ascr + (size_t)l * M * M, m);
   } else {
 #pragma unroll 1
     for (int k = 0; k < (P == 1 ? 2 : 3); ++k) refine_wbar_lj<M>(sm, m);
   }
+  substamp(2);
   double tacc[TM][TM];
 #pragma unroll
   for (int x = 0; x < TM; ++x)
@@ -1301,13 +1308,21 @@ __device__ void analyse_item(AnaSmem<M>& sm, const InstDesc* __restrict__ tab, c
   if constexpr (P == 0 && M <= 64) gather_C_fp64_mfma<M>(sm, I, obs_off, s, dbg);
   else if constexpr (P == 0) gather_C_fp64<M>(sm, I, obs_off, s, dbg);
   else gather_C_mfma<P, M>(sm, I, obs_off, s, dbg);
+  if constexpr (P == 0) {
+    // the domain's A, kept for the refinement of wbar (the Cholesky overwrites it)
+    __syncthreads();
+    double* Ag = I.Ascr + (size_t)l * M * M;
+    for (int idx = threadIdx.x; idx < M * M; idx += AnaCfg<M>::NT)
+      Ag[idx] = sm.Bm[(idx / M) * AnaCfg<M>::LDB + idx % M];
+    __syncthreads();
+  }
   stamp(1);
   if constexpr (AnaCfg<M>::TM <= 4) cholesky<M>(sm);
   else cholesky_lds<M>(sm);
   stamp(2);
   const int sweeps = jacobi<P, M>(sm, m);
   stamp(3);
-  transform<P, M>(sm, I, obs_off, s, dbg);
+  transform<P, M>(sm, I, l, dbg);
   stamp(4);
   if (threadIdx.x == 0) {
     if (I.dbg_sweeps) I.dbg_sweeps[l] = sweeps;

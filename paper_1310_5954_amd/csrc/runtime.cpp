@@ -175,6 +175,10 @@ Layout make_layout(const Problem& P) {
     L.bigf = take((size_t)P.n_dom * 4 * 4);
   }
   L.dom_sweeps = take((size_t)P.n_dom * 4);
+  {
+    const size_t M = padded_members(P.m);
+    L.Ascr = (P.prec == LETKF_FP64 && M <= 128) ? take((size_t)P.n_dom * M * M * 8) : 0;
+  }
   if (P.flags & LETKF_FLAG_DEBUG) {
     L.dbg = take((size_t)P.n_dom * (2 * m * m + m + kDbgTail) * 8);
     L.dbg_sweeps = take((size_t)P.n_dom * 4);
@@ -425,6 +429,7 @@ int upload_instance(const Problem& P, const Layout& L, char* ws, const double* X
     D.bigf = (int32_t*)(ws + L.bigf);
   }
   D.dom_sweeps = (uint32_t*)(ws + L.dom_sweeps);
+  D.Ascr = L.Ascr ? (double*)(ws + L.Ascr) : nullptr;
   D.dbg = L.dbg ? (double*)(ws + L.dbg) : nullptr;
   D.dbg_sweeps = L.dbg_sweeps ? (int32_t*)(ws + L.dbg_sweeps) : nullptr;
   D.st = (InstState*)(ws + L.state);
@@ -1016,6 +1021,28 @@ int letkf_debug_placement(letkf_handle* h, int32_t domain, uint32_t* hw_id_out, 
   if (xcc_id_out) *xcc_id_out = (uint32_t)v[7];
   if (workgroup_out) *workgroup_out = (int32_t)v[8];
   if (start_clock_out) *start_clock_out = v[0];
+  return LETKF_OK;
+}
+
+int letkf_debug_substeps(letkf_handle* h, int32_t domain, double* cycles_out, void* stream) {
+  hipStream_t s;
+  int rc = access_stream(h, stream, &s);
+  if (rc) return rc;
+  if (!(h->P.flags & LETKF_FLAG_DEBUG)) return fail(LETKF_ESTATE, "handle created without LETKF_FLAG_DEBUG");
+  if (domain < 0 || domain >= h->P.n_dom) return fail(LETKF_EINVAL, "domain out of range");
+  if (h->P.m > 128) return fail(LETKF_EINVAL, "sub-steps are recorded for ensembles of at most 128 members");
+  const size_t m = h->P.m, per = 2 * m * m + m + kDbgTail;
+  double v[kDbgTail];
+  LETKF_HIP(hipMemcpyAsync(v, h->ws + h->L.dbg + (domain * per + 2 * m * m + m) * 8, sizeof(v),
+                           hipMemcpyDeviceToHost, s));
+  LETKF_HIP(hipStreamSynchronize(s));
+  // stamps 3 (Jacobi done), 10, 11, 12, 4 (wbar/W/T done)
+  if (cycles_out) {
+    cycles_out[0] = v[10] - v[3];
+    cycles_out[1] = v[11] - v[10];
+    cycles_out[2] = v[12] - v[11];
+    cycles_out[3] = v[4] - v[12];
+  }
   return LETKF_OK;
 }
 

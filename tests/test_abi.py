@@ -65,7 +65,8 @@ def test_invalid_dims_and_model_rejected(over, needle):
 
 def test_large_ensembles_fp64_only():
     """m in 129..256 is accepted in FP64 only (the multi-launch analysis), with
-    scratch for two 256 x 256 FP64 matrices per domain, and without pistons."""
+    scratch for two 256 x 256 FP64 matrices per domain, and without pistons.
+    (At m = 128 the FP64 workspace holds one 128 x 128 copy of A per domain.)"""
     b = C.c_size_t()
     pr128, pr200 = _problem(m=128), _problem(m=200)
     args = lambda pr: (C.byref(pr.dims), C.byref(pr.model), C.byref(pr.map))
@@ -73,7 +74,7 @@ def test_large_ensembles_fp64_only():
     s128 = b.value
     assert L.lib().letkf_workspace_size(*args(pr200), L.FP64, 0, C.byref(b)) == L.OK
     n_dom = pr200.map.n_domains
-    assert b.value - s128 >= n_dom * 2 * 256 * 256 * 8
+    assert b.value - (s128 - n_dom * 128 * 128 * 8) >= n_dom * 2 * 256 * 256 * 8
     for prec in (L.FP32, L.BF16):
         assert L.lib().letkf_workspace_size(*args(pr200), prec, 0, C.byref(b)) == L.EINVAL
         assert "needs LETKF_FP64" in L.lib().letkf_last_error().decode()
