@@ -813,6 +813,8 @@ template <int P, int M>
 __device__ int jacobi(AnaSmem<M>& sm, int m) {
   using C = AnaCfg<M>;
   constexpr int NT = C::NT, LDB = C::LDB, TPP = C::TPP;
+  constexpr int PSW = 64 / TPP;  // pair slots per wavefront
+  static_assert(TPP <= 64 && 64 % TPP == 0, "pair slots tile the wavefront");
   const int tid = phase_tid();
   const bool active = tid < C::ACTIVE;
   const int q = tid / TPP, sub = tid % TPP;
@@ -924,7 +926,15 @@ __device__ int jacobi(AnaSmem<M>& sm, int m) {
             }
           }
         }
-        __syncthreads();
+        // Step k + 1 reads a partner column (and its norm) that step k wrote:
+        // the writer's lower column differs from this slot's in the low bits
+        // where k and k + 1 differ, so it is a pair slot of the same wavefront
+        // unless k + 1 is a multiple of PSW, and the LDS operations of one
+        // wavefront take effect in order.  Only those steps need the
+        // workgroup barrier (the group's last step is followed by one anyway);
+        // the others only keep the compiler from moving LDS accesses across.
+        if ((k + 1) % PSW == 0 && k + 1 < (2 << h)) __syncthreads();
+        else __asm__ volatile("" ::: "memory");
       }
       if (active) {
 #pragma unroll
