@@ -1118,34 +1118,82 @@ __device__ void transform(AnaSmem<M>& sm, const InstDesc& I, int l, double* dbg)
     for (int k = 0; k < (P == 1 ? 2 : 3); ++k) refine_wbar_lj<M>(sm, m);
   }
   substamp(2);
-  double tacc[TM][TM];
+  if constexpr (M <= 64) {
+    // T = (U S) U^T on v_mfma_f64_16x16x4f64 (S = diag sqrt((m-1)/lambda), zero
+    // past m): k-steps over 4 columns c of U; wave w owns the same WT x WT block
+    // of 16 x 16 tiles as in the FP64 gather.  Column c of U is Bm[c LDB ..],
+    // so A[i][k] = U[i][c] s_c and B[k][j] = U[j][c] are rows of LDS columns.
+    constexpr int TILES = M / 16, WT = TILES >= 2 ? TILES / 2 : 1;
+    const int w = tid / 64, lane = tid % 64;
+    const bool wave_on = TILES >= 2 || w == 0;
+    const int tr0 = TILES >= 2 ? (w / 2) * WT : 0;
+    const int tc0 = TILES >= 2 ? (w % 2) * WT : 0;
+    f64x4 acc[WT][WT];
 #pragma unroll
-  for (int x = 0; x < TM; ++x)
+    for (int a = 0; a < WT; ++a)
 #pragma unroll
-    for (int y = 0; y < TM; ++y) tacc[x][y] = 0.0;
-  for (int c = 0; c < m; ++c) {
-    const double sc = sm.nrm[c];
-    double ui[TM], uj[TM];
+      for (int b = 0; b < WT; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
+    if (wave_on) {
+#pragma unroll 4
+      for (int ks = 0; ks < M / 4; ++ks) {
+        const int c = ks * 4 + lane / 16;
+        const double sc = sm.nrm[c];
+        double av[WT], bv[WT];
 #pragma unroll
-    for (int x = 0; x < TM; ++x) {
-      ui[x] = sm.Bm[c * LDB + ti + 16 * x] * sc;
-      uj[x] = sm.Bm[c * LDB + tj + 16 * x];
+        for (int a = 0; a < WT; ++a) {
+          av[a] = sm.Bm[c * LDB + (tr0 + a) * 16 + lane % 16] * sc;
+          bv[a] = sm.Bm[c * LDB + (tc0 + a) * 16 + lane % 16];
+        }
+#pragma unroll
+        for (int a = 0; a < WT; ++a)
+#pragma unroll
+          for (int b = 0; b < WT; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+      }
     }
+    __syncthreads();  // every wavefront is done with U before T overwrites it
+    if (wave_on) {
+#pragma unroll
+      for (int a = 0; a < WT; ++a)
+#pragma unroll
+        for (int b = 0; b < WT; ++b)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int i = (tr0 + a) * 16 + lane / 16 + 4 * v, j = (tc0 + b) * 16 + lane % 16;
+            const double t = (i < m && j < m) ? acc[a][b][v] + sm.wbar[i] : 0.0;
+            sm.Bm[i * LDB + j] = t;
+            if (dbg && i < m && j < m) dbg[m * m + m + i * m + j] = t;
+          }
+    }
+  } else {
+    double tacc[TM][TM];
 #pragma unroll
     for (int x = 0; x < TM; ++x)
 #pragma unroll
-      for (int y = 0; y < TM; ++y) tacc[x][y] += ui[x] * uj[y];
-  }
-  __syncthreads();
+      for (int y = 0; y < TM; ++y) tacc[x][y] = 0.0;
+    for (int c = 0; c < m; ++c) {
+      const double sc = sm.nrm[c];
+      double ui[TM], uj[TM];
 #pragma unroll
-  for (int x = 0; x < TM; ++x)
+      for (int x = 0; x < TM; ++x) {
+        ui[x] = sm.Bm[c * LDB + ti + 16 * x] * sc;
+        uj[x] = sm.Bm[c * LDB + tj + 16 * x];
+      }
 #pragma unroll
-    for (int y = 0; y < TM; ++y) {
-      const int i = ti + 16 * x, j = tj + 16 * y;
-      const double v = (i < m && j < m) ? tacc[x][y] + sm.wbar[i] : 0.0;
-      sm.Bm[i * LDB + j] = v;
-      if (dbg && i < m && j < m) dbg[m * m + m + i * m + j] = v;
+      for (int x = 0; x < TM; ++x)
+#pragma unroll
+        for (int y = 0; y < TM; ++y) tacc[x][y] += ui[x] * uj[y];
     }
+    __syncthreads();
+#pragma unroll
+    for (int x = 0; x < TM; ++x)
+#pragma unroll
+      for (int y = 0; y < TM; ++y) {
+        const int i = ti + 16 * x, j = tj + 16 * y;
+        const double v = (i < m && j < m) ? tacc[x][y] + sm.wbar[i] : 0.0;
+        sm.Bm[i * LDB + j] = v;
+        if (dbg && i < m && j < m) dbg[m * m + m + i * m + j] = v;
+      }
+  }
   if (dbg && tid < m) dbg[m * m + tid] = sm.lam[tid];
   __syncthreads();
 }
