@@ -302,7 +302,11 @@ typedef void (*letkf_done_fn)(void* user, uint64_t frame_id, int status);
  * has at most one frame in flight; its frames run in submission order.
  * A batch's analysis runs in the persistent kernel with the class's grid
  * (letkf_server_autotune; by default as many workgroups as the GPU holds at
- * once, at most one per domain item).  flags: 0 or LETKF_SERVER_GRAPHS. */
+ * once, at most one per domain item).  While batches can overlap (more
+ * admitted instances than max_batch, or instances of several classes), the
+ * grid of a class that fits two or more analysis workgroups on a CU is capped
+ * one workgroup per CU below that, so the slope and merge kernels of the
+ * batches beside it start at once.  flags: 0 or LETKF_SERVER_GRAPHS. */
 int letkf_server_create(void* arena, size_t arena_bytes, int32_t max_batch, uint32_t flags,
                         letkf_server** out);
 
@@ -318,7 +322,8 @@ int letkf_server_create(void* arena, size_t arena_bytes, int32_t max_batch, uint
 
 /* Times the analysis launch of every class with admitted instances on their
  * resident data (a batch of up to max_batch of them, as letkf_autotune does
- * for one instance) and keeps the fastest grid per class; the instances'
+ * for one instance) and keeps the fastest grid per class (within the cap on
+ * overlapping batches described at letkf_server_create); the instances'
  * domain orders are set to the fastest order.  out (nullable) has 12 entries,
  * one per class (padded size 16/32/64/128 x precision FP64/FP32/BF16, index
  * precision x 4 + size); classes without instances are zeroed.  Only while

@@ -90,8 +90,8 @@ int upload_order_vec(letkf_handle* h, const std::vector<int32_t>& order, int pol
 // device header `hdr` (instances `insts`, whose domain orders it sets).
 // Fills `res` and returns the chosen grid in *grid_out.
 int tune_class(int cls, const InstDesc* tab, BatchHdr* hdr, int slope_rows, int items,
-               const std::vector<letkf_handle*>& insts, int num_cu, int reps, bool balanced, hipStream_t s,
-               letkf_tuning* res, int* grid_out);
+               const std::vector<letkf_handle*>& insts, int num_cu, int reps, bool balanced, int max_grid,
+               hipStream_t s, letkf_tuning* res, int* grid_out);
 
 }  // namespace letkf
 

@@ -663,19 +663,22 @@ int upload_order_vec(letkf_handle* h, const std::vector<int32_t>& order, int pol
 // faster by more than 2 %.  The balanced order is placed by the sweeps of the
 // domains so far, the tuning launches included (which all analyse the current
 // frame, so its timing here favours it somewhat); the per-domain sweep sums
-// are restored afterwards like the states.
+// are restored afterwards like the states.  max_grid > 0 caps the grids
+// (candidates and default).
 int tune_class(int cls, const InstDesc* tab, BatchHdr* hdr, int slope_rows, int items,
-               const std::vector<letkf_handle*>& insts, int num_cu, int reps, bool balanced, hipStream_t s,
-               letkf_tuning* res, int* grid_out) {
+               const std::vector<letkf_handle*>& insts, int num_cu, int reps, bool balanced, int max_grid,
+               hipStream_t s, letkf_tuning* res, int* grid_out) {
   if (items <= 0 || insts.empty()) return fail(LETKF_EINVAL, "nothing to tune");
   reps = std::max(1, std::min(reps, 100));
   const int bpc = analysis_blocks_per_cu(cls);
   std::vector<int> grids;
   for (int k = 1; k <= 2 * bpc; ++k) grids.push_back(std::min(items, (k * num_cu + 1) / 2));
   grids.push_back(std::min(items, 65535));  // one workgroup per item: the hardware dispatcher balances
+  if (max_grid > 0)
+    for (int& g : grids) g = std::min(g, max_grid);
   std::sort(grids.begin(), grids.end());
   grids.erase(std::unique(grids.begin(), grids.end()), grids.end());
-  const int def_grid = std::min(items, bpc * num_cu);
+  const int def_grid = std::min(items, max_grid > 0 ? std::min(bpc * num_cu, max_grid) : bpc * num_cu);
 
   std::vector<InstState> saved(insts.size());
   std::vector<std::vector<uint32_t>> saved_sw(insts.size());
@@ -1099,7 +1102,7 @@ int letkf_autotune(letkf_handle* h, int32_t reps, letkf_tuning* out, void* strea
   int num_cu = 0;
   LETKF_HIP(hipDeviceGetAttribute(&num_cu, hipDeviceAttributeMultiprocessorCount, h->device));
   int grid = h->ana_grid;
-  if ((rc = tune_class(h->cls, dev_desc(h), dev_hdr(h), h->P.p(), h->P.n_dom, {h}, num_cu, reps, true,
+  if ((rc = tune_class(h->cls, dev_desc(h), dev_hdr(h), h->P.p(), h->P.n_dom, {h}, num_cu, reps, true, 0,
                        (hipStream_t)stream, out, &grid)))
     return rc;
   h->ana_grid = grid;

@@ -141,6 +141,25 @@ struct letkf_server {
   int launch_batch(Batch& b);
   int graph_for(int slot, const GraphKey& k, hipGraphExec_t* out);
   void drop_graphs();
+  // Most analysis workgroups of class c per launch while batches can overlap
+  // (more admitted instances than one batch takes, or several classes): a
+  // class that fits two or more workgroups on a CU leaves one slot per CU free,
+  // so that the slope and merge kernels of the batches beside it start at once
+  // instead of waiting for the analysis to drain (measured with 4 BF16 84x84
+  // instances in batches of 2: grid 512 against 750 gave +9 % frames/s and a
+  // p99 of 0.86 ms against 1.23 ms).  0: no cap.  Caller holds mu.
+  int overlap_cap(int c) const {
+    if (bpc[c] < 2) return 0;
+    int n = 0, cls0 = -1;
+    bool classes = false;
+    for (letkf_handle* h : inst) {
+      if (!h) continue;
+      ++n;
+      if (cls0 < 0) cls0 = h->cls;
+      else if (h->cls != cls0) classes = true;
+    }
+    return (n > max_batch || classes) ? (bpc[c] - 1) * num_cu : 0;
+  }
   // nothing queued, being launched or in flight (caller holds mu)
   bool idle() const {
     if (pending > 0 || inflight > 0) return false;
@@ -223,6 +242,7 @@ int letkf_server::launch_batch(Batch& b) {
   const int rows_s = cb.slope_off[cb.n], rows_a = cb.act_off[cb.n], items = cb.dom_off[cb.n];
   int grid = std::min(items, cls_grid[c] ? cls_grid[c] : bpc[c] * num_cu);
   if (b.grid_cap) grid = std::min(grid, b.grid_cap);
+  if (const int cap = overlap_cap(c)) grid = std::min(grid, cap);
   hipStream_t st = stream[s];
   LETKF_HIP(hipMemcpyAsync(dhdr(s), &H, sizeof(H), hipMemcpyHostToDevice, st));
   if (ytot) LETKF_HIP(hipMemcpyAsync(dy(s), h_y[s], ytot * sizeof(double), hipMemcpyHostToDevice, st));
@@ -645,7 +665,7 @@ int letkf_server_autotune(letkf_server* s, int32_t reps, letkf_tuning* out) {
     LETKF_HIP(hipStreamSynchronize(st));  // H is reused for the next class
     int grid = 0;
     int rc = tune_class(c, s->table(), s->dhdr(slot), cb.slope_off[cb.n], cb.dom_off[cb.n], insts, s->num_cu, reps, false,
-                        st, out ? &out[c] : nullptr, &grid);
+                        s->overlap_cap(c), st, out ? &out[c] : nullptr, &grid);
     if (rc) return rc;
     s->cls_grid[c] = grid;
   }
