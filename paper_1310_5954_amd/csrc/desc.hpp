@@ -44,6 +44,7 @@ struct InstDesc {
   const int32_t* est_act;    // [sum e]
   const int32_t* obs_row;    // [2 sum s]: slope row of each observation (x rows then y rows per domain)
   const double* obs_r;       // [2 sum s]: taper * R^-1 of each observation
+  const double* obs_sr;      // [2 sum s]: its square root (the weight of the staged rows of C)
   const int32_t* mptr;       // [n_act+1] merge CSR: covering (domain, position) entries per actuator
   const int32_t* mrow;       // [2*entries]: Z row of the phi_k copy and of the phi_{k-1} copy
   const double* mw;          // [entries]: merge weight

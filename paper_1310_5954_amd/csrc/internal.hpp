@@ -26,7 +26,7 @@ int hip_fail(hipError_t e, const char* what);
 // Byte offsets of every region of one instance workspace.
 struct Layout {
   size_t desc, state, hdr, ens, Yp, d, Z, y, amean, pmean;
-  size_t a1, a2, rowptr, col, val, dom, order, est, obs_row, obs_r, mptr, mrow, mw, mdom, pist_op;
+  size_t a1, a2, rowptr, col, val, dom, order, est, obs_row, obs_r, obs_sr, mptr, mrow, mw, mdom, pist_op;
   size_t pist_r, pist_c, pist_ptr, pist_row, pist_coef;
   size_t bigA, bigB, bigv, bigf;   // m > 128 only
   size_t dom_sweeps, Ascr, dbg, dbg_sweeps;

@@ -457,15 +457,17 @@ __device__ void gather_C_fp64_mfma(AnaSmem<M>& sm, const InstDesc& I, int obs_of
   static_assert(KCH * M % NT == 0, "whole chunks per thread");
   // M >= 64: a wavefront's lanes share kk0, so the observation's row, r and d are scalar loads
   const int kk0 = M >= 64 ? __builtin_amdgcn_readfirstlane(tid / M) : tid / M, j = tid % M;
-  double yv[EPT], rv[EPT], dv[EPT];
+  // per staged value: y, sqrt(r) (host-computed) and d; fetch() only issues
+  // loads, so they stay in flight across the current chunk's products
+  double yv[EPT], sv[EPT], dv[EPT];
   auto fetch = [&](int q0) {
 #pragma unroll
     for (int e = 0; e < EPT; ++e) {
       const int q = q0 + kk0 + e * (NT / M);
-      yv[e] = rv[e] = dv[e] = 0.0;
+      yv[e] = sv[e] = dv[e] = 0.0;
       if (q < nobs && j < m) {
         const int o = 2 * obs_off + q, row = I.obs_row[o];
-        rv[e] = I.obs_r[o];
+        sv[e] = I.obs_sr[o];
         dv[e] = I.d[row];
         yv[e] = Yp[(size_t)row * m + j];
       }
@@ -475,8 +477,9 @@ __device__ void gather_C_fp64_mfma(AnaSmem<M>& sm, const InstDesc& I, int obs_of
   for (int q0 = 0; q0 < nobs; q0 += KCH) {
 #pragma unroll
     for (int e = 0; e < EPT; ++e) {
-      bpart = fma(rv[e] * dv[e], yv[e], bpart);
-      At[j * LDK + kk0 + e * (NT / M)] = sqrt(rv[e]) * yv[e];
+      const double sy = sv[e] * yv[e];
+      bpart = fma(sv[e] * dv[e], sy, bpart);  // r d y with r = sqrt(r)^2
+      At[j * LDK + kk0 + e * (NT / M)] = sy;
     }
     __syncthreads();
     if (q0 + KCH < nobs) fetch(q0 + KCH);
@@ -555,16 +558,16 @@ __device__ void gather_C_mfma(AnaSmem<M>& sm, const InstDesc& I, int obs_off, in
   static_assert(KCH * M % NT == 0, "whole chunks per thread");
   const int kk0 = M >= 64 ? __builtin_amdgcn_readfirstlane(tid / M) : tid / M, j = tid % M;
   float yv[EPT];
-  double rv[EPT], dv[EPT];
+  double sv[EPT], dv[EPT];  // sqrt(r) (host-computed) and d; fetch() only issues loads
   auto fetch = [&](int q0) {
 #pragma unroll
     for (int e = 0; e < EPT; ++e) {
       const int q = q0 + kk0 + e * (NT / M);
       yv[e] = 0.f;
-      rv[e] = dv[e] = 0.0;
+      sv[e] = dv[e] = 0.0;
       if (q < nobs && j < m) {
         const int o = 2 * obs_off + q, row = I.obs_row[o];
-        rv[e] = I.obs_r[o];
+        sv[e] = I.obs_sr[o];
         dv[e] = I.d[row];
         yv[e] = Yp[(size_t)row * m + j];
       }
@@ -576,11 +579,12 @@ __device__ void gather_C_mfma(AnaSmem<M>& sm, const InstDesc& I, int obs_off, in
     for (int e = 0; e < EPT; ++e) {
       const int kk = kk0 + e * (NT / M);
       const double y = (double)yv[e];
-      bpart += (rv[e] * dv[e]) * y;
-      if constexpr (P == 1) ((float*)sm.stage)[j * C::LDKF + kk] = (float)(sqrt(rv[e]) * y);
+      const double sy = sv[e] * y;
+      bpart += (sv[e] * dv[e]) * sy;  // r d y with r = sqrt(r)^2
+      if constexpr (P == 1) ((float*)sm.stage)[j * C::LDKF + kk] = (float)sy;
       else {
         // split BF16: x = hi + lo with hi = bf16(x), lo = bf16(x - hi)
-        const float xf = (float)(sqrt(rv[e]) * y);
+        const float xf = (float)sy;
         const __bf16 hi = (__bf16)xf;
         ((__bf16*)sm.stage)[j * C::LDKB + kk] = hi;
         ((__bf16*)sm.stage)[M * C::LDKB + j * C::LDKB + kk] = (__bf16)(xf - (float)hi);
@@ -691,11 +695,20 @@ __device__ void cholesky(AnaSmem<M>& sm) {
     const double* pc = sm.pcol[k & 1];
     const double rs = rsqrt(pc[k]);
     double lc[TM], li[TM], lj[TM];
+    // every pivot-column value is loaded unconditionally (one wait for all of
+    // them) and masked afterwards: a load under the mask made the compiler
+    // branch around each one, serialising TM LDS round trips per step
+    double vi[TM], vj[TM];
 #pragma unroll
     for (int x = 0; x < TM; ++x) {
-      lc[x] = pc[ti + 16 * x] * rs;
+      vi[x] = pc[ti + 16 * x];
+      vj[x] = pc[tj + 16 * x];
+    }
+#pragma unroll
+    for (int x = 0; x < TM; ++x) {
+      lc[x] = vi[x] * rs;
       li[x] = ti + 16 * x > k ? lc[x] : 0.0;
-      lj[x] = tj + 16 * x > k ? pc[tj + 16 * x] * rs : 0.0;
+      lj[x] = (tj + 16 * x > k ? 1.0 : 0.0) * (vj[x] * rs);
     }
     const bool own_k = tj == (k & 15);
 #pragma unroll

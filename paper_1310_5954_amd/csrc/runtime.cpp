@@ -147,6 +147,7 @@ Layout make_layout(const Problem& P) {
   L.est = take((size_t)P.sum_e() * 4);
   L.obs_row = take((size_t)2 * P.sum_s() * 4);
   L.obs_r = take((size_t)2 * P.sum_s() * 8);
+  L.obs_sr = take((size_t)2 * P.sum_s() * 8);
   L.mptr = take((n_act + 1) * 4);
   L.mrow = take((size_t)2 * P.sum_e() * 4);
   L.mw = take((size_t)P.sum_e() * 8);
@@ -351,6 +352,9 @@ int upload_instance(const Problem& P, const Layout& L, char* ws, const double* X
   }
   put(blob, B, L.obs_row, obs_row.data(), obs_row.size());
   put(blob, B, L.obs_r, obs_r.data(), obs_r.size());
+  std::vector<double> obs_sr(obs_r.size());
+  for (size_t o = 0; o < obs_r.size(); ++o) obs_sr[o] = std::sqrt(obs_r[o]);
+  put(blob, B, L.obs_sr, obs_sr.data(), obs_sr.size());
   // merge CSR: for each actuator, the (Z row of phi_k, Z row of phi_{k-1}, weight) of every covering domain
   std::vector<int32_t> mptr(n_act + 1, 0);
   for (int q = 0; q < P.sum_e(); ++q) mptr[P.est_act[q] + 1]++;
@@ -411,6 +415,7 @@ int upload_instance(const Problem& P, const Layout& L, char* ws, const double* X
   D.dom = (const int32_t*)(ws + L.dom); D.order = (const int32_t*)(ws + L.order);
   D.est_act = (const int32_t*)(ws + L.est);
   D.obs_row = (const int32_t*)(ws + L.obs_row); D.obs_r = (const double*)(ws + L.obs_r);
+  D.obs_sr = (const double*)(ws + L.obs_sr);
   D.mptr = (const int32_t*)(ws + L.mptr); D.mrow = (const int32_t*)(ws + L.mrow);
   D.mw = (const double*)(ws + L.mw);
   D.mdom = (const int32_t*)(ws + L.mdom);
