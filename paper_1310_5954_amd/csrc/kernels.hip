@@ -1172,7 +1172,8 @@ __device__ void transform(AnaSmem<M>& sm, const InstDesc& I, int l, double* dbg)
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             const int i = (tr0 + a) * 16 + lane / 16 + 4 * v, j = (tc0 + b) * 16 + lane % 16;
-            const double t = (i < m && j < m) ? acc[a][b][v] + sm.wbar[i] : 0.0;
+            // masked by arithmetic (T and wbar are zero and finite past m)
+            const double t = (i < m && j < m ? 1.0 : 0.0) * (acc[a][b][v] + sm.wbar[i]);
             sm.Bm[i * LDB + j] = t;
             if (dbg && i < m && j < m) dbg[m * m + m + i * m + j] = t;
           }
@@ -1282,14 +1283,20 @@ __device__ void update_fp64(AnaSmem<M>& sm, const InstDesc& I, int est_off, int 
 #pragma unroll 4
       for (int ks = 0; ks < M / 4; ++ks) {
         const int k = ks * 4 + lane / 16;
-        const double a = k < m ? Xd[arow * M + k] - xb : 0.0;
+        // loaded unconditionally, masked by arithmetic (the staged rows are
+        // zero past m, so the product is finite): a load under the mask is a
+        // branch and a wait of its own before every MFMA
+        const double a = (k < m ? 1.0 : 0.0) * (Xd[arow * M + k] - xb);
         const double b = sm.Bm[k * LDB + col];
         acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
       }
+      double mean[4];  // read before the stores' branches, so the reads share one wait
+#pragma unroll
+      for (int v = 0; v < 4; ++v) mean[v] = sm.rc[lane / 16 + 4 * v];
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int row = lane / 16 + 4 * v;
-        if (row < kc && col < m) Z[(size_t)(q0 + row) * m + col] = sm.rc[row] + acc[v];
+        if (row < kc && col < m) Z[(size_t)(q0 + row) * m + col] = mean[v] + acc[v];
       }
     }
     __syncthreads();
@@ -1323,7 +1330,7 @@ __device__ void update_mfma(AnaSmem<M>& sm, const InstDesc& I, int est_off, int 
 #pragma unroll 4
         for (int ks = 0; ks < M / 4; ++ks) {
           const int k = ks * 4 + lane / 16;
-          const float a = k < m ? Xf[arow * M + k] - xb : 0.f;
+          const float a = (k < m ? 1.f : 0.f) * (Xf[arow * M + k] - xb);  // masked by arithmetic, as above
           const float b = (float)sm.Bm[k * LDB + col];
           acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
         }
@@ -1333,8 +1340,17 @@ __device__ void update_mfma(AnaSmem<M>& sm, const InstDesc& I, int est_off, int 
 #pragma unroll
           for (int u = 0; u < 8; ++u) {
             const int k = ks * 32 + 8 * (lane / 16) + u;
-            const float xa = (k < m) ? Xf[arow * M + k] - xb : 0.f;
-            const double tv = k < M ? sm.Bm[k * LDB + col] : 0.0;
+            float xa;
+            double tv;
+            if constexpr (M <= 64) {
+              // masked by arithmetic, as above; k runs past M only at M = 16 (the index is clamped)
+              const int kc_ = (M % 32 == 0 || k < M) ? k : M - 1;
+              xa = (k < m ? 1.f : 0.f) * (Xf[arow * M + kc_] - xb);
+              tv = (M % 32 == 0 || k < M ? 1.0 : 0.0) * sm.Bm[kc_ * LDB + col];
+            } else {  // M = 128: the loads in flight at once would not fit in the registers
+              xa = (k < m) ? Xf[arow * M + k] - xb : 0.f;
+              tv = sm.Bm[k * LDB + col];
+            }
             const __bf16 hi = (__bf16)(float)tv;
             a[u] = (__bf16)xa;
             bh[u] = hi;
@@ -1344,10 +1360,13 @@ __device__ void update_mfma(AnaSmem<M>& sm, const InstDesc& I, int est_off, int 
           acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bl, acc, 0, 0, 0);
         }
       }
+      double mean[4];  // read before the stores' branches, so the reads share one wait
+#pragma unroll
+      for (int v = 0; v < 4; ++v) mean[v] = sm.rc[rb * 16 + 4 * (lane / 16) + v];
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int row = rb * 16 + 4 * (lane / 16) + v;
-        if (row < kc && col < m) Z[(size_t)(q0 + row) * m + col] = (float)(sm.rc[row] + (double)acc[v]);
+        if (row < kc && col < m) Z[(size_t)(q0 + row) * m + col] = (float)(mean[v] + (double)acc[v]);
       }
     }
     __syncthreads();
