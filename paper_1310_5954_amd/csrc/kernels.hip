@@ -829,7 +829,7 @@ __device__ int jacobi(AnaSmem<M>& sm, int m) {
   constexpr int PSW = 64 / TPP;  // pair slots per wavefront
   static_assert(TPP <= 64 && 64 % TPP == 0, "pair slots tile the wavefront");
   const int tid = phase_tid();
-  const bool active = tid < C::ACTIVE;
+  const bool active = C::ACTIVE >= NT || tid < C::ACTIVE;
   const int q = tid / TPP, sub = tid % TPP;
   // Rotations are skipped once |b_i.b_j| <= tol |b_i| |b_j|; the W and T this
   // leaves behind are off by about 4 tol (relative).  FP64 path: tol = M eps
@@ -861,6 +861,7 @@ __device__ int jacobi(AnaSmem<M>& sm, int m) {
       for (int r = part; r < M; r += TPC) { const double v = sm.Bm[c * LDB + r]; ss = fma(v, v, ss); }
       ss = group_sum<TPC>(ss);
       if (part == 0) sm.nrm[c] = ss;
+      if (tid == 0) sm.s_rot = 0;  // last read before the previous sweep's closing barrier
       __syncthreads();
       double ahead = 0.0;  // columns ahead of c among this thread's share (exact small integers)
       if (c < m)
@@ -883,10 +884,9 @@ __device__ int jacobi(AnaSmem<M>& sm, int m) {
           for (int k = 0; k < CH; ++k) sm.Bm[rank * LDB + part + TPC * (k0 + k)] = v[k];
         }
         if (part == 0) sm.nrm[rank] = ss;
+        __syncthreads();  // the moved columns and norms before the sweep reads them
       }
     }
-    if (tid == 0) sm.s_rot = 0;
-    __syncthreads();
     bool big = false;
     for (int h = 0; (1 << h) < M; ++h) {
       const int i = ((q >> h) << (h + 1)) | (q & ((1 << h) - 1));
