@@ -39,6 +39,16 @@ __device__ __forceinline__ double philox_normal(uint64_t seed, uint64_t frame, u
   return sqrt(-2.0 * log(u1)) * cospi(2.0 * u2);
 }
 
+// Loads through a pointer into device memory taken from a descriptor.  Such a
+// pointer is generic, and a generic (flat) load also counts against the LDS
+// counter, so every LDS wait (s_waitcnt lgkmcnt) after a prefetch would wait
+// for the prefetch too.  Reading through the global address space makes it a
+// global load that only the vector-memory counter tracks.
+template <typename T>
+__device__ __forceinline__ T gload(const T* p) {
+  return *(const __attribute__((address_space(1))) T*)p;
+}
+
 // Cross-lane moves of a double with DPP (VALU, no LDS round trip).
 template <int CTRL>
 __device__ __forceinline__ double dpp_f64(double v) {
@@ -457,32 +467,45 @@ __device__ void gather_C_fp64_mfma(AnaSmem<M>& sm, const InstDesc& I, int obs_of
   static_assert(KCH * M % NT == 0, "whole chunks per thread");
   // M >= 64: a wavefront's lanes share kk0, so the observation's row, r and d are scalar loads
   const int kk0 = M >= 64 ? __builtin_amdgcn_readfirstlane(tid / M) : tid / M, j = tid % M;
-  // per staged value: y, sqrt(r) (host-computed) and d; fetch() only issues
-  // loads, so they stay in flight across the current chunk's products
-  double yv[EPT], sv[EPT], dv[EPT];
-  auto fetch = [&](int q0) {
+  // per staged value: y, sqrt(r) (host-computed) and d, in two register sets
+  // that alternate between chunks: fetch() only issues loads, into the set
+  // the chunk after this one stages from, so they stay in flight across this
+  // chunk's products (with one set the compiler copied the fetched registers
+  // early, which waited for the loads right after the first product)
+  struct Vals {
+    double y[EPT], s[EPT], d[EPT];
+  };
+  Vals va, vb;
+  const int32_t* obs_row = I.obs_row + 2 * obs_off;
+  const double* obs_sr = I.obs_sr + 2 * obs_off;
+  const double* dvec = I.d;
+  auto fetch = [&](Vals& v, int q0) {
+    // the row indices of every value first, then the loads that depend on them
+    int row[EPT];
 #pragma unroll
     for (int e = 0; e < EPT; ++e) {
       const int q = q0 + kk0 + e * (NT / M);
-      yv[e] = sv[e] = dv[e] = 0.0;
-      if (q < nobs && j < m) {
-        const int o = 2 * obs_off + q, row = I.obs_row[o];
-        sv[e] = I.obs_sr[o];
-        dv[e] = I.d[row];
-        yv[e] = Yp[(size_t)row * m + j];
+      row[e] = (q < nobs && j < m) ? gload(obs_row + q) : -1;
+      v.s[e] = q < nobs ? gload(obs_sr + q) : 0.0;
+    }
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      v.y[e] = v.d[e] = 0.0;
+      if (row[e] >= 0) {
+        v.d[e] = gload(dvec + row[e]);
+        v.y[e] = gload(Yp + (size_t)row[e] * m + j);
       }
     }
   };
-  fetch(0);
-  for (int q0 = 0; q0 < nobs; q0 += KCH) {
+  auto chunk = [&](const Vals& v, Vals& next, int q0) {
 #pragma unroll
     for (int e = 0; e < EPT; ++e) {
-      const double sy = sv[e] * yv[e];
-      bpart = fma(sv[e] * dv[e], sy, bpart);  // r d y with r = sqrt(r)^2
+      const double sy = v.s[e] * v.y[e];
+      bpart = fma(v.s[e] * v.d[e], sy, bpart);  // r d y with r = sqrt(r)^2
       At[j * LDK + kk0 + e * (NT / M)] = sy;
     }
     __syncthreads();
-    if (q0 + KCH < nobs) fetch(q0 + KCH);
+    if (q0 + KCH < nobs) fetch(next, q0 + KCH);
     if (wave_on) {
 #pragma unroll
       for (int ks = 0; ks < KCH / 4; ++ks) {
@@ -499,6 +522,11 @@ __device__ void gather_C_fp64_mfma(AnaSmem<M>& sm, const InstDesc& I, int obs_of
       }
     }
     __syncthreads();
+  };
+  fetch(va, 0);
+  for (int q0 = 0; q0 < nobs; q0 += 2 * KCH) {
+    chunk(va, vb, q0);
+    if (q0 + KCH < nobs) chunk(vb, va, q0 + KCH);
   }
   if (wave_on) {
 #pragma unroll
@@ -559,17 +587,40 @@ __device__ void gather_C_mfma(AnaSmem<M>& sm, const InstDesc& I, int obs_off, in
   const int kk0 = M >= 64 ? __builtin_amdgcn_readfirstlane(tid / M) : tid / M, j = tid % M;
   float yv[EPT];
   double sv[EPT], dv[EPT];  // sqrt(r) (host-computed) and d; fetch() only issues loads
+  const int32_t* obs_row = I.obs_row + 2 * obs_off;
+  const double* obs_sr = I.obs_sr + 2 * obs_off;
+  const double* dvec = I.d;
   auto fetch = [&](int q0) {
+    if constexpr (M <= 64) {
+      // global loads (see gload), the row indices first, then what depends on them
+      int row[EPT];
 #pragma unroll
-    for (int e = 0; e < EPT; ++e) {
-      const int q = q0 + kk0 + e * (NT / M);
-      yv[e] = 0.f;
-      sv[e] = dv[e] = 0.0;
-      if (q < nobs && j < m) {
-        const int o = 2 * obs_off + q, row = I.obs_row[o];
-        sv[e] = I.obs_sr[o];
-        dv[e] = I.d[row];
-        yv[e] = Yp[(size_t)row * m + j];
+      for (int e = 0; e < EPT; ++e) {
+        const int q = q0 + kk0 + e * (NT / M);
+        row[e] = (q < nobs && j < m) ? gload(obs_row + q) : -1;
+        sv[e] = q < nobs ? gload(obs_sr + q) : 0.0;
+      }
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) {
+        yv[e] = 0.f;
+        dv[e] = 0.0;
+        if (row[e] >= 0) {
+          dv[e] = gload(dvec + row[e]);
+          yv[e] = gload(Yp + (size_t)row[e] * m + j);
+        }
+      }
+    } else {  // M = 128: the indices of every value at once would not fit in the registers
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) {
+        const int q = q0 + kk0 + e * (NT / M);
+        yv[e] = 0.f;
+        sv[e] = dv[e] = 0.0;
+        if (q < nobs && j < m) {
+          const int row = gload(obs_row + q);
+          sv[e] = gload(obs_sr + q);
+          dv[e] = gload(dvec + row);
+          yv[e] = gload(Yp + (size_t)row * m + j);
+        }
       }
     }
   };
@@ -1230,15 +1281,35 @@ struct RowChunk {
   __device__ void fetch(const InstDesc& I, int est_off, int e, int cur, int q0) {
     const int m = I.m;
     const T* ens = (const T*)I.ens;
+    const int32_t* est_act = I.est_act + est_off;
     const size_t slot = (size_t)I.n_act * m;
+    if constexpr (M <= 64) {
+      // global loads (see gload), the actuator indices first, then the rows
+      int act[EPT];
 #pragma unroll
-    for (int u = 0; u < EPT; ++u) {
-      const int q = q0 + qq0 + u * (NT / M);
-      v[u] = (T)0;
-      if (q < 2 * e && jj < m) {
-        const int inst = q < e ? cur : (cur ^ 1);
-        const int act = I.est_act[est_off + (q < e ? q : q - e)];
-        v[u] = ens[(size_t)inst * slot + (size_t)act * m + jj];
+      for (int u = 0; u < EPT; ++u) {
+        const int q = q0 + qq0 + u * (NT / M);
+        act[u] = (q < 2 * e && jj < m) ? gload(est_act + (q < e ? q : q - e)) : -1;
+      }
+#pragma unroll
+      for (int u = 0; u < EPT; ++u) {
+        const int q = q0 + qq0 + u * (NT / M);
+        v[u] = (T)0;
+        if (act[u] >= 0) {
+          const int inst = q < e ? cur : (cur ^ 1);
+          v[u] = gload(ens + (size_t)inst * slot + (size_t)act[u] * m + jj);
+        }
+      }
+    } else {  // M = 128: the indices of every value at once would not fit in the registers
+#pragma unroll
+      for (int u = 0; u < EPT; ++u) {
+        const int q = q0 + qq0 + u * (NT / M);
+        v[u] = (T)0;
+        if (q < 2 * e && jj < m) {
+          const int inst = q < e ? cur : (cur ^ 1);
+          const int act = gload(est_act + (q < e ? q : q - e));
+          v[u] = gload(ens + (size_t)inst * slot + (size_t)act * m + jj);
+        }
       }
     }
   }
