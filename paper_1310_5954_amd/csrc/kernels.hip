@@ -48,6 +48,11 @@ template <typename T>
 __device__ __forceinline__ T gload(const T* p) {
   return *(const __attribute__((address_space(1))) T*)p;
 }
+// The same for stores (a flat store also holds up the next LDS wait).
+template <typename T>
+__device__ __forceinline__ void gstore(T* p, T v) {
+  *(__attribute__((address_space(1))) T*)p = v;
+}
 
 // Cross-lane moves of a double with DPP (VALU, no LDS round trip).
 template <int CTRL>
@@ -1068,7 +1073,7 @@ __device__ void refine_wbar(AnaSmem<M>& sm, const double* __restrict__ Ag, int m
     const double* Ao = Ag + (size_t)o * M;
     double a[PER];
 #pragma unroll
-    for (int k = 0; k < PER; ++k) a[k] = Ao[part + TPC * k];
+    for (int k = 0; k < PER; ++k) a[k] = gload(Ao + part + TPC * k);
     double t0 = 0.0, t1 = 0.0;
 #pragma unroll
     for (int k = 0; k < PER; k += 2) {
@@ -1367,7 +1372,7 @@ __device__ void update_fp64(AnaSmem<M>& sm, const InstDesc& I, int est_off, int 
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int row = lane / 16 + 4 * v;
-        if (row < kc && col < m) Z[(size_t)(q0 + row) * m + col] = mean[v] + acc[v];
+        if (row < kc && col < m) gstore(Z + (size_t)(q0 + row) * m + col, mean[v] + acc[v]);
       }
     }
     __syncthreads();
@@ -1437,7 +1442,7 @@ __device__ void update_mfma(AnaSmem<M>& sm, const InstDesc& I, int est_off, int 
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int row = rb * 16 + 4 * (lane / 16) + v;
-        if (row < kc && col < m) Z[(size_t)(q0 + row) * m + col] = (float)(mean[v] + (double)acc[v]);
+        if (row < kc && col < m) gstore(Z + (size_t)(q0 + row) * m + col, (float)(mean[v] + (double)acc[v]));
       }
     }
     __syncthreads();
@@ -1474,7 +1479,7 @@ __device__ void analyse_item(AnaSmem<M>& sm, const InstDesc* __restrict__ tab, c
     __syncthreads();
     double* Ag = I.Ascr + (size_t)l * M * M;
     for (int idx = threadIdx.x; idx < M * M; idx += AnaCfg<M>::NT)
-      Ag[idx] = sm.Bm[(idx / M) * AnaCfg<M>::LDB + idx % M];
+      gstore(Ag + idx, sm.Bm[(idx / M) * AnaCfg<M>::LDB + idx % M]);
     __syncthreads();
   }
   stamp(1);
