@@ -53,6 +53,11 @@ template <typename T>
 __device__ __forceinline__ void gstore(T* p, T v) {
   *(__attribute__((address_space(1))) T*)p = v;
 }
+// ... and for device-scope atomic adds whose result is not used.
+template <typename T>
+__device__ __forceinline__ void gatomic_add(T* p, T v) {
+  (void)__hip_atomic_fetch_add((__attribute__((address_space(1))) T*)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
 // Cross-lane moves of a double with DPP (VALU, no LDS round trip).
 template <int CTRL>
@@ -484,23 +489,29 @@ __device__ void gather_C_fp64_mfma(AnaSmem<M>& sm, const InstDesc& I, int obs_of
   const int32_t* obs_row = I.obs_row + 2 * obs_off;
   const double* obs_sr = I.obs_sr + 2 * obs_off;
   const double* dvec = I.d;
-  auto fetch = [&](Vals& v, int q0) {
-    // the row indices of every value first, then the loads that depend on them
-    int row[EPT];
+  // The row indices run one chunk ahead of the loads that use them, so a
+  // fetch never waits for its own index loads (that wait, before the
+  // chunk's products, exposed their latency on every chunk).
+  int row[EPT];
+  auto fetch_rows = [&](int q0) {
 #pragma unroll
     for (int e = 0; e < EPT; ++e) {
       const int q = q0 + kk0 + e * (NT / M);
       row[e] = (q < nobs && j < m) ? gload(obs_row + q) : -1;
-      v.s[e] = q < nobs ? gload(obs_sr + q) : 0.0;
     }
+  };
+  auto fetch = [&](Vals& v, int q0) {  // chunk q0, whose row indices are in row[]
 #pragma unroll
     for (int e = 0; e < EPT; ++e) {
+      const int q = q0 + kk0 + e * (NT / M);
+      v.s[e] = q < nobs ? gload(obs_sr + q) : 0.0;
       v.y[e] = v.d[e] = 0.0;
       if (row[e] >= 0) {
         v.d[e] = gload(dvec + row[e]);
         v.y[e] = gload(Yp + (size_t)row[e] * m + j);
       }
     }
+    fetch_rows(q0 + KCH);
   };
   auto chunk = [&](const Vals& v, Vals& next, int q0) {
 #pragma unroll
@@ -528,6 +539,7 @@ __device__ void gather_C_fp64_mfma(AnaSmem<M>& sm, const InstDesc& I, int obs_of
     }
     __syncthreads();
   };
+  fetch_rows(0);
   fetch(va, 0);
   for (int q0 = 0; q0 < nobs; q0 += 2 * KCH) {
     chunk(va, vb, q0);
@@ -1277,11 +1289,25 @@ struct RowChunk {
   static constexpr int NT = AnaCfg<M>::NT, EPT = KCH * M / NT;
   static_assert(KCH * M % NT == 0, "whole chunks per thread");
   T v[EPT];
+  int act[EPT];  // M <= 64: actuator indices of the chunk fetched next (see fetch)
   int qq0, jj;
   __device__ RowChunk() {
     const int tid = phase_tid();
     qq0 = M >= 64 ? __builtin_amdgcn_readfirstlane(tid / M) : tid / M;  // wavefront-uniform for M >= 64
     jj = tid % M;
+  }
+  // the actuator indices of chunk q0 (M <= 64; called once for the first chunk,
+  // then by every fetch for the chunk after it)
+  __device__ void fetch_act(const InstDesc& I, int est_off, int e, int q0) {
+    if constexpr (M <= 64) {
+      const int m = I.m;
+      const int32_t* est_act = I.est_act + est_off;
+#pragma unroll
+      for (int u = 0; u < EPT; ++u) {
+        const int q = q0 + qq0 + u * (NT / M);
+        act[u] = (q < 2 * e && jj < m) ? gload(est_act + (q < e ? q : q - e)) : -1;
+      }
+    }
   }
   __device__ void fetch(const InstDesc& I, int est_off, int e, int cur, int q0) {
     const int m = I.m;
@@ -1289,13 +1315,8 @@ struct RowChunk {
     const int32_t* est_act = I.est_act + est_off;
     const size_t slot = (size_t)I.n_act * m;
     if constexpr (M <= 64) {
-      // global loads (see gload), the actuator indices first, then the rows
-      int act[EPT];
-#pragma unroll
-      for (int u = 0; u < EPT; ++u) {
-        const int q = q0 + qq0 + u * (NT / M);
-        act[u] = (q < 2 * e && jj < m) ? gload(est_act + (q < e ? q : q - e)) : -1;
-      }
+      // global loads (see gload); the actuator indices run one chunk ahead
+      // (fetch_act), so a fetch never waits for its own index loads
 #pragma unroll
       for (int u = 0; u < EPT; ++u) {
         const int q = q0 + qq0 + u * (NT / M);
@@ -1305,6 +1326,7 @@ struct RowChunk {
           v[u] = gload(ens + (size_t)inst * slot + (size_t)act[u] * m + jj);
         }
       }
+      fetch_act(I, est_off, e, q0 + KCH);
     } else {  // M = 128: the indices of every value at once would not fit in the registers
 #pragma unroll
       for (int u = 0; u < EPT; ++u) {
@@ -1346,6 +1368,7 @@ __device__ void update_fp64(AnaSmem<M>& sm, const InstDesc& I, int est_off, int 
   double* Xd = (double*)sm.stage;
   double* Z = (double*)I.Z + (size_t)2 * est_off * m;
   RowChunk<M, KR, double> rows;
+  rows.fetch_act(I, est_off, e, 0);
   rows.fetch(I, est_off, e, cur, 0);
   for (int q0 = 0; q0 < 2 * e; q0 += KR) {
     const int kc = min(KR, 2 * e - q0);
@@ -1391,6 +1414,7 @@ __device__ void update_mfma(AnaSmem<M>& sm, const InstDesc& I, int est_off, int 
   float* Xf = (float*)sm.stage;
   float* Z = (float*)I.Z + (size_t)2 * est_off * m;
   RowChunk<M, KR, float> rows;
+  rows.fetch_act(I, est_off, e, 0);
   rows.fetch(I, est_off, e, cur, 0);
   for (int q0 = 0; q0 < 2 * e; q0 += KR) {
     const int kc = min(KR, 2 * e - q0);
@@ -1492,10 +1516,10 @@ __device__ void analyse_item(AnaSmem<M>& sm, const InstDesc* __restrict__ tab, c
   stamp(4);
   if (threadIdx.x == 0) {
     if (I.dbg_sweeps) I.dbg_sweeps[l] = sweeps;
-    atomicAdd(&I.dom_sweeps[l], (unsigned)sweeps);
-    if (sweeps >= C::MAX_SWEEPS) atomicAdd(&I.st->unconverged, 1);
-    atomicAdd(&I.st->sweeps, (unsigned long long)sweeps);
-    atomicAdd(&I.st->solves, 1ull);
+    gatomic_add(&I.dom_sweeps[l], (unsigned)sweeps);
+    if (sweeps >= C::MAX_SWEEPS) gatomic_add(&I.st->unconverged, 1);
+    gatomic_add(&I.st->sweeps, (unsigned long long)sweeps);
+    gatomic_add(&I.st->solves, 1ull);
   }
   if constexpr (P == 0) update_fp64<M>(sm, I, est_off, e, cur);
   else update_mfma<P, M>(sm, I, est_off, e, cur);
