@@ -734,73 +734,80 @@ __device__ void gather_C_mfma(AnaSmem<M>& sm, const InstDesc& I, int obs_off, in
 }
 
 // ---- a6 (first half): Cholesky factor A = L L^T (FP64) ----------------------
-// Each thread keeps its TM x TM entries of A (rows ti + 16x, columns tj + 16y)
-// in registers; only the pivot column travels through LDS, in a double
-// buffer, so every column step costs one barrier.  Step k scales the pivot
-// column by 1/sqrt(a_kk) (one rsqrt), subtracts the outer product of its
-// part below k from the trailing block (entries outside it see a zero factor
-// and stay as they are), stores the scaled column as column k of L, and the
-// owners of column k+1 publish it as the next pivot column.  The upper
-// triangle is never read for the factor and is zeroed when L is written back
-// to Bm for the Jacobi phase.  A is SPD (all eigenvalues >= (m-1)/rho), so
-// every pivot is positive.
+// Right-looking, by panels of 16 columns (M <= 64).  Wavefront 0 factors a
+// panel on its own: lane l holds row c0 + l of the panel's 16 columns, the
+// pivot of column j is read from lane j (readlane), column j is scaled by
+// 1/sqrt(a_jj) (one rsqrt) and the later panel columns take its outer product
+// with the entries L[c0+jj][c0+j] read from the lanes that hold them - no
+// workgroup barrier inside the panel.  Then every wavefront subtracts the
+// panel's rank-16 product from the lower triangle of the trailing matrix, in
+// 16 x 16 tiles on v_mfma_f64_16x16x4f64 (accumulating onto the tile, with
+// the right operand negated).  Two barriers per panel, against one per
+// column for a column-at-a-time form.  L is left column-major in Bm (column c
+// at Bm[c LDB ..]) with its upper triangle zeroed for the Jacobi phase.  A is
+// SPD (all eigenvalues >= (m-1)/rho), so every pivot is positive.
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+  const long long x = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)x, lane);
+  const int hi = __builtin_amdgcn_readlane((int)(x >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 template <int M>
-__device__ void cholesky(AnaSmem<M>& sm) {
+__device__ __forceinline__ void cholesky(AnaSmem<M>& sm) {
   using C = AnaCfg<M>;
-  constexpr int LDB = C::LDB, TM = C::TM;
-  const int tid = phase_tid(), ti = tid / 16, tj = tid % 16;
-  double a[TM][TM];
+  constexpr int LDB = C::LDB, NT = C::NT, NP = M / 16;
+  static_assert(M % 16 == 0 && M <= 64, "panels of 16 rows per lane");
+  const int tid = phase_tid(), w = tid / 64, lane = tid % 64;
+#pragma unroll 1
+  for (int p = 0; p < NP; ++p) {
+    const int c0 = 16 * p;
+    if (w == 0) {
+      const int r = c0 + lane;
+      const bool on = r < M;
+      double a[16];
 #pragma unroll
-  for (int x = 0; x < TM; ++x)
+      for (int jj = 0; jj < 16; ++jj) a[jj] = on ? sm.Bm[(c0 + jj) * LDB + r] : 0.0;
 #pragma unroll
-    for (int y = 0; y < TM; ++y) a[x][y] = sm.Bm[(tj + 16 * y) * LDB + ti + 16 * x];
-  if (tj == 0)
+      for (int j = 0; j < 16; ++j) {
+        const double d = readlane_f64(a[j], j);  // a_jj after the earlier columns
+        const double rs = rsqrt(d);
+        const double lj = lane > j ? a[j] * rs : (lane == j ? d * rs : 0.0);
+        a[j] = lj;
 #pragma unroll
-    for (int x = 0; x < TM; ++x) sm.pcol[0][ti + 16 * x] = a[x][0];
-  __syncthreads();
-#pragma unroll 2
-  for (int k = 0; k < M; ++k) {
-    const double* pc = sm.pcol[k & 1];
-    const double rs = rsqrt(pc[k]);
-    double lc[TM], li[TM], lj[TM];
-    // every pivot-column value is loaded unconditionally (one wait for all of
-    // them) and masked afterwards: a load under the mask made the compiler
-    // branch around each one, serialising TM LDS round trips per step
-    double vi[TM], vj[TM];
-#pragma unroll
-    for (int x = 0; x < TM; ++x) {
-      vi[x] = pc[ti + 16 * x];
-      vj[x] = pc[tj + 16 * x];
-    }
-#pragma unroll
-    for (int x = 0; x < TM; ++x) {
-      lc[x] = vi[x] * rs;
-      li[x] = ti + 16 * x > k ? lc[x] : 0.0;
-      lj[x] = (tj + 16 * x > k ? 1.0 : 0.0) * (vj[x] * rs);
-    }
-    const bool own_k = tj == (k & 15);
-#pragma unroll
-    for (int x = 0; x < TM; ++x)
-#pragma unroll
-      for (int y = 0; y < TM; ++y) {
-        const double u = fma(-li[x], lj[y], a[x][y]);
-        a[x][y] = (own_k && y == (k >> 4)) ? lc[x] : u;
+        for (int jj = j + 1; jj < 16; ++jj) a[jj] = fma(-lj, readlane_f64(lj, jj), a[jj]);
       }
-    const int k1 = k + 1;
-    if (k1 < M && tj == (k1 & 15)) {
+      if (on)
 #pragma unroll
-      for (int y = 0; y < TM; ++y)
-        if (y == (k1 >> 4))
-#pragma unroll
-          for (int x = 0; x < TM; ++x) sm.pcol[k1 & 1][ti + 16 * x] = a[x][y];
+        for (int jj = 0; jj < 16; ++jj) sm.Bm[(c0 + jj) * LDB + r] = a[jj];
     }
     __syncthreads();
+    // trailing lower triangle: tile (R, Cc), R >= Cc, of the blocks past the panel
+    const int nt = NP - p - 1;
+    int t = 0;
+    for (int R = 0; R < nt; ++R)
+      for (int Cc = 0; Cc <= R; ++Cc, ++t) {
+        if (t % 4 != w) continue;
+        const int rb = c0 + 16 * (R + 1), cb = c0 + 16 * (Cc + 1);
+        f64x4 acc;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[v] = sm.Bm[(cb + lane % 16) * LDB + rb + lane / 16 + 4 * v];
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+          const int k = c0 + 4 * ks + lane / 16;
+          const double av = sm.Bm[k * LDB + rb + lane % 16];
+          const double bv = -sm.Bm[k * LDB + cb + lane % 16];
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) sm.Bm[(cb + lane % 16) * LDB + rb + lane / 16 + 4 * v] = acc[v];
+      }
+    __syncthreads();
   }
-#pragma unroll
-  for (int x = 0; x < TM; ++x)
-#pragma unroll
-    for (int y = 0; y < TM; ++y)
-      sm.Bm[(tj + 16 * y) * LDB + ti + 16 * x] = (ti + 16 * x < tj + 16 * y) ? 0.0 : a[x][y];
+  for (int idx = tid; idx < M * M; idx += NT) {
+    const int c = idx / M, r = idx % M;
+    if (r < c) sm.Bm[c * LDB + r] = 0.0;
+  }
   __syncthreads();
 }
 
