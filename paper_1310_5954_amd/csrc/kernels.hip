@@ -849,27 +849,52 @@ __device__ __forceinline__ double rsqrt_1_2(double x) {
   return fma(c0 * e, fma(e, 0.375, 0.5), c0);
 }
 
+// Rotation arithmetic in either precision.  approx_*: the hardware estimates
+// (FP64: relative error ~2^-23; FP32: about 1 ulp); rsqrt_acc: 1/sqrt(x) for x
+// in [1, 2] to the rounding of the type (FP32: the estimate already is).
+__device__ __forceinline__ double approx_rsq(double x) { return __builtin_amdgcn_rsq(x); }
+__device__ __forceinline__ float approx_rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double approx_rcp(double x) { return __builtin_amdgcn_rcp(x); }
+__device__ __forceinline__ float approx_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double rsqrt_acc(double x) { return rsqrt_1_2(x); }
+__device__ __forceinline__ float rsqrt_acc(float x) { return __builtin_amdgcn_rsqf(x); }
+
+// Group sum of a float (same lane patterns as the double form).
+template <int CTRL>
+__device__ __forceinline__ float dpp_f32(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, true));
+}
+template <int G>
+__device__ __forceinline__ float group_sum(float v) {
+  if constexpr (G >= 2) v += dpp_f32<0xB1>(v);
+  if constexpr (G >= 4) v += dpp_f32<0x4E>(v);
+  if constexpr (G >= 8) v += dpp_f32<0x141>(v);
+  if constexpr (G >= 16) v += dpp_f32<0x140>(v);
+  static_assert(G <= 16, "group_sum supports up to 16 lanes");
+  return v;
+}
+
 // True when every pair of columns of the current B satisfies
 // (b_i.b_j)^2 <= tol2 |b_i|^2 |b_j|^2, i.e. when a further sweep would not
 // rotate.  Each thread forms a TM x TM block of B^T B from LDS (the norms are
 // the ones the sweep kept current).  Block-uniform result; ends with a barrier.
-template <int M>
-__device__ bool gram_converged(AnaSmem<M>& sm, double tol2) {
-  using C = AnaCfg<M>;
-  constexpr int LDB = C::LDB, TM = C::TM;
+// B: column c at B[c * LD], element type R.
+template <typename R, int M, int LD>
+__device__ __forceinline__ bool gram_converged(const R* B, const R* nrm, R tol2) {
+  constexpr int TM = AnaCfg<M>::TM;
   const int tid = phase_tid(), ti = tid / 16, tj = tid % 16;
-  double g[TM][TM];
+  R g[TM][TM];
 #pragma unroll
   for (int x = 0; x < TM; ++x)
 #pragma unroll
-    for (int y = 0; y < TM; ++y) g[x][y] = 0.0;
+    for (int y = 0; y < TM; ++y) g[x][y] = 0;
 #pragma unroll 2
   for (int r = 0; r < M; ++r) {
-    double u[TM], v[TM];
+    R u[TM], v[TM];
 #pragma unroll
     for (int x = 0; x < TM; ++x) {
-      u[x] = sm.Bm[(ti + 16 * x) * LDB + r];
-      v[x] = sm.Bm[(tj + 16 * x) * LDB + r];
+      u[x] = B[(ti + 16 * x) * LD + r];
+      v[x] = B[(tj + 16 * x) * LD + r];
     }
 #pragma unroll
     for (int x = 0; x < TM; ++x)
@@ -882,7 +907,7 @@ __device__ bool gram_converged(AnaSmem<M>& sm, double tol2) {
 #pragma unroll
     for (int y = 0; y < TM; ++y) {
       const int i = ti + 16 * x, j = tj + 16 * y;
-      bad |= i < j && g[x][y] * g[x][y] > tol2 * (sm.nrm[i] * sm.nrm[j]);
+      bad |= i < j && g[x][y] * g[x][y] > tol2 * (nrm[i] * nrm[j]);
     }
   return !__syncthreads_or(bad);
 }
@@ -897,33 +922,23 @@ __device__ bool gram_converged(AnaSmem<M>& sm, double tol2) {
 // column) to one with bit h set, and each lower column meets all its
 // partners in that group, so its pair slot keeps it in registers for the
 // whole group and only the partner column goes through LDS each step.
-template <int P, int M>
-__device__ int jacobi(AnaSmem<M>& sm, int m) {
+// The columns are B[c * LD ..] (element type R: FP64, or FP32 for the BF16
+// path), their squared norms nrm[c]; tol is the rotation threshold.
+template <typename R, int M, int LD>
+__device__ __forceinline__ int jacobi_core(AnaSmem<M>& sm, int m, R* B, R* nrm, R tol) {
   using C = AnaCfg<M>;
-  constexpr int NT = C::NT, LDB = C::LDB, TPP = C::TPP;
+  constexpr int NT = C::NT, TPP = C::TPP;
   constexpr int PSW = 64 / TPP;  // pair slots per wavefront
   static_assert(TPP <= 64 && 64 % TPP == 0, "pair slots tile the wavefront");
   const int tid = phase_tid();
   const bool active = C::ACTIVE >= NT || tid < C::ACTIVE;
   const int q = tid / TPP, sub = tid % TPP;
-  // Rotations are skipped once |b_i.b_j| <= tol |b_i| |b_j|; the W and T this
-  // leaves behind are off by about 4 tol (relative).  FP64 path: tol = 32 M
-  // eps (2.3e-13 at M = 64).  The rounding of the eigenvectors (eps |L| per
-  // column, amplified by the conditioning) leaves W about 2e-12 off whatever
-  // the tolerance, so this one adds nothing measurable: over the 375 domains
-  // of the 84x84 map, W stays within 2.05e-12 of the exact one against 2.00e-12
-  // at tol = M eps, in at most 8 sweeps instead of 11 (CPU replay).  The FP32
-  // and BF16 paths form C with relative errors ~5e-8 and ~4e-6, which put
-  // their T about 6e-5 and 4e-3 from the FP64 result whatever the eigensolver
-  // does; their tolerances, 1e-6 and 1e-4, keep the eigensolver's share an
-  // order of magnitude below that.
-  const double tol = P == 0 ? 32.0 * (double)M * 1.1102230246251565e-16 : (P == 1 ? 1e-6 : 1e-4);
-  const double tol2 = tol * tol;
+  const R tol2 = tol * tol;
   // Once no rotation of a sweep exceeded this cosine, the columns are close
   // enough that the next sweep is most likely the one that finds nothing to
   // do; the Gram test decides that in a fraction of a sweep's cost.
-  const double trig = tol * 100.0 > 1e-7 ? tol * 100.0 : 1e-7;
-  const double trig2 = trig * trig;
+  const R trig = tol * (R)100 > (R)1e-7 ? tol * (R)100 : (R)1e-7;
+  const R trig2 = trig * trig;
   int sweeps = 0;
   for (; sweeps < C::MAX_SWEEPS;) {
     {
@@ -936,84 +951,84 @@ __device__ int jacobi(AnaSmem<M>& sm, int m) {
       // move, in passes of at most 16 values per thread, only when the order
       // changed (late sweeps mostly keep it).
       constexpr int PER = M / TPC, CH = PER < 16 ? PER : 16;
-      double ss = 0.0;
-      for (int r = part; r < M; r += TPC) { const double v = sm.Bm[c * LDB + r]; ss = fma(v, v, ss); }
+      R ss = 0;
+      for (int r = part; r < M; r += TPC) { const R v = B[c * LD + r]; ss = fma(v, v, ss); }
       ss = group_sum<TPC>(ss);
-      if (part == 0) sm.nrm[c] = ss;
+      if (part == 0) nrm[c] = ss;
       if (tid == 0) sm.s_rot = 0;  // last read before the previous sweep's closing barrier
       __syncthreads();
-      double ahead = 0.0;  // columns ahead of c among this thread's share (exact small integers)
+      R ahead = 0;  // columns ahead of c among this thread's share (exact small integers)
       if (c < m)
         for (int c2 = part; c2 < m; c2 += TPC) {
-          const double n2 = sm.nrm[c2];
-          ahead += (n2 > ss || (n2 == ss && c2 < c)) ? 1.0 : 0.0;
+          const R n2 = nrm[c2];
+          ahead += (n2 > ss || (n2 == ss && c2 < c)) ? (R)1 : (R)0;
         }
       ahead = group_sum<TPC>(ahead);
       const int rank = c < m ? (int)ahead : c;
       if (__syncthreads_or(rank != c)) {
         for (int k0 = 0; k0 < PER; k0 += CH) {
-          double v[CH];
+          R v[CH];
 #pragma unroll
-          for (int k = 0; k < CH; ++k) v[k] = sm.Bm[c * LDB + part + TPC * (k0 + k)];
+          for (int k = 0; k < CH; ++k) v[k] = B[c * LD + part + TPC * (k0 + k)];
           // every read of this pass's rows (rows TPC k0 .. TPC (k0 + CH) - 1, which no
           // other pass touches) is done before any column moves; the sweep reads
           // the moved columns after the barrier that follows
           __syncthreads();
 #pragma unroll
-          for (int k = 0; k < CH; ++k) sm.Bm[rank * LDB + part + TPC * (k0 + k)] = v[k];
+          for (int k = 0; k < CH; ++k) B[rank * LD + part + TPC * (k0 + k)] = v[k];
         }
-        if (part == 0) sm.nrm[rank] = ss;
+        if (part == 0) nrm[rank] = ss;
         __syncthreads();  // the moved columns and norms before the sweep reads them
       }
     }
     bool big = false;
     for (int h = 0; (1 << h) < M; ++h) {
       const int i = ((q >> h) << (h + 1)) | (q & ((1 << h) - 1));
-      double xi[C::RPT];
-      double al = 0.0;
+      R xi[C::RPT];
+      R al = 0;
       if (active) {
 #pragma unroll
-        for (int t = 0; t < C::RPT; ++t) xi[t] = sm.Bm[i * LDB + sub + t * TPP];
-        al = sm.nrm[i];
+        for (int t = 0; t < C::RPT; ++t) xi[t] = B[i * LD + sub + t * TPP];
+        al = nrm[i];
       }
       for (int k = 1 << h; k < (2 << h); ++k) {
         if (active) {
           const int jj = i ^ k;
-          double* bj = sm.Bm + jj * LDB;
-          const double be = sm.nrm[jj];
-          double xj[C::RPT];
-          double g0 = 0.0, g1 = 0.0;
+          R* bj = B + jj * LD;
+          const R be = nrm[jj];
+          R xj[C::RPT];
+          R g0 = 0, g1 = 0;
 #pragma unroll
           for (int t = 0; t < C::RPT; ++t) {
             xj[t] = bj[sub + t * TPP];
             if (t & 1) g1 = fma(xi[t], xj[t], g1);
             else g0 = fma(xi[t], xj[t], g0);
           }
-          const double gsum = group_sum<TPP>(g0 + g1);
-          const double ab = al * be;
+          const R gsum = group_sum<TPP>(g0 + g1);
+          const R ab = al * be;
           if (gsum * gsum > tol2 * ab) {
             big |= gsum * gsum > trig2 * ab;
             // t = tan(theta), the smaller root of t^2 + 2 zeta t - 1 = 0 with
             // zeta = (be - al) / (2 gsum), written without the quotient zeta.
-            // c = (1 + t^2)^(-1/2) (correctly rounded rsqrt) keeps
-            // c^2 + s^2 = 1 to rounding for whatever t is used, so t itself
-            // comes from the hardware's approximate rsq / rcp: its error only
-            // changes how far this rotation reduces gsum, never orthogonality.
-            const double dd = be - al, g2 = 2.0 * gsum;
-            const double q2 = fma(dd, dd, g2 * g2);
-            const double den = fma(q2, __builtin_amdgcn_rsq(q2), fabs(dd));
-            const double t = copysign(1.0, dd) * g2 * __builtin_amdgcn_rcp(den);
-            const double c = rsqrt_1_2(fma(t, t, 1.0));
-            const double sn = c * t;
+            // c = (1 + t^2)^(-1/2) to the rounding of R keeps c^2 + s^2 = 1 to
+            // rounding for whatever t is used, so t itself comes from the
+            // hardware's approximate rsq / rcp: its error only changes how far
+            // this rotation reduces gsum, never orthogonality.
+            const R dd = be - al, g2 = (R)2 * gsum;
+            const R q2 = fma(dd, dd, g2 * g2);
+            const R den = fma(q2, approx_rsq(q2), fabs(dd));
+            const R t = copysign((R)1, dd) * g2 * approx_rcp(den);
+            const R c = rsqrt_acc(fma(t, t, (R)1));
+            const R sn = c * t;
 #pragma unroll
             for (int u = 0; u < C::RPT; ++u) {
-              const double a = xi[u];
+              const R a = xi[u];
               xi[u] = c * a - sn * xj[u];
               bj[sub + u * TPP] = sn * a + c * xj[u];
             }
             al -= t * gsum;
             if (sub == 0) {
-              sm.nrm[jj] = be + t * gsum;
+              nrm[jj] = be + t * gsum;
               sm.s_rot = 1;
             }
           }
@@ -1030,8 +1045,8 @@ __device__ int jacobi(AnaSmem<M>& sm, int m) {
       }
       if (active) {
 #pragma unroll
-        for (int t = 0; t < C::RPT; ++t) sm.Bm[i * LDB + sub + t * TPP] = xi[t];
-        if (sub == 0) sm.nrm[i] = al;
+        for (int t = 0; t < C::RPT; ++t) B[i * LD + sub + t * TPP] = xi[t];
+        if (sub == 0) nrm[i] = al;
       }
       __syncthreads();
     }
@@ -1039,9 +1054,70 @@ __device__ int jacobi(AnaSmem<M>& sm, int m) {
     const int any = sm.s_rot;
     const int any_big = __syncthreads_or(big);
     if (!any) break;
-    if (!any_big && gram_converged<M>(sm, tol2)) break;
+    if (!any_big && gram_converged<R, M, LD>(B, nrm, tol2)) break;
   }
   return sweeps;
+}
+
+// Rotations are skipped once |b_i.b_j| <= tol |b_i| |b_j|; the W and T this
+// leaves behind are off by about 4 tol (relative).  FP64 path: tol = 32 M eps
+// (2.3e-13 at M = 64).  The rounding of the eigenvectors (eps |L| per column,
+// amplified by the conditioning) leaves W about 2e-12 off whatever the
+// tolerance, so this one adds nothing measurable: over the 375 domains of the
+// 84x84 map, W stays within 2.05e-12 of the exact one against 2.00e-12 at
+// tol = M eps, in at most 8 sweeps instead of 11 (CPU replay).  The FP32 and
+// BF16 paths form C with relative errors ~5e-8 and ~4e-6, which put their T
+// about 6e-5 and 4e-3 from the FP64 result whatever the eigensolver does;
+// their tolerances, 1e-6 and 1e-4, keep the eigensolver's share an order of
+// magnitude below that.  At 1e-4 the rotations themselves can run in FP32
+// (rounding ~6e-8 per rotation, a converged off-diagonal of a few 1e-6), which
+// the BF16 path does for M <= 64: L is rounded to FP32 in place (float columns
+// at stride M + TPP inside the double storage), rotated, and widened back.
+template <int P, int M>
+__device__ int jacobi(AnaSmem<M>& sm, int m) {
+  using C = AnaCfg<M>;
+  if constexpr (P == 2 && M <= 64) {
+    constexpr int NT = C::NT, LDB = C::LDB, LDF = M + C::TPP, PER = M * M / NT;
+    static_assert(M * LDF <= 2 * M * LDB && (M * M) % NT == 0, "float columns fit in the double storage");
+    float* Bf = reinterpret_cast<float*>(sm.Bm);
+    float* nf = reinterpret_cast<float*>(sm.nrm);
+    const int tid = phase_tid();
+    {
+      float v[PER];
+#pragma unroll
+      for (int k = 0; k < PER; ++k) {
+        const int idx = tid + NT * k;
+        v[k] = (float)sm.Bm[(idx / M) * LDB + idx % M];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < PER; ++k) {
+        const int idx = tid + NT * k;
+        Bf[(idx / M) * LDF + idx % M] = v[k];
+      }
+      __syncthreads();
+    }
+    const int sweeps = jacobi_core<float, M, LDF>(sm, m, Bf, nf, 1e-4f);
+    {
+      float v[PER];
+#pragma unroll
+      for (int k = 0; k < PER; ++k) {
+        const int idx = tid + NT * k;
+        v[k] = Bf[(idx / M) * LDF + idx % M];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < PER; ++k) {
+        const int idx = tid + NT * k;
+        sm.Bm[(idx / M) * LDB + idx % M] = (double)v[k];
+      }
+      __syncthreads();
+    }
+    return sweeps;
+  } else {
+    const double tol = P == 0 ? 32.0 * (double)M * 1.1102230246251565e-16 : (P == 1 ? 1e-6 : 1e-4);
+    return jacobi_core<double, M, C::LDB>(sm, m, sm.Bm, sm.nrm, tol);
+  }
 }
 
 // Products with the M x M matrix in LDS (column c at Bm[c * LDB ..]), by
