@@ -10,8 +10,9 @@ Two forms serve the same load, --instances B resident AO instances
 (independent ensembles, default 4) in a closed loop: each instance releases
 its next frame when its previous one is done.
   serving  the server batches the pending frames of all instances into shared
-           launches (BF16 contractions + FP64 eigensolve by default).  This is
-           `value` (aggregate frames/s) and p50/p99 (submit -> callback).
+           launches (by default BF16 contractions, FP32 Jacobi rotations and
+           FP64 Cholesky / w-bar / T).  This is `value` (aggregate frames/s)
+           and p50/p99 (submit -> callback).
   plain    the plain per-frame FP64 path (letkf_step, one frame per launch
            sequence) serves the same instances one frame at a time; its
            frames/s and p50/p99 are reported beside, together with the
@@ -689,7 +690,7 @@ def main() -> int:
                      graph_replay=dict(frames_per_s=round(graph["fps"], 2), p50_us=round(graph["p50_us"], 1),
                                        p99_us=round(graph["p99_us"], 1)),
                      tuning=plain["tuning"])
-    dname = {FP64: "f64", FP32: "f32", BF16: "bf16+f64"}
+    dname = {FP64: "f64", FP32: "f32", BF16: "bf16+f32+f64"}
     if args.plain_only:
         value, p50, p99, dtype, path = plain["fps"], plain["p50_us"], plain["p99_us"], "f64", "plain"
         ms_per_step = 1e3 / plain["fps"]

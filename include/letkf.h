@@ -78,7 +78,9 @@ extern "C" {
  * LETKF_FP32: FP32 ensemble; C and the update contraction on FP32 MFMA
  *             with FP32 accumulation; FP64 eigensolve, wbar and W.
  * LETKF_BF16: FP32 ensemble; BF16 operands for C and the update on MFMA with
- *             FP32 accumulation; FP64 eigensolve, wbar and W.             */
+ *             FP32 accumulation; FP64 Cholesky, wbar and W; the Jacobi
+ *             rotations in FP32 for m <= 64 (rotation tolerance 1e-4, far
+ *             above FP32 rounding), in FP64 above.                         */
 #define LETKF_FP64 0
 #define LETKF_FP32 1
 #define LETKF_BF16 2

@@ -217,7 +217,7 @@ def test_cfg3_full_size_fp32():
 
 
 def test_cfg3_full_size_bf16():
-    """BF16 MFMA contractions, FP64 eigensolve: per-result errors."""
+    """BF16 MFMA contractions, FP32 Jacobi rotations: per-result errors."""
     case = build_case(3)
     X, k = oracle_spin_up(case, 2)
     err = _check_step(case, X, k, BF16, debug=True, check_domains=range(0, case.dmap.n_domains, 11))
