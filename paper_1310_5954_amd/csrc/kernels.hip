@@ -1071,48 +1071,56 @@ __device__ __forceinline__ int jacobi_core(AnaSmem<M>& sm, int m, R* B, R* nrm, 
 // their tolerances, 1e-6 and 1e-4, keep the eigensolver's share an order of
 // magnitude below that.  At 1e-4 the rotations themselves can run in FP32
 // (rounding ~6e-8 per rotation, a converged off-diagonal of a few 1e-6), which
-// the BF16 path does for M <= 64: L is rounded to FP32 in place (float columns
-// at stride M + TPP inside the double storage), rotated, and widened back.
+// the BF16 path does: L is rounded to FP32 in place (float columns at stride
+// M + TPP inside the double storage), rotated, and widened back.
 template <int P, int M>
 __device__ int jacobi(AnaSmem<M>& sm, int m) {
   using C = AnaCfg<M>;
-  if constexpr (P == 2 && M <= 64) {
-    constexpr int NT = C::NT, LDB = C::LDB, LDF = M + C::TPP, PER = M * M / NT;
-    static_assert(M * LDF <= 2 * M * LDB && (M * M) % NT == 0, "float columns fit in the double storage");
+  if constexpr (P == 2) {
+    // In-place width change by chunks of CC columns (at most 16 values per
+    // thread in flight).  A float column c ends at or below the start of
+    // double column c + 1 (LDF <= 2 LDB and M <= 2 LDB), so narrowing in
+    // increasing column order, and widening in decreasing order, never
+    // overwrites a value that a later chunk still has to read; each chunk
+    // reads everything before its barrier and writes after it.
+    constexpr int NT = C::NT, LDB = C::LDB, LDF = M + C::TPP;
+    constexpr int CC = M * M / NT <= 16 ? M : 16 * NT / M, PER = CC * M / NT;
+    static_assert(LDF <= 2 * LDB && M <= 2 * LDB && M % CC == 0 && (CC * M) % NT == 0,
+                  "float columns fit in the double storage");
     float* Bf = reinterpret_cast<float*>(sm.Bm);
     float* nf = reinterpret_cast<float*>(sm.nrm);
     const int tid = phase_tid();
-    {
+    for (int c0 = 0; c0 < M; c0 += CC) {
       float v[PER];
 #pragma unroll
       for (int k = 0; k < PER; ++k) {
-        const int idx = tid + NT * k;
-        v[k] = (float)sm.Bm[(idx / M) * LDB + idx % M];
+        const int idx = tid + NT * k, c = c0 + idx / M, r = idx % M;
+        v[k] = (float)sm.Bm[c * LDB + r];
       }
       __syncthreads();
 #pragma unroll
       for (int k = 0; k < PER; ++k) {
-        const int idx = tid + NT * k;
-        Bf[(idx / M) * LDF + idx % M] = v[k];
+        const int idx = tid + NT * k, c = c0 + idx / M, r = idx % M;
+        Bf[c * LDF + r] = v[k];
       }
-      __syncthreads();
     }
+    __syncthreads();
     const int sweeps = jacobi_core<float, M, LDF>(sm, m, Bf, nf, 1e-4f);
-    {
+    for (int c0 = M - CC; c0 >= 0; c0 -= CC) {
       float v[PER];
 #pragma unroll
       for (int k = 0; k < PER; ++k) {
-        const int idx = tid + NT * k;
-        v[k] = Bf[(idx / M) * LDF + idx % M];
+        const int idx = tid + NT * k, c = c0 + idx / M, r = idx % M;
+        v[k] = Bf[c * LDF + r];
       }
       __syncthreads();
 #pragma unroll
       for (int k = 0; k < PER; ++k) {
-        const int idx = tid + NT * k;
-        sm.Bm[(idx / M) * LDB + idx % M] = (double)v[k];
+        const int idx = tid + NT * k, c = c0 + idx / M, r = idx % M;
+        sm.Bm[c * LDB + r] = (double)v[k];
       }
-      __syncthreads();
     }
+    __syncthreads();
     return sweeps;
   } else {
     const double tol = P == 0 ? 32.0 * (double)M * 1.1102230246251565e-16 : (P == 1 ? 1e-6 : 1e-4);
