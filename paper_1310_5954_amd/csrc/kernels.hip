@@ -734,9 +734,9 @@ __device__ void gather_C_mfma(AnaSmem<M>& sm, const InstDesc& I, int obs_off, in
 }
 
 // ---- a6 (first half): Cholesky factor A = L L^T (FP64) ----------------------
-// Right-looking, by panels of 16 columns (M <= 64).  Wavefront 0 factors a
-// panel on its own: lane l holds row c0 + l of the panel's 16 columns, the
-// pivot of column j is read from lane j (readlane), column j is scaled by
+// Right-looking, by panels of 16 columns.  Wavefront 0 factors a panel on its
+// own: lane l holds rows c0 + l (and c0 + 64 + l at M = 128) of the panel's
+// 16 columns, the pivot of column j is read from lane j (readlane), column j is scaled by
 // 1/sqrt(a_jj) (one rsqrt) and the later panel columns take its outer product
 // with the entries L[c0+jj][c0+j] read from the lanes that hold them - no
 // workgroup barrier inside the panel.  Then every wavefront subtracts the
@@ -757,29 +757,45 @@ template <int M>
 __device__ __forceinline__ void cholesky(AnaSmem<M>& sm) {
   using C = AnaCfg<M>;
   constexpr int LDB = C::LDB, NT = C::NT, NP = M / 16;
-  static_assert(M % 16 == 0 && M <= 64, "panels of 16 rows per lane");
+  constexpr int RS = (M + 63) / 64;  // rows per lane: c0 + lane + 64 s, s < RS
+  static_assert(M % 16 == 0 && M <= 128, "panels of 16 columns, at most two rows per lane");
   const int tid = phase_tid(), w = tid / 64, lane = tid % 64;
 #pragma unroll 1
   for (int p = 0; p < NP; ++p) {
     const int c0 = 16 * p;
     if (w == 0) {
-      const int r = c0 + lane;
-      const bool on = r < M;
-      double a[16];
+      double a[RS][16];
 #pragma unroll
-      for (int jj = 0; jj < 16; ++jj) a[jj] = on ? sm.Bm[(c0 + jj) * LDB + r] : 0.0;
+      for (int s = 0; s < RS; ++s) {
+        const int r = c0 + lane + 64 * s;
+        const bool on = r < M;
+#pragma unroll
+        for (int jj = 0; jj < 16; ++jj) a[s][jj] = on ? sm.Bm[(c0 + jj) * LDB + r] : 0.0;
+      }
 #pragma unroll
       for (int j = 0; j < 16; ++j) {
-        const double d = readlane_f64(a[j], j);  // a_jj after the earlier columns
+        const double d = readlane_f64(a[0][j], j);  // a_jj after the earlier columns
         const double rs = rsqrt(d);
-        const double lj = lane > j ? a[j] * rs : (lane == j ? d * rs : 0.0);
-        a[j] = lj;
+        double lj[RS];
+        lj[0] = lane > j ? a[0][j] * rs : (lane == j ? d * rs : 0.0);
 #pragma unroll
-        for (int jj = j + 1; jj < 16; ++jj) a[jj] = fma(-lj, readlane_f64(lj, jj), a[jj]);
+        for (int s = 1; s < RS; ++s) lj[s] = a[s][j] * rs;  // rows past the panel's diagonal block
+#pragma unroll
+        for (int s = 0; s < RS; ++s) a[s][j] = lj[s];
+#pragma unroll
+        for (int jj = j + 1; jj < 16; ++jj) {
+          const double l = readlane_f64(lj[0], jj);
+#pragma unroll
+          for (int s = 0; s < RS; ++s) a[s][jj] = fma(-lj[s], l, a[s][jj]);
+        }
       }
-      if (on)
 #pragma unroll
-        for (int jj = 0; jj < 16; ++jj) sm.Bm[(c0 + jj) * LDB + r] = a[jj];
+      for (int s = 0; s < RS; ++s) {
+        const int r = c0 + lane + 64 * s;
+        if (r < M)
+#pragma unroll
+          for (int jj = 0; jj < 16; ++jj) sm.Bm[(c0 + jj) * LDB + r] = a[s][jj];
+      }
     }
     __syncthreads();
     // trailing lower triangle: tile (R, Cc), R >= Cc, of the blocks past the panel
@@ -807,34 +823,6 @@ __device__ __forceinline__ void cholesky(AnaSmem<M>& sm) {
   for (int idx = tid; idx < M * M; idx += NT) {
     const int c = idx / M, r = idx % M;
     if (r < c) sm.Bm[c * LDB + r] = 0.0;
-  }
-  __syncthreads();
-}
-
-// The register-blocked form needs TM^2 + 2 TM doubles per thread, which at
-// M = 128 (TM = 8) no longer fits beside the rest of the kernel; that class
-// runs a right-looking LDS form instead: the trailing lower triangle is
-// updated from the unscaled column k, then column k is scaled and its upper
-// part zeroed.
-template <int M>
-__device__ void cholesky_lds(AnaSmem<M>& sm) {
-  using C = AnaCfg<M>;
-  constexpr int NT = C::NT, LDB = C::LDB;
-  const int tid = phase_tid();
-  for (int k = 0; k < M; ++k) {
-    const double akk = sm.Bm[k * LDB + k];
-    const double sk = sqrt(akk);
-    const double inv = 1.0 / akk;
-    const int n = M - 1 - k;
-    for (int idx = tid; idx < n * n; idx += NT) {
-      const int jj = k + 1 + idx / n, ii = k + 1 + idx % n;
-      if (ii >= jj) sm.Bm[jj * LDB + ii] -= sm.Bm[k * LDB + ii] * (sm.Bm[k * LDB + jj] * inv);
-    }
-    __syncthreads();
-    if (tid < M) {
-      const double v = sm.Bm[k * LDB + tid];
-      sm.Bm[k * LDB + tid] = tid < k ? 0.0 : (tid == k ? sk : v / sk);
-    }
   }
   __syncthreads();
 }
@@ -1602,8 +1590,7 @@ __device__ void analyse_item(AnaSmem<M>& sm, const InstDesc* __restrict__ tab, c
     __syncthreads();
   }
   stamp(1);
-  if constexpr (AnaCfg<M>::TM <= 4) cholesky<M>(sm);
-  else cholesky_lds<M>(sm);
+  cholesky<M>(sm);
   stamp(2);
   const int sweeps = jacobi<P, M>(sm, m);
   stamp(3);
