@@ -79,8 +79,8 @@ extern "C" {
  *             with FP32 accumulation; FP64 eigensolve, wbar and W.
  * LETKF_BF16: FP32 ensemble; BF16 operands for C and the update on MFMA with
  *             FP32 accumulation; FP64 Cholesky, wbar and W; the Jacobi
- *             rotations in FP32 for m <= 64 (rotation tolerance 1e-4, far
- *             above FP32 rounding), in FP64 above.                         */
+ *             rotations in FP32 (rotation tolerance 1e-4, far above FP32
+ *             rounding); m <= 128.                                         */
 #define LETKF_FP64 0
 #define LETKF_FP32 1
 #define LETKF_BF16 2

@@ -52,3 +52,35 @@ def test_sweep_visits_every_pair_once_and_barrier_count(M):
         barriers += 1                                   # after the group
     assert len(seen) == M * (M - 1) // 2
     assert barriers == {16: 5, 32: 9, 64: 10, 128: 11}[M]
+
+
+@pytest.mark.parametrize("M", [16, 32, 64, 128])
+def test_fp32_width_change_never_overwrites_unread_values(M):
+    """The BF16 path rotates in FP32: L (double columns at stride LDB) is
+    narrowed in place to float columns at stride LDF = M + TPP by chunks of
+    CC columns in increasing order (each chunk reads all its doubles, then a
+    barrier, then writes its floats), and widened back in decreasing order.
+    No chunk's writes may reach bytes a later chunk still reads, and the float
+    columns must stay inside the double array."""
+    NT = 256
+    TPP, _ = schedule(M, NT)
+    LDB, LDF = M + min(TPP, 8), M + TPP
+    CC = M if M * M // NT <= 16 else 16 * NT // M
+    assert M % CC == 0 and (CC * M) % NT == 0 and CC * M // NT <= 16
+
+    def dbl(c):
+        return (8 * c * LDB, 8 * c * LDB + 8 * M)
+
+    def flt(c):
+        return (4 * c * LDF, 4 * c * LDF + 4 * M)
+
+    def overlap(a, b):
+        return a[0] < b[1] and b[0] < a[1]
+
+    chunks = [range(c0, c0 + CC) for c0 in range(0, M, CC)]
+    for j, ch in enumerate(chunks):
+        for later in chunks[j + 1:]:           # narrowing: later chunks read doubles
+            assert not any(overlap(flt(c), dbl(c2)) for c in ch for c2 in later)
+        for earlier in chunks[:j]:             # widening runs downward: lower chunks read floats
+            assert not any(overlap(dbl(c), flt(c2)) for c in ch for c2 in earlier)
+    assert flt(M - 1)[1] <= 8 * M * LDB
