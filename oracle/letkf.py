@@ -5,7 +5,9 @@ TEST INFRASTRUCTURE ONLY (see the package docstring).
 State (paper Sec. 2.1): x_k holds two successive instants of the phase on the
 valid actuators, so n = 2 n_act; here the rows are [phi_k ; phi_{k-1}].
 Observations y_k are the x then y slopes of the valid subapertures, p = 2 n_sub,
-through the WFS matrix D (Sec. 3), observing the current instant: H = [D 0].
+through the WFS matrix D (Sec. 3), observing one of the two instants the state
+holds: the current one, H = [D 0] (obs_instant = 0), or the previous one,
+H = [0 D] (obs_instant = 1).
 
 Ensemble (Sec. 2.2): m members, columns of X (n x m); the covariances are the
 empirical ones, which the ETKF never forms.
@@ -52,9 +54,10 @@ def ensemble_mean_perturbations(X: np.ndarray):
     return xbar, X - xbar[:, None]
 
 
-def slope_synthesis(D: np.ndarray, X: np.ndarray, n_act: int):
-    """Slopes of each member through H = [D 0]: returns ybar (p) and Y' (p x m)."""
-    Y = D @ X[:n_act]
+def slope_synthesis(D: np.ndarray, X: np.ndarray, n_act: int, obs_instant: int = 0):
+    """Slopes of each member through H = [D 0] (obs_instant 0) or H = [0 D]
+    (obs_instant 1): returns ybar (p) and Y' (p x m)."""
+    Y = D @ X[obs_instant * n_act:(obs_instant + 1) * n_act]
     ybar = Y.mean(axis=1)
     return ybar, Y - ybar[:, None]
 
@@ -116,15 +119,16 @@ def domain_pistons(Zs: list, dmap, n_act: int) -> np.ndarray:
 
 
 def analysis(X: np.ndarray, y: np.ndarray, D: np.ndarray, dmap, r_inv: np.ndarray,
-             rho: float = 1.0, keep_domains: bool = False, pistons: bool = False):
+             rho: float = 1.0, keep_domains: bool = False, pistons: bool = False, obs_instant: int = 0):
     """Whole-pupil local ETKF analysis of the forecast ensemble X (n x m);
-    pistons: remove the differential pistons before the merge."""
+    pistons: remove the differential pistons before the merge; obs_instant:
+    the instant the slopes observe (0: phi_k, 1: phi_{k-1})."""
     n, m = X.shape
     n_act = n // 2
     p = D.shape[0]
     n_sub = p // 2
     xbar, Xp = ensemble_mean_perturbations(X)
-    ybar, Yp = slope_synthesis(D, X, n_act)
+    ybar, Yp = slope_synthesis(D, X, n_act, obs_instant)
     d = y - ybar
     Xa = np.zeros_like(X)
     per_domain = []
@@ -161,7 +165,7 @@ def forecast(Xa: np.ndarray, a1: np.ndarray, a2: np.ndarray, sigma_v: float, see
 
 
 def frame_step(Xf: np.ndarray, y: np.ndarray, D: np.ndarray, dmap, r_inv, a1, a2, sigma_v,
-               seed: int, frame: int, rho: float = 1.0):
+               seed: int, frame: int, rho: float = 1.0, obs_instant: int = 0):
     """Analysis of frame k then forecast to k+1; returns (X^a, X^f_{k+1})."""
-    Xa = analysis(Xf, y, D, dmap, r_inv, rho)
+    Xa = analysis(Xf, y, D, dmap, r_inv, rho, obs_instant=obs_instant)
     return Xa, forecast(Xa, a1, a2, sigma_v, seed, frame)

@@ -25,6 +25,50 @@ def test_philox_known_answers():
         assert [int(v) for v in out] == w[6:10]
 
 
+def test_box_muller_known_answer():
+    """The word -> uniform -> normal map, taken by hand from the published
+    Philox4x32-10 answers: u1 = ((x0 2^21 + x1 div 2^11) + 1/2) 2^-53 (one
+    rounding to double, exact integer arithmetic here), u2 likewise from
+    (x2, x3), z = sqrt(-2 ln u1) cos(2 pi u2) evaluated in 40-digit decimal
+    arithmetic.  The uniforms must match bit for bit; the normal within the
+    rounding of the double-precision formula, whose angle 2 pi u2 carries an
+    absolute error of a few eps (so a bound of 8 eps (r (1 + 2 pi u2) + |z|),
+    r = sqrt(-2 ln u1), and not a relative one near a zero of the cosine).  A
+    swapped uniform, a sine for the cosine or a dropped factor moves z by O(1)."""
+    from decimal import Decimal, getcontext
+    from fractions import Fraction
+    from oracle.philox import box_muller
+    getcontext().prec = 40
+    pi40 = Decimal("3.141592653589793238462643383279502884197")
+
+    def cos_dec(x):
+        x = x % (2 * pi40)
+        term, total, k = Decimal(1), Decimal(1), 0
+        while abs(term) > Decimal(10) ** -38:
+            k += 2
+            term *= -x * x / (k * (k - 1))
+            total += term
+        return total
+
+    rows = 0
+    for line in open(os.path.join(GOLDEN, "philox4x32_10_kat.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        x0, x1, x2, x3 = [int(t, 16) for t in line.split()][6:10]
+        u1 = float(Fraction(x0 * 2 ** 21 + (x1 >> 11)) + Fraction(1, 2)) * 2.0 ** -53
+        u2 = float(Fraction(x2 * 2 ** 21 + (x3 >> 11)) + Fraction(1, 2)) * 2.0 ** -53
+        z_exact = (-2 * Decimal(u1).ln()).sqrt() * cos_dec(2 * pi40 * Decimal(u2))
+        z = float(box_muller(np.array([[x0, x1, x2, x3]], dtype=np.uint32))[0])
+        # the oracle's uniforms, recomputed from its own arithmetic, bit for bit
+        v1 = (np.uint64(x0) << np.uint64(21)) | (np.uint64(x1) >> np.uint64(11))
+        assert (float(v1) + 0.5) * 2.0 ** -53 == u1
+        r = float((-2 * Decimal(u1).ln()).sqrt())
+        bound = 8 * 2.0 ** -52 * (r * (1 + 2 * np.pi * u2) + abs(float(z_exact)))
+        assert abs(z - float(z_exact)) <= bound, (z, z_exact, bound)
+        rows += 1
+    assert rows >= 3
+
+
 def test_forecast_normals_are_standard_normal():
     z = forecast_normals(seed=12345, frame=7, n_act=500, m=128).ravel()
     assert abs(z.mean()) < 0.02 and abs(z.var() - 1) < 0.02
@@ -167,18 +211,43 @@ def _tiny_case(rng, lenslets=4, m=8):
     return geom, D, H, X, y, R
 
 
+@pytest.mark.parametrize("obs_instant", [0, 1])
 @pytest.mark.parametrize("m", [2, 5, 16])
-def test_global_etkf_equals_kf_with_sample_covariance(m):
-    """Woodbury: one global domain gives the KF analysis with P = X'X'^T/(m-1)."""
+def test_global_etkf_equals_kf_with_sample_covariance(m, obs_instant):
+    """Woodbury: one global domain gives the KF analysis with P = X'X'^T/(m-1),
+    with the slopes observing phi_k (H = [D 0]) or phi_{k-1} (H = [0 D]), the
+    observation operator written out densely."""
     rng = np.random.default_rng(5 + m)
     geom, D, H, X, y, R = _tiny_case(rng, 4, m)
+    if obs_instant:
+        H = np.hstack([np.zeros_like(D), D])
     xbar, Xp = ensemble_mean_perturbations(X)
     P = Xp @ Xp.T / (m - 1)
     mean_kf, Pa_kf = _kf(xbar, P, H, R, y)
-    Xa = analysis(X, y, D, global_domain(geom), 1.0 / np.diag(R))
+    Xa = analysis(X, y, D, global_domain(geom), 1.0 / np.diag(R), obs_instant=obs_instant)
     xa, Xap = ensemble_mean_perturbations(Xa)
     np.testing.assert_allclose(xa, mean_kf, rtol=1e-10, atol=1e-10)
     np.testing.assert_allclose(Xap @ Xap.T / (m - 1), Pa_kf, rtol=1e-9, atol=1e-10)
+
+
+def test_observed_instant_swaps_with_the_state_rows():
+    """Observing phi_{k-1} (H = [0 D]) is observing phi_k of the ensemble
+    whose two instants are swapped: the local analysis, domain by domain and
+    merged, commutes with the swap."""
+    rng = np.random.default_rng(17)
+    geom = build_geometry(10, "circular")
+    D = fried_slope_matrix(geom).to_dense()
+    dm = window_domains(geom, 4, 3, 1, True, 0)
+    n_act, m = geom.n_act, 9
+    X = rng.standard_normal((geom.n, m))
+    y = rng.standard_normal(geom.p)
+    r = rng.uniform(0.5, 2.0, geom.p)
+    swap = lambda Z: np.vstack([Z[n_act:], Z[:n_act]])
+    a1 = analysis(X, y, D, dm, r, obs_instant=1)
+    a0 = analysis(swap(X), y, D, dm, r, obs_instant=0)
+    np.testing.assert_allclose(a1, swap(a0), rtol=1e-12, atol=1e-12)
+    # and it is a different analysis from observing phi_k
+    assert np.abs(a1 - analysis(X, y, D, dm, r)).max() > 1e-3
 
 
 def test_etkf_exact_kf_when_ensemble_spans_covariance():
