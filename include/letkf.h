@@ -15,11 +15,13 @@
  * State (Sec. 2.1): x_k = [phi_k ; phi_{k-1}] on the n_act valid actuators,
  * n = 2 n_act.  Observations (Sec. 2.1, Sec. 3): x then y slope of each
  * of the n_sub valid subapertures, p = 2 n_sub, through the WFS matrix D
- * (p x n_act, CSR), observing the current instant: H = [D 0].
+ * (p x n_act, CSR), observing the current instant, H = [D 0], or the
+ * previous one, H = [0 D] (letkf_model.obs_instant).
  *
  * Analysis of domain l (actuators E_l, subapertures O_l; ensemble-space ETKF
  * of the paper's refs [8]-[10], localized per ref [14]):
- *   X' = X - xbar 1^T,  Y' = D X'_phi,  d = y - D xbar_phi,
+ *   X' = X - xbar 1^T,  Y' = H X' = D X'_obs,  d = y - D xbar_obs  (obs: the
+ *   observed instant's rows),
  *   r = taper * R^-1 on O_l,   C = Y'_O^T diag(r) Y'_O,   b = Y'_O^T diag(r) d_O,
  *   A = (m-1)/rho I + C = U Lambda U^T,  wbar = A^-1 b,
  *   W = U ((m-1) Lambda^-1)^(1/2) U^T  (symmetric root, ref [9]),
@@ -74,13 +76,22 @@ extern "C" {
 #define LETKF_ESTATE   (-6)  /* call not valid in the handle's state (e.g. no debug buffers) */
 
 /* ---- precision paths --------------------------------------------------
- * LETKF_FP64: ensemble, slopes and both contractions in FP64; FP64 eigen.
- * LETKF_FP32: FP32 ensemble; C and the update contraction on FP32 MFMA
- *             with FP32 accumulation; FP64 eigensolve, wbar and W.
- * LETKF_BF16: FP32 ensemble; BF16 operands for C and the update on MFMA with
- *             FP32 accumulation; FP64 Cholesky, wbar and W; the Jacobi
- *             rotations in FP32 (rotation tolerance 1e-4, far above FP32
- *             rounding); m <= 128.                                         */
+ * The eigensolve (Cholesky, one-sided Jacobi rotations), wbar and W are FP64
+ * on every path (the rotations unless LETKF_FLAG_FP32_ROTATIONS is given);
+ * the paths differ in the storage of the ensemble and slopes
+ * and in the two dense contractions, C = Y'^T diag(r) Y' and X' T.
+ * LETKF_FP64: ensemble, slopes and both contractions in FP64 (C on FP64
+ *             MFMA for m <= 64, FP64 FMA above); Jacobi tolerance 32 M eps.
+ * LETKF_FP32: FP32 ensemble and slopes; C on FP32 MFMA (v_mfma_f32_16x16x4f32),
+ *             each 4-observation k-step's FP32 product added into an FP64
+ *             accumulator; X' T on FP32 MFMA with FP32 accumulation; Jacobi
+ *             tolerance 1e-6 and two refinement steps of wbar.
+ * LETKF_BF16: FP32 ensemble and slopes; C on BF16 MFMA from split operands
+ *             (sqrt(r) Y' = hi + lo, both BF16; hi hi^T + hi lo^T + lo hi^T)
+ *             with FP32 accumulation; X' T on BF16 MFMA with BF16 X' and a
+ *             hi + lo split of T, FP32 accumulation; Jacobi tolerance 1e-4 and
+ *             three refinement steps of wbar; m <= 128.
+ * b = Y'^T diag(r) d is accumulated in FP64 on every path.                 */
 #define LETKF_FP64 0
 #define LETKF_FP32 1
 #define LETKF_BF16 2
@@ -104,6 +115,14 @@ extern "C" {
  * (ring slot, frame counter), so the graph is replayed unchanged.  While
  * kernel timing is enabled, letkf_step launches the kernels one by one. */
 #define LETKF_FLAG_GRAPH 0x4u
+/* LETKF_BF16 only, opt-in: the Jacobi rotations run in FP32 instead of FP64
+ * (L rounded to FP32 in LDS, rotated to the path's tolerance 1e-4, widened
+ * back for lambda, wbar and W, which stay FP64).  A departure from the FP64
+ * eigensolve: each rotation rounds at ~6e-8, far below the tolerance, and it
+ * is faster where several workgroups share a CU.  Instances with the flag
+ * form a batch class of their own in the server.  LETKF_EINVAL with any
+ * other precision. */
+#define LETKF_FLAG_FP32_ROTATIONS 0x8u
 
 typedef struct letkf_handle letkf_handle;
 typedef struct letkf_server letkf_server;
@@ -125,6 +144,9 @@ typedef struct letkf_model {
   const double* d_val;     /* host [d_nnz] */
   double inflation;        /* rho > 0; 1 = no inflation */
   uint64_t seed;           /* Philox key of the model noise */
+  int32_t obs_instant;     /* which instant the slopes observe (Sec. 2.1: the state holds two):
+                              0 = phi_k, H = [D 0] (pseudo-open-loop slopes of the current
+                              instant); 1 = phi_{k-1}, H = [0 D]; other values LETKF_EINVAL */
 } letkf_model;
 
 typedef struct letkf_domain_map {
@@ -297,7 +319,8 @@ typedef void (*letkf_done_fn)(void* user, uint64_t frame_id, int status);
  * (arena_bytes = the HBM budget, 256-byte aligned; letkf_server_reserved_bytes
  * of it hold the server's own tables and staging) and runs one scheduler
  * thread.  Instances fall into classes (padded ensemble size 16/32/64/128 x
- * precision); a batch holds the oldest pending frame of several instances of
+ * arithmetic variant: the precision, with LETKF_FLAG_FP32_ROTATIONS a variant
+ * of its own); a batch holds the oldest pending frame of several instances of
  * one class (at most max_batch), every domain of which is one work item of
  * one analysis launch.  Up to 8 batches run at once, each on a stream of its
  * own, so the batches of different classes overlap on the GPU.  An instance
@@ -326,14 +349,17 @@ int letkf_server_create(void* arena, size_t arena_bytes, int32_t max_batch, uint
  * resident data (a batch of up to max_batch of them, as letkf_autotune does
  * for one instance) and keeps the fastest grid per class (within the cap on
  * overlapping batches described at letkf_server_create); the instances'
- * domain orders are set to the fastest order.  out (nullable) has 12 entries,
- * one per class (padded size 16/32/64/128 x precision FP64/FP32/BF16, index
- * precision x 4 + size); classes without instances are zeroed.  Only while
+ * domain orders are set to the fastest order.  out (nullable) has
+ * LETKF_SERVER_CLASSES (16) entries, one per class: padded size 16/32/64/128
+ * x arithmetic variant, index variant x 4 + size, with variant = precision
+ * (FP64 0, FP32 1, BF16 2) or 3 for LETKF_BF16 with
+ * LETKF_FLAG_FP32_ROTATIONS; classes without instances are zeroed.  Only while
  * idle: LETKF_EAGAIN when frames are queued or in flight.  Frames submitted
  * during the call wait until it returns.  Instance states are unchanged. */
+#define LETKF_SERVER_CLASSES 16
 int letkf_server_autotune(letkf_server* s, int32_t reps, letkf_tuning* out);
 
-/* Sets the analysis grid of class cls (index precision x 4 + size, as in
+/* Sets the analysis grid of class cls (index variant x 4 + size, as in
  * letkf_server_autotune's output) and the domain order of its admitted
  * instances (instances admitted later keep the default order).  Only while
  * idle (LETKF_EAGAIN otherwise); LETKF_EINVAL for out-of-range fields and

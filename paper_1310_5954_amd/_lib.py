@@ -16,6 +16,8 @@ FP64, FP32, BF16 = 0, 1, 2
 FLAG_DEBUG = 0x1
 FLAG_PISTONS = 0x2
 FLAG_GRAPH = 0x4
+FLAG_FP32_ROTATIONS = 0x8
+SERVER_CLASSES = 16
 SERVER_GRAPHS = 0x1
 ORDER_MAP, ORDER_COST, ORDER_XCD, ORDER_BALANCED = 0, 1, 2, 3
 ORDER_NAMES = {ORDER_MAP: "map", ORDER_COST: "cost", ORDER_XCD: "xcd", ORDER_BALANCED: "balanced"}
@@ -30,7 +32,7 @@ class Model(C.Structure):
                 ("sigma_v", C.c_double), ("r_inv", C.POINTER(C.c_double)),
                 ("d_nnz", C.c_int32), ("d_rowptr", C.POINTER(C.c_int32)),
                 ("d_col", C.POINTER(C.c_int32)), ("d_val", C.POINTER(C.c_double)),
-                ("inflation", C.c_double), ("seed", C.c_uint64)]
+                ("inflation", C.c_double), ("seed", C.c_uint64), ("obs_instant", C.c_int32)]
 
 
 class DomainMapC(C.Structure):

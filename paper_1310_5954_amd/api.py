@@ -29,7 +29,7 @@ class Problem:
     """C structs (and the numpy arrays they point into) for one instance."""
 
     def __init__(self, n_act, n_sub, m, a1, a2, sigma_v, r_inv, d_rowptr, d_col, d_val, est_ptr, est_act,
-                 est_w, obs_ptr, obs_sub, obs_taper, inflation=1.0, seed=0):
+                 est_w, obs_ptr, obs_sub, obs_taper, inflation=1.0, seed=0, obs_instant=0):
         self.keep = dict(a1=_f64(a1), a2=_f64(a2), r_inv=_f64(r_inv), rowptr=_i32(d_rowptr), col=_i32(d_col),
                          val=_f64(d_val), est_ptr=_i32(est_ptr), est_act=_i32(est_act), est_w=_f64(est_w),
                          obs_ptr=_i32(obs_ptr), obs_sub=_i32(obs_sub), obs_taper=_f64(obs_taper))
@@ -39,19 +39,19 @@ class Problem:
         self.model = L.Model(k["a1"].ctypes.data_as(_pd), k["a2"].ctypes.data_as(_pd), float(sigma_v),
                              k["r_inv"].ctypes.data_as(_pd), int(len(k["col"])), k["rowptr"].ctypes.data_as(_pi),
                              k["col"].ctypes.data_as(_pi), k["val"].ctypes.data_as(_pd), float(inflation),
-                             int(seed) & 0xFFFFFFFFFFFFFFFF)
+                             int(seed) & 0xFFFFFFFFFFFFFFFF, int(obs_instant))
         self.map = L.DomainMapC(int(len(k["est_ptr"]) - 1), k["est_ptr"].ctypes.data_as(_pi),
                                 k["est_act"].ctypes.data_as(_pi), k["est_w"].ctypes.data_as(_pd),
                                 k["obs_ptr"].ctypes.data_as(_pi), k["obs_sub"].ctypes.data_as(_pi),
                                 k["obs_taper"].ctypes.data_as(_pd))
 
     @classmethod
-    def from_case(cls, case, dmap=None, sigma_v=None, seed=None):
+    def from_case(cls, case, dmap=None, sigma_v=None, seed=None, obs_instant=0):
         dm = dmap if dmap is not None else case.dmap
         return cls(case.n_act, case.n_sub, case.m, case.a1, case.a2,
                    case.sigma_v if sigma_v is None else sigma_v, case.r_inv, case.D.rowptr, case.D.col,
                    case.D.val, dm.est_ptr, dm.est_act, dm.est_w, dm.obs_ptr, dm.obs_sub, dm.obs_taper,
-                   case.inflation, case.philox_seed if seed is None else seed)
+                   case.inflation, case.philox_seed if seed is None else seed, obs_instant)
 
     @property
     def n(self):
@@ -76,12 +76,12 @@ class Filter:
     """One resident ensemble on the GPU (plain per-frame path)."""
 
     def __init__(self, problem: Problem, X0, precision: int = L.FP64, debug: bool = False, device="cuda:0",
-                 pistons: bool = False, graph: bool = False):
+                 pistons: bool = False, graph: bool = False, fp32_rotations: bool = False):
         self.problem = problem
         self.precision = int(precision)
         self.device = torch.device(device)
         self.flags = ((L.FLAG_DEBUG if debug else 0) | (L.FLAG_PISTONS if pistons else 0)
-                      | (L.FLAG_GRAPH if graph else 0))
+                      | (L.FLAG_GRAPH if graph else 0) | (L.FLAG_FP32_ROTATIONS if fp32_rotations else 0))
         X0 = _f64(X0)
         if X0.shape != (problem.n, problem.m):
             raise ValueError(f"X0 must be ({problem.n}, {problem.m}), got {X0.shape}")
@@ -279,10 +279,11 @@ class Server:
         if self.on_done is not None:
             self.on_done(int(frame_id), int(status), t)
 
-    def add(self, problem: Problem, X0, precision: int = L.FP64, pistons: bool = False) -> Instance:
+    def add(self, problem: Problem, X0, precision: int = L.FP64, pistons: bool = False,
+            fp32_rotations: bool = False) -> Instance:
         X0 = _f64(X0)
         h = C.c_void_p()
-        flags = L.FLAG_PISTONS if pistons else 0
+        flags = (L.FLAG_PISTONS if pistons else 0) | (L.FLAG_FP32_ROTATIONS if fp32_rotations else 0)
         with torch.cuda.device(self.device):
             L.check(L.lib().letkf_server_add(self.handle, C.byref(problem.dims), C.byref(problem.model),
                                              C.byref(problem.map), int(precision), flags, X0.ctypes.data_as(_pd),
@@ -329,10 +330,10 @@ class Server:
         """Per-class analysis launch shapes timed on the admitted instances
         (letkf_server_autotune, only while idle); returns {class index: choice}
         for the classes that have instances."""
-        t = (L.Tuning * 12)()
+        t = (L.Tuning * L.SERVER_CLASSES)()
         with torch.cuda.device(self.device):
             L.check(L.lib().letkf_server_autotune(self.handle, int(reps), t), "letkf_server_autotune")
-        return {c: t[c].as_dict() for c in range(12) if t[c].candidates > 0}
+        return {c: t[c].as_dict() for c in range(L.SERVER_CLASSES) if t[c].candidates > 0}
 
     def set_tuning(self, cls: int, grid: int, order: int = L.ORDER_COST):
         """Sets one class's analysis grid and its instances' domain order (idle only)."""

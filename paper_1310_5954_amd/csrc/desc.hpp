@@ -6,15 +6,20 @@
 // per (padded ensemble size, storage precision) class and walk the class's
 // entries, so the frames of several instances share every launch.
 #pragma once
+#include <hip/hip_runtime.h>
+
 #include <cstdint>
 
 namespace letkf {
 
 constexpr int kMaxBatch = 64;   // frames per batch
-// classes 0..11: 4 padded sizes (16, 32, 64, 128) x 3 precisions (index
-// precision x 4 + size); class 12: 129..256 members, FP64 only
-constexpr int kNumClasses = 13;
-constexpr int kBigClass = 12;
+// classes 0..15: 4 padded sizes (16, 32, 64, 128) x 4 arithmetic variants
+// (index variant x 4 + size): FP64, FP32, BF16, and BF16 with the Jacobi
+// rotations in FP32 (LETKF_FLAG_FP32_ROTATIONS); class 16: 129..256 members,
+// FP64 only
+constexpr int kVariants = 4;
+constexpr int kNumClasses = 4 * kVariants + 1;
+constexpr int kBigClass = 4 * kVariants;
 
 struct InstState {           // mutated on the device by the forecast kernel
   int32_t cur;               // ring slot holding phi_k (the other holds phi_{k-1})
@@ -27,6 +32,8 @@ struct InstState {           // mutated on the device by the forecast kernel
 struct InstDesc {
   int32_t n_act, n_sub, m, n_dom;
   int32_t prec, flags, zrows, nnz;
+  int32_t obs_inst;          // ring slot offset of the observed instant: 0 = phi_k, 1 = phi_{k-1}
+  int32_t pad0;
   double sigma_v;
   double a_diag;             // (m-1)/rho
   uint64_t seed;
@@ -60,7 +67,7 @@ struct InstDesc {
   double* bigv;              // m > 128: [n_dom][5][256] b, wbar, lambda, spare
   int32_t* bigf;             // m > 128: [n_dom][4] converged, rounds that rotated, sweeps, spare
   uint32_t* dom_sweeps;      // [n_dom] Jacobi sweeps of each domain, summed over every analysis
-  double* Ascr;              // FP64, m <= 128: [n_dom][M*M] each domain's A (padded size M), for refining wbar
+  double* Ascr;              // FP64, m <= 128: [n_dom][m(m+1)/2] each domain's A (lower triangle packed by rows), for refining wbar
   double* dbg;               // [n_dom][2*m*m + m] C, lambda, T (NULL unless debug)
   int32_t* dbg_sweeps;       // [n_dom]
   InstState* st;
@@ -84,6 +91,12 @@ struct BatchHdr {
   double* amean;                  // analysis means (phi_k), entry e at out_off[e]
   double* pmean;                  // prediction means (phi_{k+1}), entry e at out_off[e]
   int32_t out_off[kMaxBatch];
+  // check_y != 0 (server batches): the slope kernel sets bad[e] when entry e's
+  // slopes hold a non-finite value, and the merge/forecast kernels then leave
+  // that instance's ensemble and frame counter as they were.  The host uploads
+  // the header with bad[] zeroed for every batch.
+  int32_t check_y;
+  int32_t bad[kMaxBatch];
   ClassBatch cls[kNumClasses];
 };
 
@@ -93,11 +106,19 @@ struct BatchHdr {
 // inside the wbar/W/T phase (after U, after wbar, after its refinement).
 constexpr int kDbgTail = 16;
 
-inline int class_of(int padded_m, int prec) {
+// Arithmetic variant of an instance: its precision path, or 3 for the BF16
+// path with FP32 rotations (fp32_rot: LETKF_FLAG_FP32_ROTATIONS, validated to
+// come with LETKF_BF16).
+inline int variant_of(int prec, bool fp32_rot) { return fp32_rot ? 3 : prec; }
+
+inline int class_of(int padded_m, int prec, bool fp32_rot) {
   if (padded_m > 128) return kBigClass;  // validated to be FP64
   int s = padded_m <= 16 ? 0 : padded_m <= 32 ? 1 : padded_m <= 64 ? 2 : 3;
-  return prec * 4 + s;
+  return variant_of(prec, fp32_rot) * 4 + s;
 }
+
+// Entries of the packed lower triangle of an n x n matrix (row i starts at tri_size(i)).
+__host__ __device__ inline int tri_size(int n) { return n * (n + 1) / 2; }
 
 inline int padded_members(int m) {
   int p = 16;

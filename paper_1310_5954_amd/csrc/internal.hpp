@@ -36,6 +36,7 @@ struct Layout {
 
 struct Problem {  // validated, host-side copy of the create arguments
   int n_act = 0, n_sub = 0, m = 0, prec = 0, n_dom = 0, nnz = 0;
+  int obs_instant = 0;      // 0: H = [D 0], 1: H = [0 D]
   uint32_t flags = 0;
   double sigma_v = 0, inflation = 1;
   uint64_t seed = 0;
@@ -55,6 +56,8 @@ struct Problem {  // validated, host-side copy of the create arguments
     return t;
   }
   size_t esize() const { return prec == LETKF_FP64 ? 8 : 4; }
+  bool fp32_rot() const { return (flags & LETKF_FLAG_FP32_ROTATIONS) != 0; }
+  int cls() const { return class_of(padded_members(m), prec, fp32_rot()); }
 };
 
 int validate(const letkf_dims* dims, const letkf_model* model, const letkf_domain_map* map,

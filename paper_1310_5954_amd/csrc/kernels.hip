@@ -115,7 +115,8 @@ template <typename T> __device__ __forceinline__ double ld(const T* p) { return 
 template <typename T> __device__ __forceinline__ void st(T* p, double v) { *p = (T)v; }
 
 // ----------------------------------------------------------------------------
-// a3: slope perturbations and innovation of every slope row of the class.
+// a3: slope perturbations and innovation of every slope row of the class,
+// Y' = D X'_obs and d = y - D xbar_obs, X_obs the observed instant's rows.
 // ----------------------------------------------------------------------------
 template <typename T, int MP>
 __global__ __launch_bounds__(256) void k_slopes(const InstDesc* __restrict__ tab,
@@ -139,14 +140,19 @@ __global__ __launch_bounds__(256) void k_slopes(const InstDesc* __restrict__ tab
     const int o = g - cb.slope_off[b];
     double v = 0.0;
     if (active && j < m) {
-      const T* ens = (const T*)I.ens + (size_t)I.st->cur * I.n_act * m;
+      // the observed instant: phi_k (ring slot cur) or phi_{k-1} (H = [0 D])
+      const T* ens = (const T*)I.ens + (size_t)(I.st->cur ^ I.obs_inst) * I.n_act * m;
       for (int k = I.d_rowptr[o]; k < I.d_rowptr[o + 1]; ++k)
         v += I.d_val[k] * ld(ens + (size_t)I.d_col[k] * m + j);
     }
     const double ybar = row_sum<MP>(v, red) / (double)m;
     if (active) {
       if (j < m) st((T*)I.Yp + (size_t)o * m + j, v - ybar);
-      if (j == 0) I.d[o] = hdr->yptr[cb.ent[b]][o] - ybar;
+      if (j == 0) {
+        const double yo = hdr->yptr[cb.ent[b]][o];
+        I.d[o] = yo - ybar;
+        if (hdr->check_y && !isfinite(yo)) hdr->bad[cb.ent[b]] = 1;  // every writer stores the same value
+      }
     }
   }
 }
@@ -178,7 +184,10 @@ __global__ __launch_bounds__(256) void k_rows(const InstDesc* __restrict__ tab,
     T* ens = (T*)I.ens;
     T* e_cur = ens + (size_t)cur * slot;
     T* e_prev = ens + (size_t)(cur ^ 1) * slot;
-    const bool live = active && j < m;
+    // an entry whose slopes were not finite keeps its ensemble (group-uniform:
+    // the MP lanes of a row share the entry)
+    const bool skip = hdr->check_y && hdr->bad[cb.ent[b]];
+    const bool live = active && j < m && !skip;
     double vk = 0.0, vkm1 = 0.0;
     if (live) {
       if (MODE == 1) {
@@ -208,7 +217,7 @@ __global__ __launch_bounds__(256) void k_rows(const InstDesc* __restrict__ tab,
     const int ent = cb.ent[b];
     if (MODE != 1) {
       const double s = row_sum<MP>(live ? vk : 0.0, red);
-      if (active && j == 0) hdr->amean[hdr->out_off[ent] + a] = s / (double)m;
+      if (active && !skip && j == 0) hdr->amean[hdr->out_off[ent] + a] = s / (double)m;
     }
     if (MODE != 0) {
       double nx = 0.0;
@@ -219,7 +228,7 @@ __global__ __launch_bounds__(256) void k_rows(const InstDesc* __restrict__ tab,
         st(e_prev + (size_t)a * m + j, nx);
       }
       const double s = row_sum<MP>(nx, red);
-      if (active && j == 0) hdr->pmean[hdr->out_off[ent] + a] = s / (double)m;
+      if (active && !skip && j == 0) hdr->pmean[hdr->out_off[ent] + a] = s / (double)m;
     }
   }
 }
@@ -298,6 +307,7 @@ __global__ __launch_bounds__(64) void k_advance(const InstDesc* __restrict__ tab
                                                 int cls) {
   const ClassBatch& cb = hdr->cls[cls];
   for (int e = threadIdx.x; e < cb.n; e += blockDim.x) {
+    if (hdr->check_y && hdr->bad[cb.ent[e]]) continue;  // the frame was refused: nothing advanced
     InstState* S = tab[cb.inst[e]].st;
     S->cur ^= 1;
     S->frame += 1;
@@ -309,10 +319,13 @@ __global__ __launch_bounds__(64) void k_advance(const InstDesc* __restrict__ tab
 //
 // P selects the contraction path: 0 = FP64 vector FMA, 1 = FP32 MFMA
 // (v_mfma_f32_16x16x4f32), 2 = BF16 MFMA (v_mfma_f32_16x16x32_bf16) with FP32
-// accumulation.  The eigensolve, wbar and W are FP64 on every path.  On the
-// BF16 path C uses split operands (hi + lo, three products): a single BF16
-// rounding of sqrt(r) Y' perturbs C by ~1e-3 of its largest eigenvalue, which
-// exceeds the smallest ones ((m-1)/rho) that dominate W.
+// accumulation, 3 = the BF16 path with its Jacobi rotations in FP32 (an
+// opt-in variant, LETKF_FLAG_FP32_ROTATIONS).  The eigensolve, wbar and W are
+// FP64 on paths 0-2; path 3 rotates in FP32 and keeps the Cholesky, lambda,
+// wbar and W in FP64.  On the BF16 paths C uses split operands (hi + lo, three
+// products): a single BF16 rounding of sqrt(r) Y' perturbs C by ~1e-3 of its
+// largest eigenvalue, which exceeds the smallest ones ((m-1)/rho) that
+// dominate W.
 // ----------------------------------------------------------------------------
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
@@ -911,9 +924,11 @@ __device__ __forceinline__ bool gram_converged(const R* B, const R* nrm, R tol2)
 // partners in that group, so its pair slot keeps it in registers for the
 // whole group and only the partner column goes through LDS each step.
 // The columns are B[c * LD ..] (element type R: FP64, or FP32 for the BF16
-// path), their squared norms nrm[c]; tol is the rotation threshold.
+// path), their squared norms nrm[c]; tol is the rotation threshold.  Returns
+// the sweeps done; `converged` is set when a sweep rotated nothing or the
+// Gram test passed, and stays false when the sweep cap ended the loop.
 template <typename R, int M, int LD>
-__device__ __forceinline__ int jacobi_core(AnaSmem<M>& sm, int m, R* B, R* nrm, R tol) {
+__device__ __forceinline__ int jacobi_core(AnaSmem<M>& sm, int m, R* B, R* nrm, R tol, bool& converged) {
   using C = AnaCfg<M>;
   constexpr int NT = C::NT, TPP = C::TPP;
   constexpr int PSW = 64 / TPP;  // pair slots per wavefront
@@ -928,6 +943,7 @@ __device__ __forceinline__ int jacobi_core(AnaSmem<M>& sm, int m, R* B, R* nrm, 
   const R trig = tol * (R)100 > (R)1e-7 ? tol * (R)100 : (R)1e-7;
   const R trig2 = trig * trig;
   int sweeps = 0;
+  converged = false;
   for (; sweeps < C::MAX_SWEEPS;) {
     {
       constexpr int TPC = NT / M;  // threads per column for the norms
@@ -1041,8 +1057,10 @@ __device__ __forceinline__ int jacobi_core(AnaSmem<M>& sm, int m, R* B, R* nrm, 
     ++sweeps;
     const int any = sm.s_rot;
     const int any_big = __syncthreads_or(big);
-    if (!any) break;
-    if (!any_big && gram_converged<R, M, LD>(B, nrm, tol2)) break;
+    if (!any || (!any_big && gram_converged<R, M, LD>(B, nrm, tol2))) {
+      converged = true;
+      break;
+    }
   }
   return sweeps;
 }
@@ -1059,12 +1077,13 @@ __device__ __forceinline__ int jacobi_core(AnaSmem<M>& sm, int m, R* B, R* nrm, 
 // their tolerances, 1e-6 and 1e-4, keep the eigensolver's share an order of
 // magnitude below that.  At 1e-4 the rotations themselves can run in FP32
 // (rounding ~6e-8 per rotation, a converged off-diagonal of a few 1e-6), which
-// the BF16 path does: L is rounded to FP32 in place (float columns at stride
-// M + TPP inside the double storage), rotated, and widened back.
+// the opt-in BF16 variant (P = 3) does: L is rounded to FP32 in place (float
+// columns at stride M + TPP inside the double storage), rotated, and widened
+// back.  The other paths rotate in FP64.
 template <int P, int M>
-__device__ int jacobi(AnaSmem<M>& sm, int m) {
+__device__ int jacobi(AnaSmem<M>& sm, int m, bool& converged) {
   using C = AnaCfg<M>;
-  if constexpr (P == 2) {
+  if constexpr (P == 3) {
     // In-place width change by chunks of CC columns (at most 16 values per
     // thread in flight).  A float column c ends at or below the start of
     // double column c + 1 (LDF <= 2 LDB and M <= 2 LDB), so narrowing in
@@ -1093,7 +1112,7 @@ __device__ int jacobi(AnaSmem<M>& sm, int m) {
       }
     }
     __syncthreads();
-    const int sweeps = jacobi_core<float, M, LDF>(sm, m, Bf, nf, 1e-4f);
+    const int sweeps = jacobi_core<float, M, LDF>(sm, m, Bf, nf, 1e-4f, converged);
     for (int c0 = M - CC; c0 >= 0; c0 -= CC) {
       float v[PER];
 #pragma unroll
@@ -1112,7 +1131,7 @@ __device__ int jacobi(AnaSmem<M>& sm, int m) {
     return sweeps;
   } else {
     const double tol = P == 0 ? 32.0 * (double)M * 1.1102230246251565e-16 : (P == 1 ? 1e-6 : 1e-4);
-    return jacobi_core<double, M, C::LDB>(sm, m, sm.Bm, sm.nrm, tol);
+    return jacobi_core<double, M, C::LDB>(sm, m, sm.Bm, sm.nrm, tol, converged);
   }
 }
 
@@ -1154,8 +1173,8 @@ __device__ __forceinline__ double rowsum(const AnaSmem<M>& sm, const double* z, 
 // (wbar relative errors ~1e-10 at m = 100 against ~1e-12 for W).  The
 // residual res = b - A wbar is therefore formed with A itself, as the gather
 // built it (Ag: the domain's copy of A = (m-1)/rho I + C taken before the
-// Cholesky, M x M, padded identity), not through the eigenvectors, and
-// wbar += U Lambda^-1 U^T res.  Uses pcol[0] (residual) and pcol[1].
+// Cholesky, its lower triangle packed by rows), not through the eigenvectors,
+// and wbar += U Lambda^-1 U^T res.  Uses pcol[0] (residual) and pcol[1].
 template <int M>
 __device__ void refine_wbar(AnaSmem<M>& sm, const double* __restrict__ Ag, int m) {
   constexpr int TPC = AnaCfg<M>::NT / M, PER = M / TPC;
@@ -1164,11 +1183,17 @@ __device__ void refine_wbar(AnaSmem<M>& sm, const double* __restrict__ Ag, int m
   double* z = sm.pcol[1];
   __syncthreads();  // wbar complete
   {
-    // (A wbar)_o: row o of the symmetric A, coalesced over the lanes of a group
-    const double* Ao = Ag + (size_t)o * M;
+    // (A wbar)_o: row o of the symmetric A; entry (o, c) is packed at row
+    // max(o, c), column min(o, c).  Padded rows and columns read entry 0 and
+    // are masked by arithmetic (res is zero past m anyway).
     double a[PER];
 #pragma unroll
-    for (int k = 0; k < PER; ++k) a[k] = gload(Ao + part + TPC * k);
+    for (int k = 0; k < PER; ++k) {
+      const int c = part + TPC * k;
+      const bool in = c < m && o < m;
+      const int hi = c > o ? c : o, lo = c > o ? o : c;
+      a[k] = (in ? 1.0 : 0.0) * gload(Ag + (in ? tri_size(hi) + lo : 0));
+    }
     double t0 = 0.0, t1 = 0.0;
 #pragma unroll
     for (int k = 0; k < PER; k += 2) {
@@ -1276,7 +1301,7 @@ __device__ void transform(AnaSmem<M>& sm, const InstDesc& I, int l, double* dbg)
   __syncthreads();
   substamp(1);
   if constexpr (P == 0) {
-    refine_wbar<M>(sm, I.Ascr + (size_t)l * M * M, m);
+    refine_wbar<M>(sm, I.Ascr + (size_t)l * tri_size(m), m);
   } else {
 #pragma unroll 1
     for (int k = 0; k < (P == 1 ? 2 : 3); ++k) refine_wbar_lj<M>(sm, m);
@@ -1582,24 +1607,28 @@ __device__ void analyse_item(AnaSmem<M>& sm, const InstDesc* __restrict__ tab, c
   else if constexpr (P == 0) gather_C_fp64<M>(sm, I, obs_off, s, dbg);
   else gather_C_mfma<P, M>(sm, I, obs_off, s, dbg);
   if constexpr (P == 0) {
-    // the domain's A, kept for the refinement of wbar (the Cholesky overwrites it)
+    // the domain's A, kept for the refinement of wbar (the Cholesky overwrites
+    // it): the lower triangle of the m x m matrix, packed by rows (row i at
+    // i (i + 1) / 2), rows spread over the wavefronts and coalesced over lanes
     __syncthreads();
-    double* Ag = I.Ascr + (size_t)l * M * M;
-    for (int idx = threadIdx.x; idx < M * M; idx += AnaCfg<M>::NT)
-      gstore(Ag + idx, sm.Bm[(idx / M) * AnaCfg<M>::LDB + idx % M]);
+    double* Ag = I.Ascr + (size_t)l * tri_size(m);
+    const int w = phase_tid() / 64, lane = phase_tid() % 64;
+    for (int i = w; i < m; i += AnaCfg<M>::NT / 64)
+      for (int j = lane; j <= i; j += 64) gstore(Ag + tri_size(i) + j, sm.Bm[i * AnaCfg<M>::LDB + j]);
     __syncthreads();
   }
   stamp(1);
   cholesky<M>(sm);
   stamp(2);
-  const int sweeps = jacobi<P, M>(sm, m);
+  bool converged = false;
+  const int sweeps = jacobi<P, M>(sm, m, converged);
   stamp(3);
   transform<P, M>(sm, I, l, dbg);
   stamp(4);
   if (threadIdx.x == 0) {
     if (I.dbg_sweeps) I.dbg_sweeps[l] = sweeps;
     gatomic_add(&I.dom_sweeps[l], (unsigned)sweeps);
-    if (sweeps >= C::MAX_SWEEPS) gatomic_add(&I.st->unconverged, 1);
+    if (!converged) gatomic_add(&I.st->unconverged, 1);
     gatomic_add(&I.st->sweeps, (unsigned long long)sweeps);
     gatomic_add(&I.st->solves, 1ull);
   }
@@ -2223,11 +2252,16 @@ static void launch_slopes_t(int rows, const InstDesc* tab, BatchHdr* hdr, int cl
       else if (sz_ == 1) FN((k_analysis<1, 32>));                   \
       else if (sz_ == 2) FN((k_analysis<1, 64>));                   \
       else FN((k_analysis<1, 128>));                                \
-    } else {                                                        \
+    } else if (prec_ == 2) {                                        \
       if (sz_ == 0) FN((k_analysis<2, 16>));                        \
       else if (sz_ == 1) FN((k_analysis<2, 32>));                   \
       else if (sz_ == 2) FN((k_analysis<2, 64>));                   \
       else FN((k_analysis<2, 128>));                                \
+    } else {                                                        \
+      if (sz_ == 0) FN((k_analysis<3, 16>));                        \
+      else if (sz_ == 1) FN((k_analysis<3, 32>));                   \
+      else if (sz_ == 2) FN((k_analysis<3, 64>));                   \
+      else FN((k_analysis<3, 128>));                                \
     }                                                               \
   } while (0)
 

@@ -42,7 +42,10 @@ int validate(const letkf_dims* dims, const letkf_model* model, const letkf_domai
     return fail(LETKF_EINVAL, "LETKF_FLAG_PISTONS needs m <= 128");
   if (precision != LETKF_FP64 && precision != LETKF_FP32 && precision != LETKF_BF16)
     return fail(LETKF_EINVAL, "unknown precision");
-  if (flags & ~(LETKF_FLAG_DEBUG | LETKF_FLAG_PISTONS | LETKF_FLAG_GRAPH)) return fail(LETKF_EINVAL, "unknown flags");
+  if (flags & ~(LETKF_FLAG_DEBUG | LETKF_FLAG_PISTONS | LETKF_FLAG_GRAPH | LETKF_FLAG_FP32_ROTATIONS))
+    return fail(LETKF_EINVAL, "unknown flags");
+  if ((flags & LETKF_FLAG_FP32_ROTATIONS) && precision != LETKF_BF16)
+    return fail(LETKF_EINVAL, "LETKF_FLAG_FP32_ROTATIONS needs LETKF_BF16");
   P.n_act = dims->n_act;
   P.n_sub = dims->n_sub;
   P.m = dims->m;
@@ -56,6 +59,7 @@ int validate(const letkf_dims* dims, const letkf_model* model, const letkf_domai
     return fail(LETKF_EINVAL, "non-finite AR coefficients");
   if (!std::isfinite(model->sigma_v) || model->sigma_v < 0) return fail(LETKF_EINVAL, "sigma_v must be finite and >= 0");
   if (!std::isfinite(model->inflation) || model->inflation <= 0) return fail(LETKF_EINVAL, "inflation must be > 0");
+  if (model->obs_instant != 0 && model->obs_instant != 1) return fail(LETKF_EINVAL, "obs_instant must be 0 or 1");
   for (int i = 0; i < p; ++i)
     if (!std::isfinite(model->r_inv[i]) || model->r_inv[i] < 0) return fail(LETKF_EINVAL, "r_inv must be finite and >= 0");
   if (model->d_nnz < 0) return fail(LETKF_EINVAL, "d_nnz < 0");
@@ -70,6 +74,7 @@ int validate(const letkf_dims* dims, const letkf_model* model, const letkf_domai
   P.sigma_v = model->sigma_v;
   P.inflation = model->inflation;
   P.seed = model->seed;
+  P.obs_instant = model->obs_instant;
   P.nnz = model->d_nnz;
   P.a1.assign(model->a1, model->a1 + n_act);
   P.a2.assign(model->a2, model->a2 + n_act);
@@ -178,7 +183,7 @@ Layout make_layout(const Problem& P) {
   L.dom_sweeps = take((size_t)P.n_dom * 4);
   {
     const size_t M = padded_members(P.m);
-    L.Ascr = (P.prec == LETKF_FP64 && M <= 128) ? take((size_t)P.n_dom * M * M * 8) : 0;
+    L.Ascr = (P.prec == LETKF_FP64 && M <= 128) ? take((size_t)P.n_dom * tri_size(P.m) * 8) : 0;
   }
   if (P.flags & LETKF_FLAG_DEBUG) {
     L.dbg = take((size_t)P.n_dom * (2 * m * m + m + kDbgTail) * 8);
@@ -405,6 +410,7 @@ int upload_instance(const Problem& P, const Layout& L, char* ws, const double* X
   std::memset(&D, 0, sizeof(D));
   D.n_act = n_act; D.n_sub = P.n_sub; D.m = m; D.n_dom = P.n_dom;
   D.prec = P.prec; D.flags = (int32_t)P.flags; D.zrows = P.zrows(); D.nnz = P.nnz;
+  D.obs_inst = P.obs_instant;
   D.sigma_v = P.sigma_v;
   D.a_diag = (double)(m - 1) / P.inflation;
   D.seed = P.seed;
@@ -448,7 +454,7 @@ int upload_instance(const Problem& P, const Layout& L, char* ws, const double* X
   H.yptr[0] = (const double*)(ws + L.y);
   H.amean = (double*)(ws + L.amean);
   H.pmean = (double*)(ws + L.pmean);
-  const int cls = class_of(padded_members(m), P.prec);
+  const int cls = P.cls();
   ClassBatch& cb = H.cls[cls];
   cb.n = 1;
   cb.inst[0] = 0;
@@ -805,7 +811,7 @@ int letkf_create(const letkf_dims* dims, const letkf_model* model, const letkf_d
   if (hipGetDevice(&h->device) != hipSuccess) { delete h; return fail(LETKF_EDEVICE, "hipGetDevice failed"); }
   h->ws = (char*)workspace;
   h->mpad = padded_members(h->P.m);
-  h->cls = class_of(h->mpad, h->P.prec);
+  h->cls = h->P.cls();
   rc = upload_instance(h->P, h->L, h->ws, X0, (hipStream_t)stream, h->desc);
   if (!rc) {
     int num_cu = 0;

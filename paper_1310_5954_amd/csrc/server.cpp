@@ -128,6 +128,10 @@ struct letkf_server {
   int inflight = 0;                 // batches launched and not yet completed
   int rr = 0;
   bool stop = false;
+  // letkf_server_autotune is timing launches on slot 0 (without holding mu):
+  // the scheduler launches nothing, submissions queue, and calls that change
+  // the instances or read their state return LETKF_EAGAIN
+  bool tuning = false;
   uint64_t frames_done = 0, batches = 0, batched_frames = 0, pending = 0;
   std::thread sched, compl_thr[kSlots];
 
@@ -216,6 +220,7 @@ int letkf_server::launch_batch(Batch& b) {
   std::memset(&H, 0, sizeof(H));
   H.amean = dout(s);
   H.pmean = dout(s) + kStageDoubles;
+  H.check_y = 1;  // device slopes are checked by the slope kernel (bad[] uploaded as zeros)
   size_t ytot = 0, otot = 0;
   ClassBatch& cb = H.cls[c];
   for (size_t e = 0; e < b.frames.size(); ++e) {
@@ -260,6 +265,9 @@ int letkf_server::launch_batch(Batch& b) {
     LETKF_HIP(hipGetLastError());
   }
   LETKF_HIP(hipMemcpyAsync(h_out[s], dout(s) + kStageDoubles, otot * sizeof(double), hipMemcpyDeviceToHost, st));
+  // which entries the slope kernel refused (non-finite slopes), into the pinned
+  // header, which stays untouched until this slot's completion thread is done
+  LETKF_HIP(hipMemcpyAsync(H.bad, dhdr(s)->bad, sizeof(int32_t) * b.frames.size(), hipMemcpyDeviceToHost, st));
   LETKF_HIP(hipEventRecord(done_ev[s], st));
   return LETKF_OK;
 }
@@ -268,7 +276,7 @@ void letkf_server::scheduler_loop() {
   (void)hipSetDevice(device);  // a failure shows up as an error status of the first batch
   std::unique_lock<std::mutex> lk(mu);
   for (;;) {
-    cv_work.wait(lk, [&] { return stop || pending > 0; });
+    cv_work.wait(lk, [&] { return (stop || pending > 0) && !tuning; });
     if (stop && pending == 0) return;
     int s = -1;
     for (int k = 0; k < kSlots; ++k)
@@ -392,16 +400,22 @@ void letkf_server::completion_loop(int k) {
     lk.unlock();
     const hipError_t e = hipEventSynchronize(done_ev[k]);
     const int status = e == hipSuccess ? LETKF_OK : LETKF_EDEVICE;
+    // per frame: a frame whose slopes were not finite was refused on the
+    // device (its instance's state is unchanged) and reports LETKF_ENUMERIC
+    std::vector<int> st(b.frames.size(), status);
     for (size_t i = 0; i < b.frames.size(); ++i) {
       auto& [h, f] = b.frames[i];
-      if (status == LETKF_OK && f.pred_out)
+      if (status == LETKF_OK && h_hdr[k]->bad[i]) st[i] = LETKF_ENUMERIC;
+      if (st[i] == LETKF_OK && f.pred_out)
         std::memcpy(f.pred_out, h_out[k] + b.out_off[i], sizeof(double) * h->P.n_act);
     }
     // callbacks first, then the instances are released: the frames that the
     // callbacks of one batch submit are all queued when the scheduler looks
     // at them again, so closed loops keep full batches
-    for (auto& [h, f] : b.frames)
-      if (f.cb) f.cb(f.user, f.id, status);
+    for (size_t i = 0; i < b.frames.size(); ++i) {
+      auto& [h, f] = b.frames[i];
+      if (f.cb) f.cb(f.user, f.id, st[i]);
+    }
     lk.lock();
     for (auto& [h, f] : b.frames) in_flight[h]--;
     frames_done += b.frames.size();
@@ -417,6 +431,7 @@ int letkf::server_idle_stream(letkf_handle* h, hipStream_t* stream) {
   letkf_server* s = h->server;
   {
     std::lock_guard<std::mutex> lk(s->mu);
+    if (s->tuning) return fail(LETKF_EAGAIN, "server autotuning in progress");
     if (!s->queues[h].empty() || s->in_flight[h] > 0) return fail(LETKF_EAGAIN, "instance has frames in flight");
   }
   // the instance's last batch has completed (its completion thread released
@@ -481,24 +496,39 @@ int letkf_server_create(void* arena, size_t arena_bytes, int32_t max_batch, uint
   return LETKF_OK;
 }
 
+// Whether a validated problem can be served: ensembles of at most 128
+// members, and slopes and means that fit one batch's staging slot (a batch
+// stages every frame's p slopes and n_act means in slots of kStageDoubles
+// values; a larger instance could never be batched).
+static int server_admissible(const Problem& P) {
+  if (P.m > 128) return fail(LETKF_EINVAL, "m > 128 runs on the plain path only");
+  if ((size_t)P.p() > kStageDoubles || (size_t)P.n_act > kStageDoubles)
+    return fail(LETKF_EINVAL, "instance too large for the server's staging slots: p and n_act must be <= " +
+                                  std::to_string(kStageDoubles));
+  return LETKF_OK;
+}
+
 int letkf_server_add(letkf_server* s, const letkf_dims* dims, const letkf_model* model,
                      const letkf_domain_map* map, int precision, uint32_t flags, const double* X0,
                      letkf_handle** out) {
-  if (!s || !out) return fail(LETKF_EINVAL, "null server/out");
+  if (!out) return fail(LETKF_EINVAL, "null out");
   *out = nullptr;
   auto* h = new letkf_handle();
+  // the arguments are checked before the server is used
   int rc = validate(dims, model, map, precision, flags, h->P);
+  if (!rc) rc = server_admissible(h->P);
+  if (!rc && !s) rc = fail(LETKF_EINVAL, "null server");
   if (rc) { delete h; return rc; }
-  if (h->P.m > 128) { delete h; return fail(LETKF_EINVAL, "m > 128 runs on the plain path only"); }
   if (!X0) { delete h; return fail(LETKF_EINVAL, "null X0"); }
   for (size_t i = 0; i < 2 * (size_t)h->P.n_act * h->P.m; ++i)
     if (!std::isfinite(X0[i])) { delete h; return fail(LETKF_ENUMERIC, "non-finite X0"); }
   h->L = make_layout(h->P);
   h->mpad = padded_members(h->P.m);
-  h->cls = class_of(h->mpad, h->P.prec);
+  h->cls = h->P.cls();
   h->device = s->device;
   {
     std::lock_guard<std::mutex> lk(s->mu);
+    if (s->tuning) { delete h; return fail(LETKF_EAGAIN, "server autotuning in progress"); }
     int slot = -1;
     for (int k = 0; k < kMaxInstances; ++k)
       if (!s->inst[k]) { slot = k; break; }
@@ -547,6 +577,7 @@ int letkf_server_add(letkf_server* s, const letkf_dims* dims, const letkf_model*
 int letkf_server_remove(letkf_server* s, letkf_handle* h) {
   if (!s || !h || h->server != s) return fail(LETKF_EINVAL, "handle does not belong to this server");
   std::lock_guard<std::mutex> lk(s->mu);
+  if (s->tuning) return fail(LETKF_EAGAIN, "server autotuning in progress");
   if (!s->queues[h].empty() || s->in_flight[h] > 0) return fail(LETKF_EAGAIN, "instance still has frames in flight");
   s->queues.erase(h);
   s->in_flight.erase(h);
@@ -631,11 +662,26 @@ int letkf_server_stats(letkf_server* s, uint64_t* frames, uint64_t* batches, uin
 
 int letkf_server_autotune(letkf_server* s, int32_t reps, letkf_tuning* out) {
   if (!s) return fail(LETKF_EINVAL, "null server");
-  std::unique_lock<std::mutex> lk(s->mu);  // held throughout: nothing is launched meanwhile
-  if (!s->idle()) return fail(LETKF_EAGAIN, "server has frames queued, being launched or in flight");
+  std::vector<letkf_handle*> all;
+  int caps[kBigClass] = {};
+  {
+    // The tuning launches run without the lock, so that submitters are not held
+    // up for the seconds it takes; meanwhile the scheduler launches nothing
+    // (slot 0, its stream and staging are free: the server is idle) and the
+    // instance set cannot change.
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->tuning) return fail(LETKF_EAGAIN, "server autotuning in progress");
+    if (!s->idle()) return fail(LETKF_EAGAIN, "server has frames queued, being launched or in flight");
+    s->tuning = true;
+    for (letkf_handle* h : s->inst)
+      if (h) all.push_back(h);
+    for (int c = 0; c < kBigClass; ++c) caps[c] = s->overlap_cap(c);
+  }
   const int slot = 0;
   hipStream_t st = s->stream[slot];
-  for (int c = 0; c < kBigClass; ++c) {  // the 12 tunable classes (no m > 128 instance is admitted)
+  int rc = LETKF_OK;
+  int grids[kBigClass] = {};
+  for (int c = 0; c < kBigClass && !rc; ++c) {  // the tunable classes (no m > 128 instance is admitted)
     if (out) out[c] = letkf_tuning{};
     BatchHdr& H = *s->h_hdr[slot];
     std::memset(&H, 0, sizeof(H));
@@ -644,8 +690,8 @@ int letkf_server_autotune(letkf_server* s, int32_t reps, letkf_tuning* out) {
     ClassBatch& cb = H.cls[c];
     std::vector<letkf_handle*> insts;
     size_t ytot = 0, otot = 0;
-    for (letkf_handle* h : s->inst) {
-      if (!h || h->cls != c || cb.n >= s->max_batch) continue;
+    for (letkf_handle* h : all) {
+      if (h->cls != c || cb.n >= s->max_batch) continue;
       if (ytot + h->P.p() > kStageDoubles || otot + h->P.n_act > kStageDoubles) break;
       const int k = cb.n++;
       H.yptr[k] = s->dy(slot) + ytot;  // zero slopes: the solve's cost does not depend on them
@@ -660,25 +706,35 @@ int letkf_server_autotune(letkf_server* s, int32_t reps, letkf_tuning* out) {
       insts.push_back(h);
     }
     if (insts.empty()) continue;
-    LETKF_HIP(hipMemsetAsync(s->dy(slot), 0, ytot * sizeof(double), st));
-    LETKF_HIP(hipMemcpyAsync(s->dhdr(slot), &H, sizeof(H), hipMemcpyHostToDevice, st));
-    LETKF_HIP(hipStreamSynchronize(st));  // H is reused for the next class
-    int grid = 0;
-    int rc = tune_class(c, s->table(), s->dhdr(slot), cb.slope_off[cb.n], cb.dom_off[cb.n], insts, s->num_cu, reps, false,
-                        s->overlap_cap(c), st, out ? &out[c] : nullptr, &grid);
-    if (rc) return rc;
-    s->cls_grid[c] = grid;
+    if (hipMemsetAsync(s->dy(slot), 0, ytot * sizeof(double), st) != hipSuccess ||
+        hipMemcpyAsync(s->dhdr(slot), &H, sizeof(H), hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess) {  // H is reused for the next class
+      rc = fail(LETKF_EDEVICE, "autotune staging");
+      break;
+    }
+    rc = tune_class(c, s->table(), s->dhdr(slot), cb.slope_off[cb.n], cb.dom_off[cb.n], insts, s->num_cu, reps, false,
+                    caps[c], st, out ? &out[c] : nullptr, &grids[c]);
   }
-  s->drop_graphs();  // captured with the old grids
-  return LETKF_OK;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (!rc) {
+      for (int c = 0; c < kBigClass; ++c)
+        if (grids[c]) s->cls_grid[c] = grids[c];
+      s->drop_graphs();  // captured with the old grids
+    }
+    s->tuning = false;
+  }
+  s->cv_work.notify_all();
+  return rc;
 }
 
 int letkf_server_set_tuning(letkf_server* s, int32_t cls, const letkf_tuning* t) {
   if (!s) return fail(LETKF_EINVAL, "null server");
-  if (cls < 0 || cls >= kBigClass) return fail(LETKF_EINVAL, "class must be in [0, 12)");
+  if (cls < 0 || cls >= kBigClass) return fail(LETKF_EINVAL, "class must be in [0, " + std::to_string(kBigClass) + ")");
   if (!t || t->grid < 1 || t->grid > 65535 || t->order < LETKF_ORDER_MAP || t->order > LETKF_ORDER_XCD)
     return fail(LETKF_EINVAL, "tuning: grid must be in [1, 65535] and order one of LETKF_ORDER_*");
   std::unique_lock<std::mutex> lk(s->mu);
+  if (s->tuning) return fail(LETKF_EAGAIN, "server autotuning in progress");
   if (!s->idle()) return fail(LETKF_EAGAIN, "server has frames queued, being launched or in flight");
   for (letkf_handle* h : s->inst)
     if (h && h->cls == cls) {

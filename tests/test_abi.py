@@ -66,7 +66,8 @@ def test_invalid_dims_and_model_rejected(over, needle):
 def test_large_ensembles_fp64_only():
     """m in 129..256 is accepted in FP64 only (the multi-launch analysis), with
     scratch for two 256 x 256 FP64 matrices per domain, and without pistons.
-    (At m = 128 the FP64 workspace holds one 128 x 128 copy of A per domain.)"""
+    (At m = 128 the FP64 workspace holds one copy of A per domain, its lower
+    triangle packed: 128 * 129 / 2 values.)"""
     b = C.c_size_t()
     pr128, pr200 = _problem(m=128), _problem(m=200)
     args = lambda pr: (C.byref(pr.dims), C.byref(pr.model), C.byref(pr.map))
@@ -74,7 +75,7 @@ def test_large_ensembles_fp64_only():
     s128 = b.value
     assert L.lib().letkf_workspace_size(*args(pr200), L.FP64, 0, C.byref(b)) == L.OK
     n_dom = pr200.map.n_domains
-    assert b.value - (s128 - n_dom * 128 * 128 * 8) >= n_dom * 2 * 256 * 256 * 8
+    assert b.value - (s128 - n_dom * (128 * 129 // 2) * 8) >= n_dom * 2 * 256 * 256 * 8
     for prec in (L.FP32, L.BF16):
         assert L.lib().letkf_workspace_size(*args(pr200), prec, 0, C.byref(b)) == L.EINVAL
         assert "needs LETKF_FP64" in L.lib().letkf_last_error().decode()
@@ -134,3 +135,50 @@ def test_server_reserved_bytes_is_a_host_query():
     (it sizes HBM budgets); 256-byte aligned like every arena region."""
     n = L.lib().letkf_server_reserved_bytes()
     assert n > 0 and n % 256 == 0
+
+
+def test_fp32_rotations_flag_needs_bf16():
+    """LETKF_FLAG_FP32_ROTATIONS (the opt-in FP32 Jacobi rotations) is a
+    variant of the BF16 path only."""
+    pr = _problem()
+    b = C.c_size_t()
+    args = (C.byref(pr.dims), C.byref(pr.model), C.byref(pr.map))
+    assert L.lib().letkf_workspace_size(*args, L.BF16, L.FLAG_FP32_ROTATIONS, C.byref(b)) == L.OK
+    for prec in (L.FP64, L.FP32):
+        assert L.lib().letkf_workspace_size(*args, prec, L.FLAG_FP32_ROTATIONS, C.byref(b)) == L.EINVAL
+        assert "needs LETKF_BF16" in L.lib().letkf_last_error().decode()
+
+
+def test_obs_instant_values():
+    """obs_instant 0 (H = [D 0]) and 1 (H = [0 D]) are accepted, nothing else."""
+    b = C.c_size_t()
+    for v, rc in ((0, L.OK), (1, L.OK), (2, L.EINVAL), (-1, L.EINVAL)):
+        pr = _problem(obs_instant=v)
+        assert L.lib().letkf_workspace_size(C.byref(pr.dims), C.byref(pr.model), C.byref(pr.map), L.FP64, 0,
+                                            C.byref(b)) == rc, v
+    assert "obs_instant" in L.lib().letkf_last_error().decode()
+
+
+def test_server_refuses_instances_larger_than_its_staging():
+    """A batch stages each frame's slopes and means in slots of 2^18 values, so
+    an instance with p or n_act above that could never be batched: the server
+    refuses it (arguments are checked before the server handle is used, so a
+    null server shows it without a GPU).  A problem within the limit gets to
+    the null-server check."""
+    n_sub = (1 << 17) + 1                      # p = 2^18 + 2 slopes
+    p = 2 * n_sub
+    pr = Problem(n_act=4, n_sub=n_sub, m=4, a1=np.ones(4), a2=np.zeros(4), sigma_v=0.0, r_inv=np.ones(p),
+                 d_rowptr=np.zeros(p + 1, np.int32), d_col=np.zeros(0, np.int32), d_val=np.zeros(0),
+                 est_ptr=[0, 4], est_act=[0, 1, 2, 3], est_w=np.ones(4), obs_ptr=[0, 0],
+                 obs_sub=np.zeros(0, np.int32), obs_taper=np.zeros(0))
+    X0 = np.zeros((pr.n, pr.m))
+    h = C.c_void_p()
+    rc = L.lib().letkf_server_add(None, C.byref(pr.dims), C.byref(pr.model), C.byref(pr.map), L.FP64, 0,
+                                  X0.ctypes.data_as(C.POINTER(C.c_double)), C.byref(h))
+    assert rc == L.EINVAL and not h.value
+    assert "staging" in L.lib().letkf_last_error().decode()
+    small = _problem()
+    X0 = np.zeros((small.n, small.m))
+    rc = L.lib().letkf_server_add(None, C.byref(small.dims), C.byref(small.model), C.byref(small.map), L.FP64, 0,
+                                  X0.ctypes.data_as(C.POINTER(C.c_double)), C.byref(h))
+    assert rc == L.EINVAL and "null server" in L.lib().letkf_last_error().decode()

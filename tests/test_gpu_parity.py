@@ -1,11 +1,23 @@
 """GPU parity: the HIP path through the C ABI against the FP64 oracle.
 
 Single-step protocol: the oracle is fed the GPU's own input ensemble, slopes
-and frame counter, so rounding never compounds; errors are normwise relative
-per result (analysis mean, analysis perturbations, forecast ensemble, and
-per domain C, lambda, T).  Bounds: FP64 1e-10 and FP32 1e-4 on every result;
-BF16 1e-2 on the analysis mean, with the other results bounded as stated in
-BF16_TOL (BF16 operands carry 2^-9 relative rounding).
+and frame counter, so rounding never compounds.  Errors per result: the
+normwise relative error (analysis mean, analysis perturbations, forecast
+ensemble, analysis-mean output), and the largest per-row errors of the mean,
+of the analysis ensemble and of the perturbations (one bad domain cannot hide
+in the norm of the pupil); per domain, for every domain, C, lambda and T.
+
+Bounds (TOLS).  The contract bars: FP64 1e-10 on every result and
+intermediate; FP32 1e-4 on the results; BF16 1e-2 on the analysis mean.  The
+other bounds sit at about 3x the worst values measured on MI355X over these
+cases.  Two follow from the arithmetic rather than from measurement:
+  * FP32 T: T = W + wbar 1^T, W = [(m-1) A^-1]^(1/2), wbar = A^-1 b, carries
+    the FP32 rounding of C amplified by up to kappa(A): per domain
+    T_err <= T_KAPPA kappa(A) 2^-24.
+  * per-row perturbations with an FP32 ensemble (FP32 and BF16 paths): rows
+    whose mean is 1e4-1e5 times their spread lose 2^-24 |mean| to the storage
+    of the ensemble alone (up to 8e-3 of the spread in a CPU check), so that
+    bound is the storage floor, not the kernels'.
 """
 import numpy as np
 import pytest
@@ -15,31 +27,35 @@ from paper_1310_5954_amd import BF16, FP32, FP64, Filter, LetkfError, Problem
 from workload.configs import build_case
 from workload.geometry import (DomainMap, build_geometry, fried_slope_matrix, global_domain, window_domains)
 
-from _helpers import oracle_spin_up, rel, result_errors, sparse_D
+from _helpers import oracle_spin_up, rel, result_errors, rowmax, sparse_D
 
 pytestmark = pytest.mark.gpu
 
 # Per precision and result.  Results: analysis mean, analysis perturbations,
-# forecast ensemble, analysis-mean output.  Intermediates: C, lambda, T.
-# T = [(m-1)A^-1]^(1/2) + wbar 1^T amplifies the relative rounding of C by up
-# to the conditioning of A (~1e4 here): FP32 C (~1e-7) gives T to ~1e-3 while
-# the results stay within 1e-4.
-RESULTS = ("mean", "pert", "forecast", "amean_out")
+# forecast ensemble, analysis-mean output, and the per-row maxima of the mean,
+# the analysis ensemble and the perturbations.  Intermediates (every domain):
+# C, lambda, T.
+RESULTS = ("mean", "pert", "forecast", "amean_out", "mean_row", "ens_row", "pert_row")
 TOLS = {
     FP64: dict.fromkeys(RESULTS + ("C", "lam", "T"), 1e-10),
-    FP32: dict(dict.fromkeys(RESULTS, 1e-4), C=1e-6, lam=1e-6, T=2e-3),
-    BF16: dict(mean=1e-2, amean_out=1e-2, pert=5e-2, forecast=5e-2, C=1e-4, lam=1e-4, T=5e-2),
+    FP32: dict(dict.fromkeys(RESULTS, 1e-4), pert_row=1.5e-2, C=2e-7, lam=1.5e-7, T=None),
+    BF16: dict(mean=1e-2, amean_out=1e-2, mean_row=7e-2, ens_row=7e-2, pert=3.5e-2, pert_row=1.2e-1,
+               forecast=6e-8, C=1.2e-5, lam=1.6e-5, T=6e-2),
 }
+# FP32: T of domain l within T_KAPPA kappa(A_l) 2^-24 of the oracle's
+T_KAPPA = 1.5
 
 
 def _tol(precision, key):
     return TOLS[precision][key]
 
 
-def _check_step(case, X, k, precision, debug=False, dmap=None, check_domains=None, pistons=False):
+def _check_step(case, X, k, precision, debug=False, dmap=None, check_domains=None, pistons=False,
+                fp32_rotations=False, obs_instant=0):
     """Load X at frame k, analyse y_k, compare; forecast, compare."""
     dm = dmap if dmap is not None else case.dmap
-    f = Filter(Problem.from_case(case, dmap=dm), X, precision=precision, debug=debug, pistons=pistons)
+    f = Filter(Problem.from_case(case, dmap=dm, obs_instant=obs_instant), X, precision=precision, debug=debug,
+               pistons=pistons, fp32_rotations=fp32_rotations)
     f.set_state(X, frame=k)
     Xg, fr = f.get_state()
     assert fr == k
@@ -47,7 +63,8 @@ def _check_step(case, X, k, precision, debug=False, dmap=None, check_domains=Non
     D = sparse_D(case)
     mean = f.analyse(y, mean=True)
     Xa_g, _ = f.get_state()
-    Xa_o, doms = oracle.analysis(Xg, y, D, dm, case.r_inv, case.inflation, keep_domains=True, pistons=pistons)
+    Xa_o, doms = oracle.analysis(Xg, y, D, dm, case.r_inv, case.inflation, keep_domains=True, pistons=pistons,
+                                 obs_instant=obs_instant)
     f.forecast()
     Xf_g, fr2 = f.get_state()
     assert fr2 == k + 1
@@ -59,18 +76,30 @@ def _check_step(case, X, k, precision, debug=False, dmap=None, check_domains=Non
     assert f.unconverged() == 0
     if debug:
         worst = dict(C=0.0, lam=0.0, T=0.0)
+        kappa_ratio, kappa_max = 0.0, 0.0
         for l in (check_domains if check_domains is not None else range(dm.n_domains)):
             g = f.debug_domain(l)
             o = doms[l]
             worst["C"] = max(worst["C"], rel(g["C"], o["C"]))
             worst["lam"] = max(worst["lam"], rel(g["lam"], o["lam"]))
-            worst["T"] = max(worst["T"], rel(g["T"], o["T"]))
+            t_err = rel(g["T"], o["T"])
+            worst["T"] = max(worst["T"], t_err)
+            kappa = float(o["lam"].max() / o["lam"].min())
+            kappa_max = max(kappa_max, kappa)
+            kappa_ratio = max(kappa_ratio, t_err / (kappa * 2.0 ** -24))
             assert 1 <= g["sweeps"] < 40
         for key, v in worst.items():
-            assert v < _tol(precision, key), worst
-        err.update({"dom_" + k: v for k, v in worst.items()})
-    print(f"[{case.cfg['name']} m={case.m} prec={precision}] worst relative errors: "
-          + ", ".join(f"{k} {v:.1e}" for k, v in err.items()), flush=True)
+            tol = _tol(precision, key)
+            if tol is not None:
+                assert v < tol, worst
+        if precision == FP32:
+            assert kappa_ratio < T_KAPPA, (kappa_ratio, worst)
+        err.update({"dom_" + kk: v for kk, v in worst.items()})
+        err["T_over_kappa_eps32"] = kappa_ratio
+        err["kappa_max"] = kappa_max
+    print(f"[{case.cfg['name']} m={case.m} prec={precision}{' fp32rot' if fp32_rotations else ''}"
+          f"{' obs1' if obs_instant else ''}] worst errors: " + ", ".join(f"{k} {v:.2e}" for k, v in err.items()),
+          flush=True)
     f.close()
     return err
 
@@ -157,7 +186,22 @@ def test_cfg3_full_size_fp64():
     """84x84 pupil, m = 64, 375 domains: every domain and row compared."""
     case = build_case(3)
     X, k = oracle_spin_up(case, 2)
-    _check_step(case, X, k, FP64, debug=True, check_domains=range(0, case.dmap.n_domains, 7))
+    _check_step(case, X, k, FP64, debug=True)
+
+
+def test_cfg3_obs_instant_previous_fp64():
+    """Slopes of the previous instant, H = [0 D]: the slope kernel reads the
+    other ring slot; every result against the oracle with H = [0 D]."""
+    case = build_case(3)
+    X, k = oracle_spin_up(case, 2)
+    _check_step(case, X, k, FP64, debug=True, obs_instant=1)
+
+
+def test_cfg1_obs_instant_previous_all_paths():
+    case = build_case(1)
+    X, k = oracle_spin_up(case, 2)
+    for prec in (FP64, FP32, BF16):
+        _check_step(case, X, k, prec, debug=True, obs_instant=1)
 
 
 def test_two_partitions_cfg3_fp64():
@@ -167,7 +211,7 @@ def test_two_partitions_cfg3_fp64():
     case = build_case(3, partitions=2)
     assert case.dmap.n_domains > 700
     X, k = oracle_spin_up(case, 1)
-    _check_step(case, X, k, FP64, debug=True, check_domains=range(0, case.dmap.n_domains, 13))
+    _check_step(case, X, k, FP64, debug=True)
 
 
 def test_two_partitions_cfg2_bf16():
@@ -213,36 +257,59 @@ def test_pistons_disjoint_map_is_plain_analysis():
 def test_cfg3_full_size_fp32():
     case = build_case(3)
     X, k = oracle_spin_up(case, 2)
-    _check_step(case, X, k, FP32, debug=True, check_domains=range(0, case.dmap.n_domains, 11))
+    _check_step(case, X, k, FP32, debug=True)
 
 
-def test_cfg3_full_size_bf16():
-    """BF16 MFMA contractions, FP32 Jacobi rotations: per-result errors."""
+@pytest.mark.parametrize("fp32_rotations", [False, True])
+def test_cfg3_full_size_bf16(fp32_rotations):
+    """BF16 MFMA contractions with the FP64 eigensolve (the default), and the
+    opt-in variant with FP32 Jacobi rotations: every domain, per result."""
     case = build_case(3)
     X, k = oracle_spin_up(case, 2)
-    err = _check_step(case, X, k, BF16, debug=True, check_domains=range(0, case.dmap.n_domains, 11))
-    print("bf16 per-result errors:", {kk: f"{v:.2e}" for kk, v in err.items()})
+    _check_step(case, X, k, BF16, debug=True, fp32_rotations=fp32_rotations)
 
 
-@pytest.mark.parametrize("precision", [FP32, BF16])
+@pytest.mark.parametrize("precision", [FP64, BF16])
+def test_cfg5_full_size_single_step(precision):
+    """128x128 pupil, m = 128, 852 domains of up to 36 actuators and 162
+    slopes (full-rank C, unlike the 15x15 pupil): the M = 128 panel Cholesky
+    with two rows per lane and the M = 128 Jacobi; every domain's C, lambda
+    and T and every row of the results."""
+    case = build_case(5)
+    assert case.dmap.n_domains == 852
+    X, k = oracle_spin_up(case, 1)
+    _check_step(case, X, k, precision, debug=True)
+
+
+def test_cfg5_full_size_bf16_fp32_rotations():
+    """The opt-in FP32 rotations at M = 128 (four 32-column chunks in the
+    in-place width change), full-rank domains."""
+    case = build_case(5)
+    X, k = oracle_spin_up(case, 1)
+    _check_step(case, X, k, BF16, debug=True, fp32_rotations=True)
+
+
+@pytest.mark.parametrize("precision,fp32_rotations", [(FP32, False), (BF16, False), (BF16, True)])
 @pytest.mark.parametrize("m", [5, 16, 33, 100, 128])
-def test_ensemble_sizes_mfma_paths(precision, m):
-    """MFMA tiles with padded members (m -> 16/32/64/128) on both low-precision paths."""
+def test_ensemble_sizes_mfma_paths(precision, fp32_rotations, m):
+    """MFMA tiles with padded members (m -> 16/32/64/128) on both low-precision
+    paths (BF16 with either rotation precision)."""
     case = build_case(1, m=m)
     X, k = oracle_spin_up(case, 2)
-    _check_step(case, X, k, precision, debug=True)
+    _check_step(case, X, k, precision, debug=True, fp32_rotations=fp32_rotations)
 
 
 def test_cfg2_fp32_ragged_with_intermediates():
     case = build_case(2)
     X, k = oracle_spin_up(case, 3)
-    _check_step(case, X, k, FP32, debug=True, check_domains=range(0, case.dmap.n_domains, 5))
+    _check_step(case, X, k, FP32, debug=True)
 
 
-def _residual_variance(case, precision, frames, burn):
+def _residual_variance(case, precision, frames, burn, fp32_rotations=False):
     """Piston-removed residual phase variance of the analysis mean against the
-    truth, averaged over frames burn..frames-1."""
-    f = Filter(Problem.from_case(case), case.X0, precision=precision)
+    truth, averaged over frames burn..frames-1 (the plain path, frame after
+    frame from X0)."""
+    f = Filter(Problem.from_case(case), case.X0, precision=precision, fp32_rotations=fp32_rotations)
     acc = []
     for k in range(frames):
         mean = f.analyse(case.slopes(k), mean=True)
@@ -254,14 +321,46 @@ def _residual_variance(case, precision, frames, burn):
     return float(np.mean(acc))
 
 
-def test_cfg3_bf16_residual_variance_within_1pct_of_fp64():
+def test_cfg3_residual_variance_within_1pct_of_fp64():
+    """Trajectory quality on the 84x84 workload (wind ramp): 300 frames, burn-in
+    100; the FP32 path within 0.1 % and the BF16 paths within 1 % of the
+    FP64 path's residual phase variance."""
     case = build_case(3)
-    v64 = _residual_variance(case, FP64, 60, 20)
-    v16 = _residual_variance(case, BF16, 60, 20)
-    v32 = _residual_variance(case, FP32, 60, 20)
-    print(f"residual variance fp64 {v64:.5f} fp32 {v32:.5f} bf16 {v16:.5f}")
+    v64 = _residual_variance(case, FP64, 300, 100)
+    v32 = _residual_variance(case, FP32, 300, 100)
+    v16 = _residual_variance(case, BF16, 300, 100)
+    v16r = _residual_variance(case, BF16, 300, 100, fp32_rotations=True)
+    print(f"residual variance (300 frames, burn-in 100): fp64 {v64:.6f} fp32 {v32:.6f} ({v32 / v64 - 1:+.2e}) "
+          f"bf16 {v16:.6f} ({v16 / v64 - 1:+.2e}) bf16+fp32rot {v16r:.6f} ({v16r / v64 - 1:+.2e})", flush=True)
     assert abs(v32 / v64 - 1) < 1e-3
     assert abs(v16 / v64 - 1) < 1e-2
+    assert abs(v16r / v64 - 1) < 1e-2
+
+
+def test_cfg1_trajectory_200_frames_fp64():
+    """The 15x15 workload's 200 frames on the plain path (letkf_step) against
+    the oracle's own 200-frame trajectory from the same X0 (the same Philox
+    noise; nothing of the GPU's state is fed back): within 1e-9 on every
+    frame's state and prediction."""
+    case = build_case(1)
+    D = sparse_D(case)
+    f = Filter(Problem.from_case(case), case.X0, precision=FP64)
+    Xo = case.X0.copy()
+    worst, series = 0.0, []
+    for k in range(200):
+        y = case.slopes(k)
+        pred = f.step(y, pred=True)
+        Xa_o = oracle.analysis(Xo, y, D, case.dmap, case.r_inv)
+        Xo = oracle.forecast(Xa_o, case.a1, case.a2, case.sigma_v, case.philox_seed, k)
+        Xg, fr = f.get_state()
+        assert fr == k + 1
+        e = max(rel(Xg, Xo), rel(pred, Xo[:case.n_act].mean(axis=1)), rowmax(Xg, Xo))
+        series.append(e)
+        worst = max(worst, e)
+    print(f"cfg1 200-frame FP64 trajectory: worst {worst:.2e}, frame 0 {series[0]:.2e}, "
+          f"frame 99 {series[99]:.2e}, frame 199 {series[199]:.2e}", flush=True)
+    assert worst < 1e-9, worst
+    f.close()
 
 
 def test_deterministic_and_device_y():

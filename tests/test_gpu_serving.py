@@ -8,6 +8,8 @@
 * Instances are admitted against the HBM budget and re-admitted when
   memory frees up.
 """
+import functools
+
 import numpy as np
 import pytest
 
@@ -20,36 +22,44 @@ pytestmark = pytest.mark.gpu
 FRAMES = 8
 
 
+@functools.lru_cache(maxsize=1)
 def _mix_cases():
-    """Five classes (padded ensemble size x precision) and, in the first
-    class, two instances with different pupils and ensembles, so that some
-    batches share launches and batches of other classes run beside them."""
+    """Seven classes (padded ensemble size x arithmetic variant) and, in the
+    first class, two instances with different pupils and ensembles, so that
+    some batches share launches and batches of other classes run beside them.
+    The 100x100, m = 128 BF16 instance is the serving workload's largest: its
+    workgroups fill a CU each, so while the other classes are resident its
+    analysis runs on at most 3/4 of the CUs.  The 24x24 BF16 instance also
+    runs with the opt-in FP32 rotations, a class of its own."""
     c16 = dict(build_case(2).cfg)
     c16.update(lenslets=16, seeds=(21, 22, 23))
     c24 = dict(build_case(2).cfg)
     c24.update(lenslets=24, seeds=(31, 32, 33), m=64)
     c12 = dict(build_case(1).cfg)
     c12.update(lenslets=12, seeds=(41, 42, 43), window=3, stride=3)
-    return [(build_case(1), FP64), (build_case(c12), FP64), (build_case(2), FP32), (build_case(c16, m=20), FP64),
-            (build_case(c24), BF16), (build_case(1, m=33), FP64)]
+    c100 = dict(build_case(3).cfg)
+    c100.update(lenslets=100, seeds=(51, 52, 53), frames=20)
+    return [(build_case(1), FP64, {}), (build_case(c12), FP64, {}), (build_case(2), FP32, {}),
+            (build_case(c16, m=20), FP64, {}), (build_case(c24), BF16, {}), (build_case(1, m=33), FP64, {}),
+            (build_case(c100, m=128), BF16, {}), (build_case(c24), BF16, dict(fp32_rotations=True))]
 
 
-def _run_server(cases, frames=FRAMES, drain_each=False, budget=1 << 30, graphs=False, tune=False, grid=None):
+def _run_server(cases, frames=FRAMES, drain_each=False, budget=1 << 31, graphs=False, tune=False, grid=None):
     srv = Server(budget, graphs=graphs)
-    insts = [srv.add(Problem.from_case(c), c.X0, p) for c, p in cases]
+    insts = [srv.add(Problem.from_case(c), c.X0, p, **kw) for c, p, kw in cases]
     if tune:
         choice = srv.autotune(reps=1)
-        classes = {L_class(c.m, p) for c, p in cases}
+        classes = {L_class(c.m, p, kw.get("fp32_rotations", False)) for c, p, kw in cases}
         assert set(choice) == classes, (choice, classes)
         assert all(1 <= t["grid"] and t["candidates"] >= 2 for t in choice.values()), choice
     if grid is not None:                 # persistent analysis with `grid` workgroups, map order
-        for cls in range(12):
+        for cls in range(L.SERVER_CLASSES):
             srv.set_tuning(cls, grid, order=L.ORDER_XCD if grid > 1 else L.ORDER_MAP)
         # the balanced order is for plain instances: a batch's placement depends on the batch
         with pytest.raises(LetkfError):
             srv.set_tuning(0, grid, order=L.ORDER_BALANCED)
-    ys = [[c.slopes(k) for k in range(frames)] for c, _ in cases]
-    preds = [[np.empty(c.n_act) for _ in range(frames)] for c, _ in cases]
+    ys = [[c.slopes(k) for k in range(frames)] for c, _, _ in cases]
+    preds = [[np.empty(c.n_act) for _ in range(frames)] for c, _, _ in cases]
     for k in range(frames):
         for i, inst in enumerate(insts):
             assert srv.submit(inst, ys[i][k], 1000 * i + k, preds[i][k]) == 0
@@ -64,16 +74,18 @@ def _run_server(cases, frames=FRAMES, drain_each=False, budget=1 << 30, graphs=F
     return preds, states, stats
 
 
-def L_class(m, precision):
-    """Class index of an instance: precision x 4 + padded-size index."""
+def L_class(m, precision, fp32_rotations=False):
+    """Class index of an instance: arithmetic variant x 4 + padded-size index
+    (variant: the precision, or 3 for BF16 with FP32 rotations)."""
     pm = 16
     while pm < m:
         pm *= 2
-    return precision * 4 + {16: 0, 32: 1, 64: 2, 128: 3}[pm]
+    variant = 3 if fp32_rotations else precision
+    return variant * 4 + {16: 0, 32: 1, 64: 2, 128: 3}[pm]
 
 
-@pytest.mark.parametrize("graphs,tune,grid", [(True, False, None), (True, True, None), (False, False, 1),
-                                              (True, False, 3)])
+@pytest.mark.parametrize("graphs,tune,grid", [(True, False, None), (True, True, None), (False, False, 2),
+                                              (True, False, 5)])
 def test_graphs_tuning_and_grid_leave_mix_results_unchanged(graphs, tune, grid):
     """Replayed batch graphs (LETKF_SERVER_GRAPHS), autotuned launch shapes,
     and a persistent analysis grid far below the domain count (the
@@ -121,7 +133,7 @@ def test_server_pistons_equal_plain_pistons():
 
 def test_server_equals_plain_path():
     case = build_case(1)
-    preds, states, _ = _run_server([(case, FP64)], drain_each=True)
+    preds, states, _ = _run_server([(case, FP64, {})], drain_each=True)
     f = Filter(Problem.from_case(case), case.X0, precision=FP64)
     for k in range(FRAMES):
         p = f.step(case.slopes(k), pred=True)
@@ -173,7 +185,7 @@ def test_device_slopes_equal_host_slopes():
     gives the same bits as host submission."""
     import torch
     case = build_case(1)
-    host_preds, host_states, _ = _run_server([(case, FP64)], drain_each=True)
+    host_preds, host_states, _ = _run_server([(case, FP64, {})], drain_each=True)
     srv = Server(1 << 28)
     inst = srv.add(Problem.from_case(case), case.X0, FP64)
     ys = [torch.tensor(case.slopes(k), dtype=torch.float64, device="cuda:0") for k in range(FRAMES)]
@@ -209,4 +221,69 @@ def test_callback_may_submit_next_frame():
     assert done.wait(60)
     srv.drain()
     assert order == list(range(FRAMES))
+    srv.close()
+
+
+def test_nonfinite_device_slopes_refused_and_state_kept():
+    """Device slopes are checked by the slope kernel: a frame with a NaN is
+    reported with LETKF_ENUMERIC, leaves its instance's ensemble and frame
+    counter as they were, and the frames after it run as if it had never
+    been submitted (equal, bit for bit, to a run without it)."""
+    import torch
+    case = build_case(1)
+    ref_preds, ref_states, _ = _run_server([(case, FP64, {})], frames=3, drain_each=True)
+    srv = Server(1 << 28)
+    inst = srv.add(Problem.from_case(case), case.X0, FP64)
+    good = [torch.tensor(case.slopes(k), dtype=torch.float64, device="cuda:0") for k in range(3)]
+    bad = good[1].clone()
+    bad[7] = float("nan")
+    preds = [np.empty(case.n_act) for _ in range(4)]
+    seq = [(good[0], 0), (bad, 1), (good[1], 2), (good[2], 3)]
+    for y, fid in seq:
+        assert srv.submit(inst, y, fid, preds[fid]) == 0
+        srv.drain()
+        if fid == 1:
+            X, fr = inst.get_state()
+            assert fr == 1                              # the refused frame advanced nothing
+    assert srv.done[1][0] == L.ENUMERIC
+    assert all(srv.done[f][0] == 0 for f in (0, 2, 3))
+    for k, fid in ((0, 0), (1, 2), (2, 3)):
+        assert np.array_equal(preds[fid], ref_preds[0][k]), (k, fid)
+    X, fr = inst.get_state()
+    assert fr == 3 and np.array_equal(X, ref_states[0][0])
+    srv.close()
+
+
+def test_autotune_runs_without_blocking_submitters():
+    """letkf_server_autotune times its launches without holding the server
+    lock: a frame submitted meanwhile is queued at once (the call returns in
+    well under the tuning time) and launched after the tuning, with the same
+    result as without tuning."""
+    import threading
+    import time
+    case = build_case(3)
+    ref_preds, _, _ = _run_server([(case, BF16, {})], frames=1)
+    srv = Server(1 << 30)
+    inst = srv.add(Problem.from_case(case), case.X0, BF16)
+    t_tune = {}
+
+    def tune():
+        t0 = time.perf_counter()
+        srv.autotune(reps=30)
+        t_tune["s"] = time.perf_counter() - t0
+
+    th = threading.Thread(target=tune)
+    th.start()
+    time.sleep(0.05)                 # the tuning is under way
+    pred = np.empty(case.n_act)
+    t0 = time.perf_counter()
+    rc = srv.submit(inst, case.slopes(0), 0, pred)
+    t_submit = time.perf_counter() - t0
+    during = th.is_alive()           # the submission returned while the tuning ran
+    th.join()
+    srv.drain()
+    assert rc == 0 and srv.done[0][0] == 0
+    print(f"autotune {t_tune['s']:.3f} s, submit during it {1e3 * t_submit:.2f} ms", flush=True)
+    assert during and t_submit < 0.1 and t_submit < t_tune["s"] / 4, (during, t_submit, t_tune)
+    assert np.array_equal(pred, ref_preds[0][0])
     srv.close()
