@@ -196,6 +196,27 @@ int letkf_forecast(letkf_handle* h, void* stream);
  * call waits for completion. */
 int letkf_step(letkf_handle* h, const double* y, int y_on_device, double* pred_out, void* stream);
 
+/* For callers that cannot allocate memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation): one frame of the
+ * plain path, like letkf_step with device slopes, that allocates nothing -
+ * no device memory, no pinned staging, no host synchronisation.  y_dev
+ * (device [p] FP64) is read by the frame's kernels; pred_dev (device
+ * [n_act] FP64) receives the prediction mean of phi_{k+1}; both are the
+ * caller's and must stay valid until the stream reaches the frame.
+ * Asynchronous on `stream`.  The frame's scratch (slope perturbations,
+ * innovation, per-domain analysis rows, the copies of A on the FP64 path,
+ * analysis means, and the descriptor copies that point the kernels there)
+ * lives in a static device array of the library, 32 MiB per GPU, held until
+ * the process ends, instead of the instance workspace: LETKF_EINVAL when the
+ * frame needs more (e.g. 84x84 subapertures with m = 64 needs about 26 MB in
+ * FP64, 10 MB in FP32/BF16) or m > 128.  Every such call on one GPU shares
+ * that array, so calls that overlap on one GPU (other streams, other
+ * threads) race and must be ordered by the caller.  The first call on a GPU
+ * looks the array's address up (make it outside a graph capture).  Device
+ * slopes are not checked for non-finite values; letkf_last_means does not
+ * see these frames. */
+int letkf_step_noalloc(letkf_handle* h, const double* y_dev, double* pred_dev, void* stream);
+
 /* Copies the ensemble (host [n x m] FP64, rows [phi_k; phi_{k-1}]) and the
  * frame counter out (frame_out may be NULL); waits for the stream. */
 int letkf_get_state(letkf_handle* h, double* X_out, uint64_t* frame_out, void* stream);

@@ -73,6 +73,7 @@ def _sig(lib):
     lib.letkf_analyse.argtypes = [P, P, C.c_int, pd, P]
     lib.letkf_forecast.argtypes = [P, P]
     lib.letkf_step.argtypes = [P, P, C.c_int, pd, P]
+    lib.letkf_step_noalloc.argtypes = [P, P, P, P]
     lib.letkf_get_state.argtypes = [P, pd, C.POINTER(C.c_uint64), P]
     lib.letkf_set_state.argtypes = [P, pd, C.c_uint64, P]
     lib.letkf_debug_domain.argtypes = [P, C.c_int32, pd, pd, pd, C.POINTER(C.c_int32), pd, P]

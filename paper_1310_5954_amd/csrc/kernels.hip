@@ -12,6 +12,8 @@
 // and storage precision) so that frames of several instances share a launch.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "desc.hpp"
 #include "launch.hpp"
 
@@ -2193,6 +2195,66 @@ __global__ __launch_bounds__(256) void k_big_update(const InstDesc* __restrict__
       const int rr = ty + 16 * x, q = q0 + rr, j = j0 + tx + 16 * y;
       if (q < rows && j < m) Z[(size_t)q * m + j] = xb[rr] + acc[x][y];
     }
+}
+
+// ----------------------------------------------------------------------------
+// The allocation-free frame (letkf_step_noalloc): callers that cannot
+// allocate device memory run a frame with its per-frame scratch in this
+// file-scope array instead of the instance workspace.  Each GPU holds its own
+// copy (kScratchBytes) until the process ends, shared by every such call on
+// that GPU.  Host code reaches it only through the address hipGetSymbolAddress
+// returns for the current device (scratch_address), never through its name.
+// ----------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+hipError_t scratch_address(int device, unsigned char** out) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static unsigned char* addr[kMaxDevices] = {};
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(mu);
+  if (!addr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));  // the current device's copy
+    if (e != hipSuccess) return e;
+    addr[device] = (unsigned char*)p;
+  }
+  *out = addr[device];
+  return hipSuccess;
+}
+
+// One workgroup: word copies of the instance descriptor and of the class's
+// batch entry, then the pointers moved into the array.  Everything the frame
+// kernels read of the header is written here (the work counter is zeroed by
+// the slope kernel); the other classes' entries are never read.
+__global__ __launch_bounds__(256) void k_noalloc_setup(const InstDesc* __restrict__ src,
+                                                       const BatchHdr* __restrict__ src_hdr, unsigned char* sp,
+                                                       NoallocLayout lay, const double* y, double* pred, int cls) {
+  InstDesc* d = (InstDesc*)(sp + lay.desc);
+  BatchHdr* h = (BatchHdr*)(sp + lay.hdr);
+  static_assert(sizeof(InstDesc) % 4 == 0 && sizeof(ClassBatch) % 4 == 0, "word copies");
+  for (int i = threadIdx.x; i < (int)(sizeof(InstDesc) / 4); i += blockDim.x)
+    ((uint32_t*)d)[i] = ((const uint32_t*)src)[i];
+  for (int i = threadIdx.x; i < (int)(sizeof(ClassBatch) / 4); i += blockDim.x)
+    ((uint32_t*)&h->cls[cls])[i] = ((const uint32_t*)&src_hdr->cls[cls])[i];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    d->Yp = sp + lay.Yp;
+    d->d = (double*)(sp + lay.d);
+    d->Z = sp + lay.Z;
+    d->Ascr = lay.Ascr ? (double*)(sp + lay.Ascr) : nullptr;
+    h->yptr[0] = y;
+    h->amean = (double*)(sp + lay.amean);
+    h->pmean = pred;
+    h->out_off[0] = 0;
+    h->check_y = 0;
+    h->bad[0] = 0;
+  }
+}
+
+void launch_noalloc_setup(const InstDesc* src, const BatchHdr* src_hdr, unsigned char* sp, const NoallocLayout& lay,
+                          const double* y, double* pred, int cls, hipStream_t s) {
+  hipLaunchKernelGGL(k_noalloc_setup, dim3(1), dim3(256), 0, s, src, src_hdr, sp, lay, y, pred, cls);
 }
 
 // ----------------------------------------------------------------------------

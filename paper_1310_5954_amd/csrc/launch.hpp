@@ -23,6 +23,26 @@ void launch_pistons(int cls, int domain_items, const InstDesc* tab, BatchHdr* hd
 void launch_analysis(int cls, int grid, const InstDesc* tab, BatchHdr* hdr, hipStream_t s);
 // Analysis workgroups of the class one CU holds at once (LDS and registers).
 int analysis_blocks_per_cu(int cls);
+
+// ---- the allocation-free frame (letkf_step_noalloc) ----
+// Byte offsets, inside the library's static device array, of the scratch of
+// one frame run without the instance workspace's scratch: copies of the
+// instance descriptor and batch header pointing the kernels there, the slope
+// perturbations, the innovation, the per-domain analysis rows, the packed
+// copies of A (FP64) and the analysis means.
+constexpr size_t kScratchBytes = size_t(32) << 20;
+struct NoallocLayout {
+  size_t desc, hdr, Yp, d, Z, Ascr, amean, total;
+};
+// The array's address on the current device (looked up once per device and
+// kept); LETKF_EDEVICE-style HIP error otherwise.
+hipError_t scratch_address(int device, unsigned char** out);
+// Builds the descriptor and header copies in the array at sp (device address):
+// the instance's descriptor with Yp, d, Z and Ascr moved into the array, and a
+// one-entry header of class cls reading y (device) and writing the prediction
+// means to pred (device), the analysis means into the array.
+void launch_noalloc_setup(const InstDesc* src, const BatchHdr* src_hdr, unsigned char* sp, const NoallocLayout& lay,
+                          const double* y, double* pred, int cls, hipStream_t s);
 // The analysis of the m > 128 class (FP64): a fixed sequence of launches over
 // the domains' scratch (rows_max: most state rows of a domain, m_max: most
 // members of an instance in the batch).

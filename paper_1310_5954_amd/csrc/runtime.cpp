@@ -952,6 +952,51 @@ int letkf_step(letkf_handle* h, const double* y, int y_on_device, double* pred_o
   return LETKF_OK;
 }
 
+// Offsets of the frame scratch of letkf_step_noalloc in the static array.
+static NoallocLayout noalloc_layout(const Problem& P) {
+  NoallocLayout L{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    off = (off + 255) & ~size_t(255);
+    const size_t o = off;
+    off += bytes;
+    return o;
+  };
+  const size_t es = P.esize(), m = P.m, p = P.p();
+  L.desc = take(sizeof(InstDesc));
+  L.hdr = take(sizeof(BatchHdr));
+  L.Yp = take(p * m * es);
+  L.d = take(p * 8);
+  L.Z = take((size_t)P.zrows() * m * es);
+  L.Ascr = P.prec == LETKF_FP64 ? take((size_t)P.n_dom * tri_size(P.m) * 8) : 0;
+  L.amean = take((size_t)P.n_act * 8);
+  L.total = (off + 255) & ~size_t(255);
+  return L;
+}
+
+int letkf_step_noalloc(letkf_handle* h, const double* y_dev, double* pred_dev, void* stream) {
+  int rc = check_plain(h);
+  if (rc) return rc;
+  if (!y_dev || !pred_dev) return fail(LETKF_EINVAL, "null y_dev or pred_dev");
+  if (h->cls == kBigClass) return fail(LETKF_EINVAL, "letkf_step_noalloc needs m <= 128");
+  const NoallocLayout lay = noalloc_layout(h->P);
+  if (lay.total > kScratchBytes)
+    return fail(LETKF_EINVAL, "frame scratch of " + std::to_string(lay.total) + " bytes exceeds the static maximum of " +
+                                  std::to_string(kScratchBytes) + " bytes");
+  unsigned char* sp = nullptr;
+  LETKF_HIP(scratch_address(h->device, &sp));  // the current device's array (check_plain set it)
+  hipStream_t s = (hipStream_t)stream;
+  launch_noalloc_setup(dev_desc(h), dev_hdr(h), sp, lay, y_dev, pred_dev, h->cls, s);
+  const InstDesc* tab = (const InstDesc*)(sp + lay.desc);
+  BatchHdr* hdr = (BatchHdr*)(sp + lay.hdr);
+  launch_slopes(h->cls, h->P.p(), tab, hdr, s);
+  launch_analysis(h->cls, h->ana_grid, tab, hdr, s);
+  if (h->P.flags & LETKF_FLAG_PISTONS) launch_pistons(h->cls, h->P.n_dom, tab, hdr, s);
+  launch_rows(h->cls, 2, h->P.n_act, tab, hdr, s);
+  LETKF_HIP(hipGetLastError());
+  return LETKF_OK;
+}
+
 int letkf_get_state(letkf_handle* h, double* X_out, uint64_t* frame_out, void* stream) {
   hipStream_t s;
   int rc = access_stream(h, stream, &s);
