@@ -10,14 +10,20 @@ Two forms serve the same load, --instances B resident AO instances
 (independent ensembles, default 4) in a closed loop: each instance releases
 its next frame when its previous one is done.
   serving  the server batches the pending frames of all instances into shared
-           launches (by default BF16 contractions, FP32 Jacobi rotations and
-           FP64 Cholesky / w-bar / T).  This is `value` (aggregate frames/s)
-           and p50/p99 (submit -> callback).
+           launches (by default BF16 contractions and the FP64 eigensolve:
+           Cholesky, Jacobi rotations, w-bar, W, T).  This is `value`
+           (aggregate frames/s) and p50/p99 (submit -> callback, over at least
+           500 frames), with device-resident slopes; the same with host slopes
+           and with the opt-in FP32 rotations are reported beside it.
   plain    the plain per-frame FP64 path (letkf_step, one frame per launch
            sequence) serves the same instances one frame at a time; its
            frames/s and p50/p99 are reported beside, together with the
-           unloaded single-instance latency.  Its analysis kernel gives the
-           roofline line.
+           unloaded single-instance latency and its analysis kernel's
+           roofline (plain_fp64.roofline).
+The roofline line is the serving path's analysis kernel (BF16 contractions,
+FP64 eigensolve), timed with HIP events on one instance per launch.  The CPU
+baseline is the FP64 oracle over the host's cores (a process pool over the
+domains) and on one core.
 
     python bench.py [--steps K] [--warmup W] [--instances B] [--precision fp64|fp32|bf16]
 
@@ -41,22 +47,36 @@ PEAK_HBM_GBS = 8000.0
 FP64_ = 0        # precision code of the FP64 path (the library's LETKF_FP64)
 
 METRIC = "frames/s + p50/p99 frame latency (µs), LETKF 84×84 subaps m=64"
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_analysis_fp64_84x84_m64_traffic.txt")
+TRAFFIC_FILES = {  # rocprofv3 counter summaries of the analysis kernel, per precision path
+    "fp64": os.path.join(ROOT, "profiles", "k_analysis_fp64_84x84_m64_traffic.txt"),
+    "bf16": os.path.join(ROOT, "profiles", "k_analysis_bf16_84x84_m64_traffic.txt"),
+}
 
 
-def measured_traffic(kernels: str, tuning):
-    """HBM bytes per k_analysis launch from the committed rocprofv3 counter
+def measured_traffic(path: str, kernels: str, tuning):
+    """HBM bytes per k_analysis launch from a committed rocprofv3 counter
     summary (FETCH_SIZE x fetch scale + WRITE_SIZE x write scale) for the
     launch shape (domain order, grid) this run chose, or None when the summary
     was taken on another build of the device code or has no such shape."""
     try:
-        kv = dict(line.split(":", 1) for line in open(TRAFFIC_FILE) if ":" in line and not line.startswith("#"))
+        kv = dict(line.split(":", 1) for line in open(path) if ":" in line and not line.startswith("#"))
     except OSError:
         return None
     if kv.get("kernels", "").strip() != kernels or not tuning:
         return None
     v = kv.get(f"traffic_bytes_per_launch.{tuning['order']}.{tuning['grid']}")
     return float(v) if v is not None else None
+
+
+def unique_bytes(case, esize: int) -> int:
+    """Bytes the analysis kernel must move at least per launch: every slope row
+    of Y' and every state row of X read once (esize bytes per value), d and
+    r (8 bytes each per slope), and the per-domain analysis rows Z written
+    once.  The ratio of the measured HBM traffic to this is the re-read and
+    scratch overhead."""
+    m, p, n = case.m, 2 * case.n_sub, 2 * case.n_act
+    zrows = 2 * int(case.dmap.est_ptr[-1])
+    return int(p * m * esize + n * m * esize + 16 * p + zrows * m * esize)
 
 
 def analysis_flops(m: int, dmap, sweeps_total: int, solves: int, frames: int) -> float:
@@ -274,30 +294,138 @@ def run_closed_loop(ms, frames: int, burn_in: int) -> dict:
                                  by_m=rows), library=build_id())
 
 
-def cpu_baseline(case, seconds: float = 15.0):
-    """The FP64 oracle on the host, one thread, on the first frames of the
-    same workload until `seconds` have passed (at least two frames)."""
+def cpu_model() -> str:
+    """The host CPU's model name (/proc/cpuinfo), as lscpu reports it."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def host_cores(cap: int = 16) -> int:
+    """Cores this process may run on, at most `cap` (a GPU machine's CPU share)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(n, cap))
+
+
+_CPU = {}   # per worker process of the CPU baseline: shared arrays and the domain map
+
+
+def _cpu_init(shm_names, shapes, dmap, n_act, n_sub, r_inv, rho):
+    from multiprocessing import shared_memory
+
+    from threadpoolctl import threadpool_limits
+    _CPU["limit"] = threadpool_limits(limits=1)          # BLAS at one thread per worker
+    _CPU["shm"] = [shared_memory.SharedMemory(name=n) for n in shm_names]
+    _CPU["arr"] = [np.ndarray(sh, dtype=np.float64, buffer=m.buf) for m, sh in zip(_CPU["shm"], shapes)]
+    _CPU.update(dmap=dmap, n_act=n_act, n_sub=n_sub, r_inv=r_inv, rho=rho)
+
+
+def _cpu_domains(ls):
+    """The oracle's per-domain analysis of domains `ls`; Z rows into the shared output."""
+    import oracle
+    from oracle.letkf import domain_rows
+    Xp, xbar, Yp, d, Z = _CPU["arr"]
+    dm = _CPU["dmap"]
+    for l in ls:
+        E, O, srows, orows = domain_rows(dm, l, _CPU["n_act"], _CPU["n_sub"])
+        taper = np.asarray(dm.taper(l), dtype=float)
+        r_O = np.concatenate([taper, taper]) * _CPU["r_inv"][orows]
+        res = oracle.domain_analysis(Xp[srows], xbar[srows], Yp[orows], d[orows], r_O, _CPU["rho"])
+        z0 = 2 * int(dm.est_ptr[l])
+        Z[z0:z0 + len(srows)] = res["Z"]
+    return len(ls)
+
+
+def cpu_baseline_pool(case, seconds: float, cores: int):
+    """The FP64 oracle on `cores` host cores: per frame the parent forms the
+    ensemble mean, perturbations and slopes (oracle.letkf), a pool of worker
+    processes (one per core, BLAS at one thread each, started before the GPU
+    is touched) runs the oracle's domain analysis on interleaved shares of the
+    domains through shared memory, and the parent merges and forecasts.
+    Frames of the same workload until `seconds` have passed (at least two)."""
+    import multiprocessing as mp
+    from multiprocessing import shared_memory
+
+    import scipy.sparse as sp
+
+    import oracle
+    from oracle.letkf import domain_rows
+    D = sp.csr_matrix((case.D.val, case.D.col, case.D.rowptr), shape=case.D.shape)
+    dm, m, n_act, n_sub = case.dmap, case.m, case.n_act, case.n_sub
+    zrows = 2 * int(dm.est_ptr[-1])
+    shapes = [(2 * n_act, m), (2 * n_act,), (2 * n_sub, m), (2 * n_sub,), (zrows, m)]
+    shms = [shared_memory.SharedMemory(create=True, size=int(np.prod(sh)) * 8) for sh in shapes]
+    try:
+        Xp_s, xbar_s, Yp_s, d_s, Z_s = (np.ndarray(sh, dtype=np.float64, buffer=mm.buf) for mm, sh in zip(shms, shapes))
+        shares = [list(range(k, dm.n_domains, cores)) for k in range(cores)]
+        ctx = mp.get_context("fork")
+        with ctx.Pool(cores, initializer=_cpu_init,
+                      initargs=([mm.name for mm in shms], shapes, dm, n_act, n_sub, case.r_inv, case.inflation)) as pool:
+            X = case.X0.copy()
+            times = []
+            t0 = time.perf_counter()
+            k = 0
+            while k < 2 or time.perf_counter() - t0 < seconds:
+                y = case.slopes(k)
+                ts = time.perf_counter()
+                xbar, Xp = oracle.ensemble_mean_perturbations(X)
+                ybar, Yp = oracle.slope_synthesis(D, X, n_act)
+                Xp_s[:], xbar_s[:], Yp_s[:], d_s[:] = Xp, xbar, Yp, y - ybar
+                pool.map(_cpu_domains, shares)
+                Xa = np.zeros_like(X)
+                for l in range(dm.n_domains):       # the oracle's merge
+                    E, O, srows, orows = domain_rows(dm, l, n_act, n_sub)
+                    w = np.asarray(dm.weights(l), dtype=float)
+                    z0 = 2 * int(dm.est_ptr[l])
+                    Xa[srows] += np.concatenate([w, w])[:, None] * Z_s[z0:z0 + len(srows)]
+                X = oracle.forecast(Xa, case.a1, case.a2, case.sigma_v, case.philox_seed, k)
+                times.append(time.perf_counter() - ts)
+                k += 1
+    finally:
+        for mm in shms:
+            mm.close()
+            mm.unlink()
+    return len(times) / float(np.sum(times)), len(times)
+
+
+def cpu_baseline(case, seconds: float = 12.0, single_seconds: float = 6.0):
+    """The FP64 oracle timed on the host: over the host's cores (a process pool,
+    the plan of the baseline) and on one core, each on the first frames of the
+    same workload for about `seconds` / `single_seconds`."""
     import scipy.sparse as sp
     from threadpoolctl import threadpool_limits
 
     import oracle
+    cores = host_cores()
+    fps, n_pool = cpu_baseline_pool(case, seconds, cores)
     D = sp.csr_matrix((case.D.val, case.D.col, case.D.rowptr), shape=case.D.shape)
     X = case.X0.copy()
     ys = []
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
         k = 0
-        while k < 2 or time.perf_counter() - t0 < seconds:
+        while k < 2 or time.perf_counter() - t0 < single_seconds:
             y = case.slopes(k)
             ts = time.perf_counter()
             Xa = oracle.analysis(X, y, D, case.dmap, case.r_inv, case.inflation)
             X = oracle.forecast(Xa, case.a1, case.a2, case.sigma_v, case.philox_seed, k)
             ys.append(time.perf_counter() - ts)
             k += 1
-    fps = len(ys) / float(np.sum(ys))
-    return dict(value=round(fps, 3), unit="frames/s", cores=1, kind="oracle",
-                sample=f"first {len(ys)} frames of the same {case.cfg['lenslets']}x{case.cfg['lenslets']}, "
-                       f"m={case.m} workload (NumPy/LAPACK FP64, 1 thread)")
+    fps1 = len(ys) / float(np.sum(ys))
+    L_ = case.cfg["lenslets"]
+    return dict(value=round(fps, 3), unit="frames/s", cores=cores, kind="oracle",
+                cpu=cpu_model(),
+                sample=f"first {n_pool} frames of the same {L_}x{L_}, m={case.m} workload: NumPy/LAPACK FP64 oracle, "
+                       f"domains over a pool of {cores} worker processes (BLAS at 1 thread each)",
+                single_core=dict(value=round(fps1, 3), unit="frames/s", cores=1,
+                                 sample=f"first {len(ys)} frames, oracle.analysis + forecast on one thread"))
 
 
 PISTONS = False  # set from --pistons
@@ -410,10 +538,15 @@ def run_plain_loaded(case, B, K, W, ys):
                 p99_us=float(np.percentile(lat_us, 99)))
 
 
-def run_serving(case, prec, B, K, W, ys, depth=1):
+def run_serving(case, prec, B, K, W, ys, depth=1, NL=0, fp32_rotations=False):
     """B resident instances in a closed loop through the batching server, each
     keeping `depth` frames submitted (depth 1: a frame is submitted when the
-    previous one of that instance is done).  Latency = submit to callback."""
+    previous one of that instance is done).  Frames W .. W+K-1 of every
+    instance are timed (throughput: their count over the span from the first
+    one's submission to the last one's completion); latency = submit to
+    callback over frames W .. W+K+NL-1, so the loop continues for NL frames
+    per instance past the timed ones.  ys: device slopes (a CUDA tensor, read
+    in place) or host slopes (a numpy array, copied at submission)."""
     import threading
 
     import torch
@@ -421,10 +554,10 @@ def run_serving(case, prec, B, K, W, ys, depth=1):
     from paper_1310_5954_amd import Problem, Server
     from paper_1310_5954_amd import _lib as L
     pr = Problem.from_case(case)
-    flags = L.FLAG_PISTONS if PISTONS else 0
+    flags = (L.FLAG_PISTONS if PISTONS else 0) | (L.FLAG_FP32_ROTATIONS if fp32_rotations else 0)
     budget = B * pr.workspace_size(prec, flags) + L.lib().letkf_server_reserved_bytes() + (16 << 20)
     # instance i starts from the ensemble shifted by i columns and reads frame k + 7 i of the slope stream
-    total = W + K
+    total = W + K + NL
     state = dict(t_sub={}, t_done={}, done=0)
     cv = threading.Condition()
     preds = [np.empty(case.n_act) for _ in range(B)]
@@ -446,7 +579,8 @@ def run_serving(case, prec, B, K, W, ys, depth=1):
             cv.notify_all()
 
     srv = Server(budget, on_done=on_done, graphs=GRAPHS, max_batch=MAX_BATCH or max(1, (B + 1) // 2))
-    insts = [srv.add(pr, np.roll(case.X0, i, axis=1), prec, pistons=PISTONS) for i in range(B)]
+    insts = [srv.add(pr, np.roll(case.X0, i, axis=1), prec, pistons=PISTONS, fp32_rotations=fp32_rotations)
+             for i in range(B)]
     tuning = list(srv.autotune().values())[0] if TUNE else None
     torch.cuda.synchronize()
     # warm-up frames 0..W-1 run in the same closed loop; the clock starts when every instance has finished them
@@ -459,14 +593,14 @@ def run_serving(case, prec, B, K, W, ys, depth=1):
     srv.drain()
     st = srv.stats()
     srv.close()
-    # timed frames: k >= W of every instance; throughput over the span from the
-    # first timed submission to the last timed completion (the completion
-    # thread's clock, so the main thread's wake-ups do not enter it)
-    timed = [i * 1_000_000 + k for i in range(B) for k in range(W, total)]
-    lat_us = np.array([state["t_done"][f] - state["t_sub"][f] for f in timed]) * 1e6
+    # timed frames: W <= k < W + K of every instance, on the completion thread's
+    # clock, so the main thread's wake-ups do not enter it
+    timed = [i * 1_000_000 + k for i in range(B) for k in range(W, W + K)]
+    sampled = [i * 1_000_000 + k for i in range(B) for k in range(W, total)]
+    lat_us = np.array([state["t_done"][f] - state["t_sub"][f] for f in sampled]) * 1e6
     span = max(state["t_done"][f] for f in timed) - min(state["t_sub"][f] for f in timed)
     return dict(fps=len(timed) / span, p50_us=float(np.percentile(lat_us, 50)),
-                p99_us=float(np.percentile(lat_us, 99)), batches=st["batches"],
+                p99_us=float(np.percentile(lat_us, 99)), latency_frames=len(sampled), batches=st["batches"],
                 mean_batch=st["batched_frames"] / max(st["batches"], 1), tuning=tuning)
 
 
@@ -582,7 +716,13 @@ def main() -> int:
                     help="precision path of the serving form (the plain form is always FP64)")
     ap.add_argument("--phases-precision", default="fp64", choices=["fp64", "fp32", "bf16"],
                     help="--phases: precision path of the debug instance")
-    ap.add_argument("--latency-frames", type=int, default=200)
+    ap.add_argument("--latency-frames", type=int, default=500,
+                    help="plain path: frames timed one by one for the latency percentiles")
+    ap.add_argument("--serving-latency-frames", type=int, default=500,
+                    help="serving: at least this many frames in the latency percentiles (the closed loop "
+                         "continues past the timed frames)")
+    ap.add_argument("--fp32-rotations", action="store_true",
+                    help="--serving-only: the opt-in FP32 Jacobi rotations (BF16 path)")
     ap.add_argument("--plain-only", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mix", type=float, default=0.0, metavar="SECONDS",
@@ -650,11 +790,18 @@ def main() -> int:
     prec = dict(fp64=FP64, fp32=FP32, bf16=BF16)[args.precision]
     case = build_case(3 if args.workload == 84 else 5, partitions=args.partitions)
     K, W, NL, B = args.steps, args.warmup, args.latency_frames, args.instances
+    NLS = -(-max(0, args.serving_latency_frames - B * K) // B)  # serving frames per instance past the timed ones
     n_frames = W + K + NL
     L_ = case.cfg["lenslets"]
     print(f"[bench] {L_}x{L_} m={case.m} domains={case.dmap.n_domains} library={build_id()} frames={n_frames}",
           file=sys.stderr, flush=True)
-    ys_host = np.stack([case.slopes(k) for k in range(n_frames)])
+    # the CPU baseline's worker processes are forked before anything touches the GPU
+    cpu = None
+    if not args.no_cpu_baseline and not (args.phases or args.serving_only):
+        cpu = cpu_baseline(case)
+        print(f"[bench] cpu baseline (oracle): {cpu['value']:.2f} frames/s on {cpu['cores']} cores "
+              f"({cpu['cpu']}), {cpu['single_core']['value']:.2f} frames/s on one", file=sys.stderr, flush=True)
+    ys_host = np.stack([case.slopes(k) for k in range(max(n_frames, W + K + NLS))])
     ys = torch.tensor(ys_host, dtype=torch.float64, device="cuda:0")
 
     if args.phases:
@@ -663,75 +810,126 @@ def main() -> int:
                               library=build_id())), flush=True)
         return 0
     if args.serving_only:
-        lat = run_serving(case, prec, B, K, W, ys, depth=1)
+        lat = run_serving(case, prec, B, K, W, ys, depth=1, NL=NLS, fp32_rotations=args.fp32_rotations)
         print(json.dumps(dict(metric=METRIC, value=round(lat["fps"], 2), unit="frames/s", n_gpus=1, steps=K,
                               warmup=W, p50_us=round(lat["p50_us"], 1), p99_us=round(lat["p99_us"], 1),
-                              mean_batch=round(lat["mean_batch"], 3), precision=args.precision,
+                              latency_frames=lat["latency_frames"], mean_batch=round(lat["mean_batch"], 3),
+                              precision=args.precision, fp32_rotations=args.fp32_rotations,
                               graphs=GRAPHS, tuning=lat["tuning"], library=build_id())), flush=True)
         return 0
+
+    def roofline_of(run, path_name):
+        """Algorithmic FP64-dominated work of one analysis launch over its
+        HIP-event duration; HBM traffic from the committed counter summary."""
+        ana_ms = run["kernel_ms"][1]
+        flops = analysis_flops(case.m, case.dmap, run["sweeps"], run["solves"], K) / K
+        achieved = flops / (ana_ms * 1e-3) / 1e12
+        es = 8 if path_name == "fp64" else 4
+        traffic = measured_traffic(TRAFFIC_FILES[path_name], kernel_hash(), run["tuning"]) if args.workload == 84 else None
+        uniq = unique_bytes(case, es)
+        return dict(bound="alu", achieved=round(achieved, 3), peak=PEAK_FP64_TFLOPS, unit="TFLOP/s",
+                    frac=round(achieved / PEAK_FP64_TFLOPS, 4), traffic=traffic,
+                    unique_bytes=uniq, traffic_over_unique=round(traffic / uniq, 3) if traffic else None,
+                    kernel_us=round(ana_ms * 1e3, 2), flops_per_launch=round(flops),
+                    jacobi_sweeps_mean=round(run["sweeps"] / max(run["solves"], 1), 3))
+
     plain = run_plain(case, FP64, K, W, NL, ys)
     print(f"[bench] plain fp64: {plain['fps']:.1f} frames/s p50 {plain['p50_us']:.0f} us "
           f"p99 {plain['p99_us']:.0f} us", file=sys.stderr, flush=True)
     graph = run_plain_graph(case, K, W, NL, ys)
     print(f"[bench] plain fp64, graph replay: {graph['fps']:.1f} frames/s p50 {graph['p50_us']:.0f} us "
           f"p99 {graph['p99_us']:.0f} us", file=sys.stderr, flush=True)
-    ana_ms = plain["kernel_ms"][1]
-    flops = analysis_flops(case.m, case.dmap, plain["sweeps"], plain["solves"], K) / K
-    achieved = flops / (ana_ms * 1e-3) / 1e12
-    roofline = dict(bound="alu", achieved=round(achieved, 3), peak=PEAK_FP64_TFLOPS, unit="TFLOP/s",
-                    frac=round(achieved / PEAK_FP64_TFLOPS, 4),
-                    traffic=measured_traffic(kernel_hash(), plain["tuning"]) if args.workload == 84 else None,
-                    kernel=f"k_analysis<FP64, m={case.m}> (vector FP64: Cholesky + one-sided Jacobi dominate)")
+    rf64 = roofline_of(plain, "fp64")
+    rf64["kernel"] = f"k_analysis<FP64, m={case.m}> (vector FP64: Cholesky + one-sided Jacobi dominate)"
     plain_out = dict(frames_per_s=round(plain["fps"], 2), p50_us=round(plain["p50_us"], 1),
-                     p99_us=round(plain["p99_us"], 1),
-                     kernel_ms=dict(slopes=round(plain["kernel_ms"][0], 4), analysis=round(ana_ms, 4),
+                     p99_us=round(plain["p99_us"], 1), latency_frames=NL,
+                     kernel_ms=dict(slopes=round(plain["kernel_ms"][0], 4), analysis=round(plain["kernel_ms"][1], 4),
                                     merge_forecast=round(plain["kernel_ms"][2], 4)),
                      jacobi_sweeps_mean=round(plain["sweeps"] / max(plain["solves"], 1), 3),
                      graph_replay=dict(frames_per_s=round(graph["fps"], 2), p50_us=round(graph["p50_us"], 1),
                                        p99_us=round(graph["p99_us"], 1)),
-                     tuning=plain["tuning"])
-    dname = {FP64: "f64", FP32: "f32", BF16: "bf16+f32+f64"}
+                     tuning=plain["tuning"], roofline=rf64)
     if args.plain_only:
-        value, p50, p99, dtype, path = plain["fps"], plain["p50_us"], plain["p99_us"], "f64", "plain"
-        ms_per_step = 1e3 / plain["fps"]
-        serving_out = None
-    else:
-        loaded = run_plain_loaded(case, B, K, W, ys)
-        print(f"[bench] plain fp64 x{B} closed loop: {loaded['fps']:.1f} frames/s p50 {loaded['p50_us']:.0f} us "
-              f"p99 {loaded['p99_us']:.0f} us", file=sys.stderr, flush=True)
-        lat = run_serving(case, prec, B, K, W, ys, depth=1)
-        print(f"[bench] serving {args.precision} x{B} closed loop: {lat['fps']:.1f} frames/s p50 {lat['p50_us']:.0f} us "
-              f"p99 {lat['p99_us']:.0f} us, mean batch {lat['mean_batch']:.2f}", file=sys.stderr, flush=True)
-        value, p50, p99, dtype = lat["fps"], lat["p50_us"], lat["p99_us"], dname[prec]
-        mb = MAX_BATCH or max(1, (B + 1) // 2)
-        path = (f"serving: {B} resident instances in a closed loop (each submits its next frame when the previous "
-                f"one is done), continuous batching through the server in batches of at most {mb} frames; "
-                f"latency = submit to completion callback")
-        ms_per_step = 1e3 * B / lat["fps"]
-        plain_out["closed_loop"] = dict(instances=B, frames_per_s=round(loaded["fps"], 2),
-                                        p50_us=round(loaded["p50_us"], 1), p99_us=round(loaded["p99_us"], 1))
-        serving_out = dict(instances=B, max_batch=mb, mean_batch=round(lat["mean_batch"], 3), graphs=GRAPHS,
-                           tuning=lat["tuning"],
-                           beats_plain_fp64=bool(lat["fps"] > loaded["fps"] and lat["p99_us"] < loaded["p99_us"]))
+        out = dict(metric=METRIC if args.workload == 84 else METRIC.replace("84×84", "128×128").replace("m=64", "m=128"),
+                   value=round(plain["fps"], 2), unit="frames/s", n_gpus=1, steps=K, warmup=W,
+                   ms_per_step=round(1e3 / plain["fps"], 4), higher_is_better=True, scaling="weak", vs_baseline=None,
+                   dtype="f64", data="synthetic",
+                   config=dict(workload=f"{L_}x{L_} circular SH pupil, m={case.m}, {case.dmap.n_domains} domains",
+                               path="plain", precision="fp64"),
+                   p50_us=round(plain["p50_us"], 1), p99_us=round(plain["p99_us"], 1), roofline=rf64,
+                   plain_fp64=plain_out, library=build_id())
+        if cpu:
+            out["cpu_baseline"] = cpu
+        print(json.dumps(out), flush=True)
+        return 0
+    # the serving path's analysis kernel, one instance per launch (HIP events on its stream)
+    plain_s = run_plain(case, prec, K, W, min(NL, 50), ys)
+    print(f"[bench] plain {args.precision}: analysis {plain_s['kernel_ms'][1] * 1e3:.1f} us per launch",
+          file=sys.stderr, flush=True)
+    roofline = roofline_of(plain_s, "bf16" if prec == BF16 else ("fp64" if prec == FP64 else "fp32"))
+    roofline["kernel"] = (f"k_analysis<{args.precision.upper()}, m={case.m}>, the serving path's analysis kernel, "
+                          f"one instance ({case.dmap.n_domains} domains) per launch (vector FP64: Cholesky + one-sided "
+                          f"Jacobi dominate; C and X'T on {args.precision.upper()} MFMA)")
+    loaded = run_plain_loaded(case, B, K, W, ys)
+    print(f"[bench] plain fp64 x{B} closed loop: {loaded['fps']:.1f} frames/s p50 {loaded['p50_us']:.0f} us "
+          f"p99 {loaded['p99_us']:.0f} us", file=sys.stderr, flush=True)
+    lat = run_serving(case, prec, B, K, W, ys, depth=1, NL=NLS)
+    print(f"[bench] serving {args.precision} x{B} closed loop: {lat['fps']:.1f} frames/s p50 {lat['p50_us']:.0f} us "
+          f"p99 {lat['p99_us']:.0f} us ({lat['latency_frames']} latency frames), mean batch {lat['mean_batch']:.2f}",
+          file=sys.stderr, flush=True)
+    host = run_serving(case, prec, B, K, W, ys_host, depth=1, NL=NLS)
+    print(f"[bench] serving {args.precision}, host slopes: {host['fps']:.1f} frames/s p50 {host['p50_us']:.0f} us "
+          f"p99 {host['p99_us']:.0f} us", file=sys.stderr, flush=True)
+    rot32 = None
+    if prec == BF16:
+        rot32 = run_serving(case, prec, B, K, W, ys, depth=1, NL=NLS, fp32_rotations=True)
+        print(f"[bench] serving bf16 with FP32 rotations: {rot32['fps']:.1f} frames/s p50 {rot32['p50_us']:.0f} us "
+              f"p99 {rot32['p99_us']:.0f} us", file=sys.stderr, flush=True)
+    # whole-job rate of the serving form: the analysis kernel's algorithmic work per frame at `value` frames/s
+    flops_frame = roofline["flops_per_launch"]
+    roofline["serving_wall"] = dict(achieved=round(flops_frame * lat["fps"] / 1e12, 3),
+                                    frac=round(flops_frame * lat["fps"] / 1e12 / PEAK_FP64_TFLOPS, 4),
+                                    note="analysis work per frame x serving frames/s (wall clock, batches overlap)")
+    mb = MAX_BATCH or max(1, (B + 1) // 2)
+    path = (f"serving: {B} resident instances in a closed loop (each submits its next frame when the previous one "
+            f"is done), continuous batching through the server in batches of at most {mb} frames, device-resident "
+            f"slopes; latency = submit to completion callback")
+    dname = {FP64: "f64", FP32: "f32+f64", BF16: "bf16+f64"}
+    pname = {FP64: "fp64", FP32: "fp32 contractions (FP32 MFMA), FP64 eigensolve, wbar and W",
+             BF16: "bf16 contractions (BF16 MFMA, FP32 accumulation), FP64 eigensolve (Cholesky, Jacobi rotations), "
+                   "FP64 wbar and W"}
     out = dict(
         metric=METRIC if args.workload == 84 else METRIC.replace("84×84", "128×128").replace("m=64", "m=128"),
-        value=round(value, 2), unit="frames/s", n_gpus=1, steps=K, warmup=W,
-        ms_per_step=round(ms_per_step, 4), higher_is_better=True, scaling="weak", vs_baseline=None,
-        dtype=dtype, data="synthetic",
+        value=round(lat["fps"], 2), unit="frames/s", n_gpus=1, steps=K, warmup=W,
+        ms_per_step=round(1e3 * B / lat["fps"], 4), higher_is_better=True, scaling="weak", vs_baseline=None,
+        dtype=dname[prec], data="synthetic",
         config=dict(workload=f"{L_}x{L_} circular SH pupil, {case.n_act} actuators (n={2 * case.n_act}), "
                              f"{case.n_sub} subapertures (p={2 * case.n_sub}), "
                              f"m={case.m}, {case.dmap.n_domains} overlapping 6x6-actuator domains"
                              + (" (two staggered partitions, averaged)" if args.partitions == 2 else "")
                              + (", differential pistons removed before the merge" if args.pistons else "")
                              + ", halo 2, Gaspari-Cohn taper; one frame = analysis + AR(2) forecast",
-                    path=path, precision=args.precision if serving_out else "fp64"),
-        p50_us=round(p50, 1), p99_us=round(p99, 1),
-        plain_fp64=plain_out, roofline=roofline, library=build_id(),
+                    path=path, precision=pname[prec]),
+        p50_us=round(lat["p50_us"], 1), p99_us=round(lat["p99_us"], 1), latency_frames=lat["latency_frames"],
+        roofline=roofline,
+        serving=dict(instances=B, max_batch=mb, mean_batch=round(lat["mean_batch"], 3), graphs=GRAPHS,
+                     tuning=lat["tuning"],
+                     beats_plain_fp64=bool(lat["fps"] > loaded["fps"] and lat["p99_us"] < loaded["p99_us"]),
+                     host_slopes=dict(frames_per_s=round(host["fps"], 2), p50_us=round(host["p50_us"], 1),
+                                      p99_us=round(host["p99_us"], 1), latency_frames=host["latency_frames"],
+                                      note="slopes submitted from host memory (letkf_submit_frame): 88 KB H2D "
+                                           "per frame inside the latency")),
+        plain_fp64=dict(plain_out, closed_loop=dict(instances=B, frames_per_s=round(loaded["fps"], 2),
+                                                    p50_us=round(loaded["p50_us"], 1), p99_us=round(loaded["p99_us"], 1))),
+        library=build_id(),
     )
-    if serving_out:
-        out["serving"] = serving_out
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(case)
+    if rot32:
+        out["serving_fp32_rotations"] = dict(frames_per_s=round(rot32["fps"], 2), p50_us=round(rot32["p50_us"], 1),
+                                             p99_us=round(rot32["p99_us"], 1), latency_frames=rot32["latency_frames"],
+                                             note="opt-in LETKF_FLAG_FP32_ROTATIONS: the Jacobi rotations in FP32, a "
+                                                  "departure from the FP64 eigensolve")
+    if cpu:
+        out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
     return 0
 
