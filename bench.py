@@ -723,7 +723,10 @@ def main() -> int:
                          "continues past the timed frames)")
     ap.add_argument("--fp32-rotations", action="store_true",
                     help="--serving-only: the opt-in FP32 Jacobi rotations (BF16 path)")
-    ap.add_argument("--plain-only", action="store_true")
+    ap.add_argument("--plain-only", action="store_true",
+                    help="only the plain per-frame path (precision --plain-precision)")
+    ap.add_argument("--plain-precision", default="fp64", choices=["fp64", "fp32", "bf16"],
+                    help="--plain-only: precision path of the plain instance")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mix", type=float, default=0.0, metavar="SECONDS",
                     help="instead of the headline run: six mixed instances with Poisson arrivals for SECONDS")
@@ -833,6 +836,20 @@ def main() -> int:
                     kernel_us=round(ana_ms * 1e3, 2), flops_per_launch=round(flops),
                     jacobi_sweeps_mean=round(run["sweeps"] / max(run["solves"], 1), 3))
 
+    if args.plain_only and args.plain_precision != "fp64":
+        pp = dict(fp32=FP32, bf16=BF16)[args.plain_precision]
+        run = run_plain(case, pp, K, W, NL, ys)
+        rl = roofline_of(run, args.plain_precision)
+        rl["kernel"] = f"k_analysis<{args.plain_precision.upper()}, m={case.m}>, one instance per launch"
+        out = dict(metric=METRIC, value=round(run["fps"], 2), unit="frames/s", n_gpus=1, steps=K, warmup=W,
+                   ms_per_step=round(1e3 / run["fps"], 4), higher_is_better=True, scaling="weak", vs_baseline=None,
+                   dtype={"fp32": "f32+f64", "bf16": "bf16+f64"}[args.plain_precision], data="synthetic",
+                   config=dict(workload=f"{L_}x{L_} circular SH pupil, m={case.m}, {case.dmap.n_domains} domains",
+                               path="plain", precision=args.plain_precision),
+                   p50_us=round(run["p50_us"], 1), p99_us=round(run["p99_us"], 1), roofline=rl,
+                   tuning=run["tuning"], library=build_id())
+        print(json.dumps(out), flush=True)
+        return 0
     plain = run_plain(case, FP64, K, W, NL, ys)
     print(f"[bench] plain fp64: {plain['fps']:.1f} frames/s p50 {plain['p50_us']:.0f} us "
           f"p99 {plain['p99_us']:.0f} us", file=sys.stderr, flush=True)
