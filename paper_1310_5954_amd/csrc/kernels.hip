@@ -944,6 +944,7 @@ __device__ __forceinline__ int jacobi_core(AnaSmem<M>& sm, int m, R* B, R* nrm, 
   // do; the Gram test decides that in a fraction of a sweep's cost.
   const R trig = tol * (R)100 > (R)1e-7 ? tol * (R)100 : (R)1e-7;
   const R trig2 = trig * trig;
+  constexpr bool PREFETCH = C::RPT <= 16;
   int sweeps = 0;
   converged = false;
   for (; sweeps < C::MAX_SWEEPS;) {
@@ -988,31 +989,44 @@ __device__ __forceinline__ int jacobi_core(AnaSmem<M>& sm, int m, R* B, R* nrm, 
       }
     }
     bool big = false;
+#pragma unroll
     for (int h = 0; (1 << h) < M; ++h) {
       const int i = ((q >> h) << (h + 1)) | (q & ((1 << h) - 1));
+      const int kend = 2 << h;
       R xi[C::RPT];
       R al = 0;
-      if (active) {
+      // One step k: pair (i, i ^ k) with the partner column in xc (norm bc).
+      // With PREFETCH the next step's partner is loaded into xn (norm bn)
+      // before this step rotates the lower column (registers only), so that
+      // its LDS latency overlaps that arithmetic instead of stalling the next
+      // dot product; two register sets alternate between consecutive steps.
+      // (M = 128 holds 32 rows per lane: a second set would spill, so there
+      // each step loads its own partner.)
+      auto step = [&](const int k, R (&xc)[C::RPT], R& bc, R (&xn)[C::RPT], R& bn) {
+        // the lower column index as a value the compiler may not carry across
+        // steps: unrolled, it would otherwise keep every step's partner
+        // address live from the start of the group (registers, occupancy)
+        int iv = i;
+        __asm__ volatile("" : "+v"(iv));
+        const int jj = iv ^ k;
+        R c = 1, sn = 0;
+        bool rot = false;
+        if (!PREFETCH && active) {
 #pragma unroll
-        for (int t = 0; t < C::RPT; ++t) xi[t] = B[i * LD + sub + t * TPP];
-        al = nrm[i];
-      }
-      for (int k = 1 << h; k < (2 << h); ++k) {
+          for (int t = 0; t < C::RPT; ++t) xc[t] = B[jj * LD + sub + t * TPP];
+          bc = nrm[jj];
+        }
         if (active) {
-          const int jj = i ^ k;
-          R* bj = B + jj * LD;
-          const R be = nrm[jj];
-          R xj[C::RPT];
           R g0 = 0, g1 = 0;
 #pragma unroll
           for (int t = 0; t < C::RPT; ++t) {
-            xj[t] = bj[sub + t * TPP];
-            if (t & 1) g1 = fma(xi[t], xj[t], g1);
-            else g0 = fma(xi[t], xj[t], g0);
+            if (t & 1) g1 = fma(xi[t], xc[t], g1);
+            else g0 = fma(xi[t], xc[t], g0);
           }
           const R gsum = group_sum<TPP>(g0 + g1);
-          const R ab = al * be;
+          const R ab = al * bc;
           if (gsum * gsum > tol2 * ab) {
+            rot = true;
             big |= gsum * gsum > trig2 * ab;
             // t = tan(theta), the smaller root of t^2 + 2 zeta t - 1 = 0 with
             // zeta = (be - al) / (2 gsum), written without the quotient zeta.
@@ -1020,21 +1034,19 @@ __device__ __forceinline__ int jacobi_core(AnaSmem<M>& sm, int m, R* B, R* nrm, 
             // rounding for whatever t is used, so t itself comes from the
             // hardware's approximate rsq / rcp: its error only changes how far
             // this rotation reduces gsum, never orthogonality.
-            const R dd = be - al, g2 = (R)2 * gsum;
+            const R dd = bc - al, g2 = (R)2 * gsum;
             const R q2 = fma(dd, dd, g2 * g2);
             const R den = fma(q2, approx_rsq(q2), fabs(dd));
             const R t = copysign((R)1, dd) * g2 * approx_rcp(den);
-            const R c = rsqrt_acc(fma(t, t, (R)1));
-            const R sn = c * t;
+            c = rsqrt_acc(fma(t, t, (R)1));
+            sn = c * t;
+            // the partner first: the slot that pairs it next reads it from LDS
+            R* bj = B + jj * LD;
 #pragma unroll
-            for (int u = 0; u < C::RPT; ++u) {
-              const R a = xi[u];
-              xi[u] = c * a - sn * xj[u];
-              bj[sub + u * TPP] = sn * a + c * xj[u];
-            }
+            for (int u = 0; u < C::RPT; ++u) bj[sub + u * TPP] = sn * xi[u] + c * xc[u];
             al -= t * gsum;
             if (sub == 0) {
-              nrm[jj] = be + t * gsum;
+              nrm[jj] = bc + t * gsum;
               sm.s_rot = 1;
             }
           }
@@ -1046,8 +1058,39 @@ __device__ __forceinline__ int jacobi_core(AnaSmem<M>& sm, int m, R* B, R* nrm, 
         // wavefront take effect in order.  Only those steps need the
         // workgroup barrier (the group's last step is followed by one anyway);
         // the others only keep the compiler from moving LDS accesses across.
-        if ((k + 1) % PSW == 0 && k + 1 < (2 << h)) __syncthreads();
+        if ((k + 1) % PSW == 0 && k + 1 < kend) __syncthreads();
         else __asm__ volatile("" ::: "memory");
+        if (PREFETCH && active && k + 1 < kend) {
+          const R* bk = B + (iv ^ (k + 1)) * LD;
+#pragma unroll
+          for (int t = 0; t < C::RPT; ++t) xn[t] = bk[sub + t * TPP];
+          bn = nrm[iv ^ (k + 1)];
+        }
+        if (rot) {
+#pragma unroll
+          for (int u = 0; u < C::RPT; ++u) xi[u] = c * xi[u] - sn * xc[u];
+        }
+      };
+      R xa[C::RPT], xb[PREFETCH ? C::RPT : 1];
+      R ba = 0, bb = 0;
+      if (active) {
+        const R* b0 = B + (i ^ (1 << h)) * LD;  // the group's first partner
+#pragma unroll
+        for (int t = 0; t < C::RPT; ++t) {
+          xi[t] = B[i * LD + sub + t * TPP];
+          if (PREFETCH) xa[t] = b0[sub + t * TPP];
+        }
+        al = nrm[i];
+        if (PREFETCH) ba = nrm[i ^ (1 << h)];
+      }
+      if constexpr (PREFETCH) {
+#pragma unroll
+        for (int k = 1 << h; k < kend; k += 2) {
+          step(k, xa, ba, xb, bb);
+          if (k + 1 < kend) step(k + 1, xb, bb, xa, ba);
+        }
+      } else {
+        for (int k = 1 << h; k < kend; ++k) step(k, xa, ba, xa, ba);
       }
       if (active) {
 #pragma unroll
