@@ -860,6 +860,9 @@ __device__ __forceinline__ float approx_rsq(float x) { return __builtin_amdgcn_r
 __device__ __forceinline__ double approx_rcp(double x) { return __builtin_amdgcn_rcp(x); }
 __device__ __forceinline__ float approx_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ double rsqrt_acc(double x) { return rsqrt_1_2(x); }
+// the word holding the sign: non-negative exactly when x >= +0
+__device__ __forceinline__ int sign_word(double x) { return (int)(__double_as_longlong(x) >> 32); }
+__device__ __forceinline__ int sign_word(float x) { return __float_as_int(x); }
 __device__ __forceinline__ float rsqrt_acc(float x) { return __builtin_amdgcn_rsqf(x); }
 
 // Group sum of a float (same lane patterns as the double form).
@@ -944,7 +947,14 @@ __device__ __forceinline__ int jacobi_core(AnaSmem<M>& sm, int m, R* B, R* nrm, 
   // do; the Gram test decides that in a fraction of a sweep's cost.
   const R trig = tol * (R)100 > (R)1e-7 ? tol * (R)100 : (R)1e-7;
   const R trig2 = trig * trig;
+  const R tol4 = (R)4 * tol2, trig4 = (R)4 * trig2;
   constexpr bool PREFETCH = C::RPT <= 16;
+  // the step's column and norm accesses through LDS-typed pointers, so that
+  // their addresses are 32-bit offsets (a generic pointer makes every partner
+  // address a 64-bit multiply-add)
+  using LR = __attribute__((address_space(3))) R;
+  LR* const LB = (LR*)B;
+  LR* const LN = (LR*)nrm;
   int sweeps = 0;
   converged = false;
   for (; sweeps < C::MAX_SWEEPS;) {
@@ -988,7 +998,7 @@ __device__ __forceinline__ int jacobi_core(AnaSmem<M>& sm, int m, R* B, R* nrm, 
         __syncthreads();  // the moved columns and norms before the sweep reads them
       }
     }
-    bool big = false;
+    int big = INT_MIN;
 #pragma unroll
     for (int h = 0; (1 << h) < M; ++h) {
       const int i = ((q >> h) << (h + 1)) | (q & ((1 << h) - 1));
@@ -1008,13 +1018,14 @@ __device__ __forceinline__ int jacobi_core(AnaSmem<M>& sm, int m, R* B, R* nrm, 
         // address live from the start of the group (registers, occupancy)
         int iv = i;
         __asm__ volatile("" : "+v"(iv));
+        iv &= M - 1;  // a known range: 24-bit multiply-adds for the addresses
         const int jj = iv ^ k;
         R c = 1, sn = 0;
         bool rot = false;
         if (!PREFETCH && active) {
 #pragma unroll
-          for (int t = 0; t < C::RPT; ++t) xc[t] = B[jj * LD + sub + t * TPP];
-          bc = nrm[jj];
+          for (int t = 0; t < C::RPT; ++t) xc[t] = LB[jj * LD + sub + t * TPP];
+          bc = LN[jj];
         }
         if (active) {
           R g0 = 0, g1 = 0;
@@ -1024,31 +1035,34 @@ __device__ __forceinline__ int jacobi_core(AnaSmem<M>& sm, int m, R* B, R* nrm, 
             else g0 = fma(xi[t], xc[t], g0);
           }
           const R gsum = group_sum<TPP>(g0 + g1);
-          const R ab = al * bc;
-          if (gsum * gsum > tol2 * ab) {
+          // (2 gsum)^2 serves both the test, against 4 tol^2 al bc, and the angle
+          const R ab = al * bc, g2 = gsum + gsum, g4 = g2 * g2;
+          if (g4 > tol4 * ab) {
             rot = true;
-            big |= gsum * gsum > trig2 * ab;
+            // the largest sign word of g4 - 4 trig^2 al bc: non-negative once a
+            // rotation of this sweep had a cosine above trig (an integer
+            // maximum: no exec-mask update, no NaN handling)
+            big = max(big, sign_word(fma(-trig4, ab, g4)));
             // t = tan(theta), the smaller root of t^2 + 2 zeta t - 1 = 0 with
             // zeta = (be - al) / (2 gsum), written without the quotient zeta.
             // c = (1 + t^2)^(-1/2) to the rounding of R keeps c^2 + s^2 = 1 to
             // rounding for whatever t is used, so t itself comes from the
             // hardware's approximate rsq / rcp: its error only changes how far
             // this rotation reduces gsum, never orthogonality.
-            const R dd = bc - al, g2 = (R)2 * gsum;
-            const R q2 = fma(dd, dd, g2 * g2);
+            const R dd = bc - al;
+            const R q2 = fma(dd, dd, g4);
             const R den = fma(q2, approx_rsq(q2), fabs(dd));
             const R t = copysign((R)1, dd) * g2 * approx_rcp(den);
             c = rsqrt_acc(fma(t, t, (R)1));
             sn = c * t;
             // the partner first: the slot that pairs it next reads it from LDS
-            R* bj = B + jj * LD;
+            LR* bj = LB + jj * LD;
 #pragma unroll
             for (int u = 0; u < C::RPT; ++u) bj[sub + u * TPP] = sn * xi[u] + c * xc[u];
             al -= t * gsum;
-            if (sub == 0) {
-              nrm[jj] = bc + t * gsum;
-              sm.s_rot = 1;
-            }
+            // every lane of the slot stores the same norm (and flag)
+            LN[jj] = bc + t * gsum;
+            sm.s_rot = 1;
           }
         }
         // Step k + 1 reads a partner column (and its norm) that step k wrote:
@@ -1061,10 +1075,10 @@ __device__ __forceinline__ int jacobi_core(AnaSmem<M>& sm, int m, R* B, R* nrm, 
         if ((k + 1) % PSW == 0 && k + 1 < kend) __syncthreads();
         else __asm__ volatile("" ::: "memory");
         if (PREFETCH && active && k + 1 < kend) {
-          const R* bk = B + (iv ^ (k + 1)) * LD;
+          const LR* bk = LB + (iv ^ (k + 1)) * LD;
 #pragma unroll
           for (int t = 0; t < C::RPT; ++t) xn[t] = bk[sub + t * TPP];
-          bn = nrm[iv ^ (k + 1)];
+          bn = LN[iv ^ (k + 1)];
         }
         if (rot) {
 #pragma unroll
@@ -1101,7 +1115,7 @@ __device__ __forceinline__ int jacobi_core(AnaSmem<M>& sm, int m, R* B, R* nrm, 
     }
     ++sweeps;
     const int any = sm.s_rot;
-    const int any_big = __syncthreads_or(big);
+    const int any_big = __syncthreads_or(big >= 0);
     if (!any || (!any_big && gram_converged<R, M, LD>(B, nrm, tol2))) {
       converged = true;
       break;
