@@ -805,8 +805,9 @@ int letkf_create(const letkf_dims* dims, const letkf_model* model, const letkf_d
   if (!workspace) { delete h; return fail(LETKF_EINVAL, "null workspace"); }
   if (((uintptr_t)workspace & 255) != 0) { delete h; return fail(LETKF_EINVAL, "workspace must be 256-byte aligned"); }
   if (workspace_bytes < h->L.total) {
+    const size_t need = h->L.total;
     delete h;
-    return fail(LETKF_ENOMEM, "workspace too small: need " + std::to_string(make_layout(h->P).total) + " bytes");
+    return fail(LETKF_ENOMEM, "workspace too small: need " + std::to_string(need) + " bytes");
   }
   if (hipGetDevice(&h->device) != hipSuccess) { delete h; return fail(LETKF_EDEVICE, "hipGetDevice failed"); }
   h->ws = (char*)workspace;

@@ -119,6 +119,9 @@ def test_create_rejects_small_workspace_before_device_work():
     rc = L.lib().letkf_create(C.byref(pr.dims), C.byref(pr.model), C.byref(pr.map), L.FP64, 0,
                               X0.ctypes.data_as(C.POINTER(C.c_double)), C.c_void_p(256), 1024, None, C.byref(h))
     assert rc == L.ENOMEM and not h.value
+    # the message reports the size letkf_workspace_size gives (computed before
+    # the half-built handle is released)
+    assert f"need {pr.workspace_size(L.FP64)} bytes" in L.lib().letkf_last_error().decode()
     X0[0, 0] = np.nan
     rc = L.lib().letkf_create(C.byref(pr.dims), C.byref(pr.model), C.byref(pr.map), L.FP64, 0,
                               X0.ctypes.data_as(C.POINTER(C.c_double)), C.c_void_p(256), 1 << 40, None, C.byref(h))
