@@ -870,6 +870,9 @@ template <int CTRL>
 __device__ __forceinline__ float dpp_f32(float v) {
   return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, true));
 }
+// lanes l and l ^ 8 exchange v (row_ror:8 within each row of 16 lanes)
+__device__ __forceinline__ double swap_lanes8(double v) { return dpp_f64<0x128>(v); }
+__device__ __forceinline__ float swap_lanes8(float v) { return dpp_f32<0x128>(v); }
 template <int G>
 __device__ __forceinline__ float group_sum(float v) {
   if constexpr (G >= 2) v += dpp_f32<0xB1>(v);
@@ -949,6 +952,8 @@ __device__ __forceinline__ int jacobi_core(AnaSmem<M>& sm, int m, R* B, R* nrm, 
   const R trig2 = trig * trig;
   const R tol4 = (R)4 * tol2, trig4 = (R)4 * trig2;
   constexpr bool PREFETCH = C::RPT <= 16;
+  // partners exchanged between slots q and q ^ 1 by a lane swap within 16-lane rows
+  constexpr bool SWAP = PREFETCH && TPP == 8;
   // the step's column and norm accesses through LDS-typed pointers, so that
   // their addresses are 32-bit offsets (a generic pointer makes every partner
   // address a 64-bit multiply-add)
@@ -1006,12 +1011,17 @@ __device__ __forceinline__ int jacobi_core(AnaSmem<M>& sm, int m, R* B, R* nrm, 
       R xi[C::RPT];
       R al = 0;
       // One step k: pair (i, i ^ k) with the partner column in xc (norm bc).
-      // With PREFETCH the next step's partner is loaded into xn (norm bn)
-      // before this step rotates the lower column (registers only), so that
-      // its LDS latency overlaps that arithmetic instead of stalling the next
-      // dot product; two register sets alternate between consecutive steps.
+      // With PREFETCH the next step's partner arrives in xn (norm bn) before
+      // this step rotates the lower column (registers only), so that its
+      // latency overlaps that arithmetic instead of stalling the next dot
+      // product; two register sets alternate between consecutive steps.
       // (M = 128 holds 32 rows per lane: a second set would spill, so there
       // each step loads its own partner.)
+      // Between an even step k and k + 1 the slots exchange partners in pairs
+      // (slot q takes the column slot q ^ 1 just rotated), so with SWAP the
+      // rotated partner goes to its next slot by a lane swap and not through
+      // LDS; the odd step after it writes that column back, rotated or not,
+      // since its LDS copy is then out of date.
       auto step = [&](const int k, R (&xc)[C::RPT], R& bc, R (&xn)[C::RPT], R& bn) {
         // the lower column index as a value the compiler may not carry across
         // steps: unrolled, it would otherwise keep every step's partner
@@ -1020,6 +1030,8 @@ __device__ __forceinline__ int jacobi_core(AnaSmem<M>& sm, int m, R* B, R* nrm, 
         __asm__ volatile("" : "+v"(iv));
         iv &= M - 1;  // a known range: 24-bit multiply-adds for the addresses
         const int jj = iv ^ k;
+        const bool swp = SWAP && (k & 1) == 0 && k + 1 < kend;
+        const bool stale = SWAP && (k & 1) == 1 && k > (1 << h);
         R c = 1, sn = 0;
         bool rot = false;
         if (!PREFETCH && active) {
@@ -1055,14 +1067,31 @@ __device__ __forceinline__ int jacobi_core(AnaSmem<M>& sm, int m, R* B, R* nrm, 
             const R t = copysign((R)1, dd) * g2 * approx_rcp(den);
             c = rsqrt_acc(fma(t, t, (R)1));
             sn = c * t;
-            // the partner first: the slot that pairs it next reads it from LDS
+            if (swp) {
+              // both columns in registers; the partner leaves by the swap below
+#pragma unroll
+              for (int u = 0; u < C::RPT; ++u) {
+                const R a = xi[u], b = xc[u];
+                xi[u] = c * a - sn * b;
+                xc[u] = sn * a + c * b;
+              }
+            } else {
+              // the partner first: the slot that pairs it next reads it from LDS
+              LR* bj = LB + jj * LD;
+#pragma unroll
+              for (int u = 0; u < C::RPT; ++u) bj[sub + u * TPP] = sn * xi[u] + c * xc[u];
+            }
+            al -= t * gsum;
+            bc += t * gsum;
+            // every lane of the slot stores the same norm (and flag)
+            if (!swp) LN[jj] = bc;
+            sm.s_rot = 1;
+          }
+          if (stale && !rot) {
             LR* bj = LB + jj * LD;
 #pragma unroll
-            for (int u = 0; u < C::RPT; ++u) bj[sub + u * TPP] = sn * xi[u] + c * xc[u];
-            al -= t * gsum;
-            // every lane of the slot stores the same norm (and flag)
-            LN[jj] = bc + t * gsum;
-            sm.s_rot = 1;
+            for (int u = 0; u < C::RPT; ++u) bj[sub + u * TPP] = xc[u];
+            LN[jj] = bc;
           }
         }
         // Step k + 1 reads a partner column (and its norm) that step k wrote:
@@ -1075,12 +1104,18 @@ __device__ __forceinline__ int jacobi_core(AnaSmem<M>& sm, int m, R* B, R* nrm, 
         if ((k + 1) % PSW == 0 && k + 1 < kend) __syncthreads();
         else __asm__ volatile("" ::: "memory");
         if (PREFETCH && active && k + 1 < kend) {
-          const LR* bk = LB + (iv ^ (k + 1)) * LD;
+          if (swp) {
 #pragma unroll
-          for (int t = 0; t < C::RPT; ++t) xn[t] = bk[sub + t * TPP];
-          bn = LN[iv ^ (k + 1)];
+            for (int t = 0; t < C::RPT; ++t) xn[t] = swap_lanes8(xc[t]);
+            bn = swap_lanes8(bc);
+          } else {
+            const LR* bk = LB + (iv ^ (k + 1)) * LD;
+#pragma unroll
+            for (int t = 0; t < C::RPT; ++t) xn[t] = bk[sub + t * TPP];
+            bn = LN[iv ^ (k + 1)];
+          }
         }
-        if (rot) {
+        if (rot && !swp) {
 #pragma unroll
           for (int u = 0; u < C::RPT; ++u) xi[u] = c * xi[u] - sn * xc[u];
         }
