@@ -1760,9 +1760,9 @@ __global__ __launch_bounds__(256) void k_analysis(const InstDesc* __restrict__ t
 // 256 x 256 matrices (512 KB each) do not fit in LDS, so its analysis is a
 // sequence of launches over scratch in the instance workspace (A, B and a few
 // vectors per domain, which stay in L2 between launches):
-//   k_big_rhs     b = Y'^T diag(r) d; clears the domain's Jacobi flags
-//   k_big_gram    A = (m-1)/rho I + Y'^T diag(r) Y', by 64 x 64 tiles
-//   k_big_chol    A = L L^T, right-looking, one workgroup per domain
+//   k_big_gram    A = (m-1)/rho I + Y'^T diag(r) Y' by 64 x 64 tiles on FP64
+//                 MFMA, b = Y'^T diag(r) d; clears the domain's Jacobi flags
+//   k_big_chol    A = L L^T, right-looking by panels, one workgroup per domain
 //   k_big_round   one round of the blocked one-sided Jacobi (below)
 //   k_big_sweep   end of a sweep: a domain is done when no round rotated
 //   k_big_eig     lambda, U, wbar (one refinement step through the exact A)
@@ -1813,140 +1813,215 @@ __device__ __forceinline__ double* big_dbg(const BigDom& D) {
 }
 
 // 1024 threads: member j = t % 256 of observation quarter t / 256, summed in LDS.
-__global__ __launch_bounds__(1024) void k_big_rhs(const InstDesc* __restrict__ tab, const BatchHdr* __restrict__ hdr,
-                                                  int cls) {
-  __shared__ double part_sum[4][kBigM];
-  const ClassBatch& cb = hdr->cls[cls];
-  if ((int)blockIdx.x >= cb.dom_off[cb.n]) return;
-  const BigDom D = big_dom(tab, cb, blockIdx.x);
-  const InstDesc& I = *D.I;
-  const int m = I.m, j = threadIdx.x % kBigM, part = threadIdx.x / kBigM, nobs = 2 * D.s;
-  const double* Yp = (const double*)I.Yp;
-  if (threadIdx.x == 0) {
-    D.f[0] = 0;
-    D.f[1] = 0;
-    D.f[2] = 0;
-  }
-  double acc[2] = {0.0, 0.0};
-  if (j < m) {
-    int q = part;
-    for (; q + 4 < nobs; q += 8)
-#pragma unroll
-      for (int u = 0; u < 2; ++u) {
-        const int o = 2 * D.obs_off + q + 4 * u, row = I.obs_row[o];
-        acc[u] = fma(I.obs_r[o] * I.d[row], Yp[(size_t)row * m + j], acc[u]);
-      }
-    for (; q < nobs; q += 4) {
-      const int o = 2 * D.obs_off + q, row = I.obs_row[o];
-      acc[0] = fma(I.obs_r[o] * I.d[row], Yp[(size_t)row * m + j], acc[0]);
-    }
-  }
-  part_sum[part][j] = acc[0] + acc[1];
-  __syncthreads();
-  if (part == 0)
-    D.v[j] = j < m ? (part_sum[0][j] + part_sum[1][j]) + (part_sum[2][j] + part_sum[3][j]) : 0.0;
-}
-
 // grid (10, items): the upper tiles (ti <= tj) of the 4 x 4 grid of 64 x 64
-// tiles; each thread owns 4 x 4 entries, observations staged 32 at a time.
+// tiles of C = Y'^T diag(r) Y', on FP64 MFMA: wavefront w owns the 32 x 32
+// quadrant (w / 2, w % 2) of the tile, 2 x 2 MFMA tiles of 16 x 16, over
+// chunks of 32 observations staged in LDS (Ya: Y' rows of the tile's rows,
+// Yb: r Y' of its columns).  The diagonal tiles also form their 64 entries of
+// b = Y'^T diag(r) d, and tile 0 clears the domain's Jacobi flags.
 __global__ __launch_bounds__(256) void k_big_gram(const InstDesc* __restrict__ tab, const BatchHdr* __restrict__ hdr,
                                                   int cls) {
-  __shared__ double Ya[32][64], Yb[32][64];
+  __shared__ double Ya[32][64], Yb[32][64], rd[32], bred[4][64];
   const ClassBatch& cb = hdr->cls[cls];
   if ((int)blockIdx.y >= cb.dom_off[cb.n]) return;
   int t = blockIdx.x, ti = 0;
   while (t >= 4 - ti) { t -= 4 - ti; ++ti; }
   const int tj = ti + t, i0 = 64 * ti, j0 = 64 * tj;
+  const bool diag = ti == tj;
   const BigDom D = big_dom(tab, cb, blockIdx.y);
   const InstDesc& I = *D.I;
-  const int m = I.m, tid = threadIdx.x, tx = tid % 16, ty = tid / 16, nobs = 2 * D.s;
+  const int m = I.m, tid = threadIdx.x, w = tid / 64, lane = tid % 64, nobs = 2 * D.s;
+  if (blockIdx.x == 0 && tid == 0) {
+    D.f[0] = 0;
+    D.f[1] = 0;
+    D.f[2] = 0;
+  }
   const double* Yp = (const double*)I.Yp;
-  double acc[4][4];
+  const int qr = 32 * (w / 2), qc = 32 * (w % 2);  // the wavefront's quadrant
+  f64x4 acc[2][2];
 #pragma unroll
-  for (int x = 0; x < 4; ++x)
+  for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int y = 0; y < 4; ++y) acc[x][y] = 0.0;
-  for (int q0 = 0; q0 < nobs; q0 += 32) {
-    for (int idx = tid; idx < 32 * 64; idx += 256) {
-      const int qq = idx / 64, c = idx % 64, q = q0 + qq;
-      double a = 0.0, b = 0.0;
+    for (int b = 0; b < 2; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
+  double bpart = 0.0;  // diagonal tiles: b for row i0 + lane, observations w, w + 4, ...
+  // Thread tid stages observations tid / 64 + 4 e (e < 8) of every chunk, row
+  // entry c = tid % 64.  The next chunk's values are loaded into registers
+  // before this chunk's products, and their row indices one chunk earlier
+  // still, so the loads' latency overlaps the MFMAs instead of preceding them.
+  const int c = tid % 64;
+  int prow[8];
+  double pr[8], pa[8], pb[8], pd[8];
+  auto fetch_idx = [&](int q0n) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int q = q0n + tid / 64 + 4 * e;
+      prow[e] = -1;
+      pr[e] = 0.0;
       if (q < nobs) {
         const int o = 2 * D.obs_off + q;
-        const size_t row = (size_t)I.obs_row[o] * m;
-        if (i0 + c < m) a = Yp[row + i0 + c];
-        if (j0 + c < m) b = I.obs_r[o] * Yp[row + j0 + c];
+        prow[e] = I.obs_row[o];
+        pr[e] = I.obs_r[o];
       }
-      Ya[qq][c] = a;
-      Yb[qq][c] = b;
+    }
+  };
+  auto fetch_val = [&]() {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      pa[e] = pb[e] = pd[e] = 0.0;
+      if (prow[e] >= 0) {
+        const size_t row = (size_t)prow[e] * m;
+        if (i0 + c < m) pa[e] = Yp[row + i0 + c];
+        if (j0 + c < m) pb[e] = pr[e] * Yp[row + j0 + c];
+        if (diag && c == 0) pd[e] = pr[e] * I.d[prow[e]];
+      }
+    }
+  };
+  fetch_idx(0);
+  fetch_val();
+  fetch_idx(32);
+  for (int q0 = 0; q0 < nobs; q0 += 32) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      Ya[tid / 64 + 4 * e][c] = pa[e];
+      Yb[tid / 64 + 4 * e][c] = pb[e];
+      if (c == 0) rd[tid / 64 + 4 * e] = pd[e];
     }
     __syncthreads();
-#pragma unroll 4
-    for (int qq = 0; qq < 32; ++qq) {
-      double a[4], b[4];
-#pragma unroll
-      for (int x = 0; x < 4; ++x) a[x] = Ya[qq][ty + 16 * x];
-#pragma unroll
-      for (int y = 0; y < 4; ++y) b[y] = Yb[qq][tx + 16 * y];
-#pragma unroll
-      for (int x = 0; x < 4; ++x)
-#pragma unroll
-        for (int y = 0; y < 4; ++y) acc[x][y] = fma(a[x], b[y], acc[x][y]);
+    if (q0 + 32 < nobs) {
+      fetch_val();
+      fetch_idx(q0 + 64);
     }
+#pragma unroll
+    for (int ks = 0; ks < 8; ++ks) {
+      const int k = 4 * ks + lane / 16;
+      double av[2], bv[2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        av[a] = Ya[k][qr + 16 * a + lane % 16];
+        bv[a] = Yb[k][qc + 16 * a + lane % 16];
+      }
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+    }
+    if (diag)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) bpart = fma(Ya[w + 4 * e][lane], rd[w + 4 * e], bpart);
     __syncthreads();
+  }
+  if (diag) {
+    bred[w][lane] = bpart;
+    __syncthreads();
+    if (tid < 64) {
+      const int i = i0 + tid;
+      D.v[i] = i < m ? (bred[0][tid] + bred[1][tid]) + (bred[2][tid] + bred[3][tid]) : 0.0;
+    }
   }
   double* dbg = big_dbg(D);
 #pragma unroll
-  for (int x = 0; x < 4; ++x)
+  for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int y = 0; y < 4; ++y) {
-      const int i = i0 + ty + 16 * x, j = j0 + tx + 16 * y;
-      if (i > j) continue;  // one writer per symmetric pair (deterministic)
-      double v;
-      if (i < m && j < m) {
-        v = acc[x][y] + (i == j ? I.a_diag : 0.0);
-        if (dbg) {
-          dbg[(size_t)i * m + j] = acc[x][y];
-          dbg[(size_t)j * m + i] = acc[x][y];
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = i0 + qr + 16 * a + lane / 16 + 4 * v, j = j0 + qc + 16 * b + lane % 16;
+        if (i > j) continue;  // one writer per symmetric pair (deterministic)
+        const double c = acc[a][b][v];
+        double x;
+        if (i < m && j < m) {
+          x = c + (i == j ? I.a_diag : 0.0);
+          if (dbg) {
+            dbg[(size_t)i * m + j] = c;
+            dbg[(size_t)j * m + i] = c;
+          }
+        } else {
+          x = i == j ? 1.0 : 0.0;  // padded members: identity
         }
-      } else {
-        v = i == j ? 1.0 : 0.0;  // padded members: identity
+        D.A[(size_t)i * kBigM + j] = x;
+        D.A[(size_t)j * kBigM + i] = x;
       }
-      D.A[(size_t)i * kBigM + j] = v;
-      D.A[(size_t)j * kBigM + i] = v;
-    }
 }
 
-// 1024 threads: thread t owns row r = t % 256 of L (column-major B) and every
-// fourth trailing column from t / 256 on: per column k it reads the pivot
-// column from LDS, writes its entry of column k and updates its entries of
-// the trailing columns (coalesced across threads for each column).
-__global__ __launch_bounds__(1024) void k_big_chol(const InstDesc* __restrict__ tab, const BatchHdr* __restrict__ hdr,
-                                                   int cls) {
-  __shared__ double pc[kBigM];
+// A = L L^T into B (column-major, leading dimension kBigM; the upper triangle
+// zero, padded members the identity), right-looking by panels of 16 columns
+// as the m <= 128 kernel: wavefront 0 factors the panel in registers (rows
+// c0 + lane + 64 s), which also stages it in LDS, and all eight wavefronts
+// subtract its rank-16 product from the trailing lower triangle in 16 x 16
+// tiles on FP64 MFMA (the tiles in B, whose loads are the latency that more
+// wavefronts hide; the panel's columns from LDS).
+constexpr int kBigCholWaves = 8;
+__global__ __launch_bounds__(64 * kBigCholWaves) void k_big_chol(const InstDesc* __restrict__ tab,
+                                                                 const BatchHdr* __restrict__ hdr, int cls) {
+  __shared__ double pnl[16][kBigM];
   const ClassBatch& cb = hdr->cls[cls];
   if ((int)blockIdx.x >= cb.dom_off[cb.n]) return;
   const BigDom D = big_dom(tab, cb, blockIdx.x);
-  const int m = D.I->m, r = threadIdx.x % kBigM, part = threadIdx.x / kBigM;
-  for (int c = part; c < kBigM; c += 4) {
+  const int m = D.I->m, mp = (m + 15) & ~15, tid = threadIdx.x, w = tid / 64, lane = tid % 64;
+  for (int idx = tid; idx < kBigM * kBigM; idx += 64 * kBigCholWaves) {
+    const int c = idx / kBigM, r = idx % kBigM;
     double v;
     if (c < m) v = (r >= c && r < m) ? D.A[(size_t)c * kBigM + r] : 0.0;  // A symmetric
     else v = r == c ? 1.0 : 0.0;
-    D.B[(size_t)c * kBigM + r] = v;
+    D.B[idx] = v;
   }
   __syncthreads();
-  for (int k = 0; k < m; ++k) {
-    if (part == 0 && r >= k && r < m) pc[r] = D.B[(size_t)k * kBigM + r];
-    __syncthreads();
-    const double sk = sqrt(pc[k]);
-    const double inv = 1.0 / sk;
-    if (r >= k && r < m) {
-      const double lr = r == k ? sk : pc[r] * inv;
-      if (part == 0) D.B[(size_t)k * kBigM + r] = lr;
-      if (r > k) {
-#pragma unroll 4
-        for (int c = k + 1 + part; c <= r; c += 4) D.B[(size_t)c * kBigM + r] -= lr * (pc[c] * inv);
+  for (int c0 = 0; c0 < mp; c0 += 16) {
+    if (w == 0) {
+      double a[4][16];
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int r = c0 + lane + 64 * s;
+        const bool on = r < mp;
+#pragma unroll
+        for (int jj = 0; jj < 16; ++jj) a[s][jj] = on ? D.B[(size_t)(c0 + jj) * kBigM + r] : 0.0;
+      }
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const double d = readlane_f64(a[0][j], j);  // a_jj after the earlier columns
+        const double rs = rsqrt(d);
+        double lj[4];
+        lj[0] = lane > j ? a[0][j] * rs : (lane == j ? d * rs : 0.0);
+#pragma unroll
+        for (int s = 1; s < 4; ++s) lj[s] = a[s][j] * rs;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) a[s][j] = lj[s];
+#pragma unroll
+        for (int jj = j + 1; jj < 16; ++jj) {
+          const double l = readlane_f64(lj[0], jj);
+#pragma unroll
+          for (int s = 0; s < 4; ++s) a[s][jj] = fma(-lj[s], l, a[s][jj]);
+        }
+      }
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int r = c0 + lane + 64 * s;
+        if (r < mp)
+#pragma unroll
+          for (int jj = 0; jj < 16; ++jj) {
+            D.B[(size_t)(c0 + jj) * kBigM + r] = a[s][jj];
+            pnl[jj][r] = a[s][jj];
+          }
       }
     }
+    __syncthreads();
+    const int nt = (mp - c0) / 16 - 1;
+    int t = 0;
+    for (int R = 0; R < nt; ++R)
+      for (int Cc = 0; Cc <= R; ++Cc, ++t) {
+        if (t % kBigCholWaves != w) continue;
+        const int rb = c0 + 16 * (R + 1), cb = c0 + 16 * (Cc + 1);
+        f64x4 acc;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[v] = D.B[(size_t)(cb + lane % 16) * kBigM + rb + lane / 16 + 4 * v];
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+          const int k = 4 * ks + lane / 16;
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(pnl[k][rb + lane % 16], -pnl[k][cb + lane % 16], acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) D.B[(size_t)(cb + lane % 16) * kBigM + rb + lane / 16 + 4 * v] = acc[v];
+      }
     __syncthreads();
   }
 }
@@ -2437,9 +2512,8 @@ void launch_rows(int cls, int mode, int rows, const InstDesc* tab, BatchHdr* hdr
 void launch_big_analysis(int items, int rows_max, int m_max, const InstDesc* tab, BatchHdr* hdr, hipStream_t s) {
   if (items <= 0) return;
   const int cls = kBigClass, nb = 2 * ((m_max + 31) / 32);
-  hipLaunchKernelGGL(k_big_rhs, dim3(items), dim3(1024), 0, s, tab, hdr, cls);
   hipLaunchKernelGGL(k_big_gram, dim3(10, items), dim3(256), 0, s, tab, hdr, cls);
-  hipLaunchKernelGGL(k_big_chol, dim3(items), dim3(1024), 0, s, tab, hdr, cls);
+  hipLaunchKernelGGL(k_big_chol, dim3(items), dim3(64 * kBigCholWaves), 0, s, tab, hdr, cls);
   for (int sw = 0; sw < kBigMaxSweeps; ++sw) {
     for (int r = 0; r < nb - 1; ++r)
       hipLaunchKernelGGL(k_big_round, dim3(nb / 2, items), dim3(256), 0, s, tab, hdr, cls, nb, r);
