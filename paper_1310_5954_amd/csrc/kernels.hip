@@ -1050,7 +1050,42 @@ __device__ __forceinline__ int jacobi_core(AnaSmem<M>& sm, int m, R* B, R* nrm, 
           const R gsum = group_sum<TPP>(g0 + g1);
           // (2 gsum)^2 serves both the test, against 4 tol^2 al bc, and the angle
           const R ab = al * bc, g2 = gsum + gsum, g4 = g2 * g2;
-          if (g4 > tol4 * ab) {
+          if (swp) {
+            // A step whose partner leaves by the lane exchange: when any pair of
+            // the wavefront rotates, every lane takes the step, a lane whose pair
+            // does not with t = 0, c = 1, sn = 0 (an exact identity).  The branch
+            // is wavefront-uniform, so the rotated columns need no merge with
+            // the unrotated ones of masked lanes (that merge cost a register move
+            // per value).
+            rot = g4 > tol4 * ab;
+            if (__builtin_amdgcn_ballot_w64(rot) != 0) {
+              big = max(big, sign_word(fma(-trig4, ab, g4)));  // negative where no rotation
+              const R dd = bc - al;
+              const R q2 = fma(dd, dd, g4);
+              const R den = fma(q2, approx_rsq(q2), fabs(dd));
+              const R t = rot ? copysign((R)1, dd) * g2 * approx_rcp(den) : (R)0;
+              c = rot ? rsqrt_acc(fma(t, t, (R)1)) : (R)1;
+              sn = c * t;
+#pragma unroll
+              for (int u = 0; u < C::RPT; ++u) {
+                const R a = xi[u], b = xc[u];
+                xi[u] = c * a - sn * b;
+                xc[u] = sn * a + c * b;
+              }
+              al -= t * gsum;
+              bc += t * gsum;
+              sm.s_rot = 1;
+              // the exchange on both sides of the branch, so that the rotated
+              // partner goes from the registers it was computed in
+#pragma unroll
+              for (int u = 0; u < C::RPT; ++u) xn[u] = swap_lanes8(xc[u]);
+              bn = swap_lanes8(bc);
+            } else {
+#pragma unroll
+              for (int u = 0; u < C::RPT; ++u) xn[u] = swap_lanes8(xc[u]);
+              bn = swap_lanes8(bc);
+            }
+          } else if (g4 > tol4 * ab) {
             rot = true;
             // the largest sign word of g4 - 4 trig^2 al bc: non-negative once a
             // rotation of this sweep had a cosine above trig (an integer
@@ -1068,24 +1103,14 @@ __device__ __forceinline__ int jacobi_core(AnaSmem<M>& sm, int m, R* B, R* nrm, 
             const R t = copysign((R)1, dd) * g2 * approx_rcp(den);
             c = rsqrt_acc(fma(t, t, (R)1));
             sn = c * t;
-            if (swp) {
-              // both columns in registers; the partner leaves by the swap below
+            // the partner first: the slot that pairs it next reads it from LDS
+            LR* bj = LB + jj * LD;
 #pragma unroll
-              for (int u = 0; u < C::RPT; ++u) {
-                const R a = xi[u], b = xc[u];
-                xi[u] = c * a - sn * b;
-                xc[u] = sn * a + c * b;
-              }
-            } else {
-              // the partner first: the slot that pairs it next reads it from LDS
-              LR* bj = LB + jj * LD;
-#pragma unroll
-              for (int u = 0; u < C::RPT; ++u) bj[sub + u * TPP] = sn * xi[u] + c * xc[u];
-            }
+            for (int u = 0; u < C::RPT; ++u) bj[sub + u * TPP] = sn * xi[u] + c * xc[u];
             al -= t * gsum;
             bc += t * gsum;
             // every lane of the slot stores the same norm (and flag)
-            if (!swp) LN[jj] = bc;
+            LN[jj] = bc;
             sm.s_rot = 1;
           }
           if (stale && !rot) {
@@ -1104,17 +1129,11 @@ __device__ __forceinline__ int jacobi_core(AnaSmem<M>& sm, int m, R* B, R* nrm, 
         // the others only keep the compiler from moving LDS accesses across.
         if ((k + 1) % PSW == 0 && k + 1 < kend) __syncthreads();
         else __asm__ volatile("" ::: "memory");
-        if (PREFETCH && active && k + 1 < kend) {
-          if (swp) {
+        if (PREFETCH && active && !swp && k + 1 < kend) {
+          const LR* bk = LB + (iv ^ (k + 1)) * LD;
 #pragma unroll
-            for (int t = 0; t < C::RPT; ++t) xn[t] = swap_lanes8(xc[t]);
-            bn = swap_lanes8(bc);
-          } else {
-            const LR* bk = LB + (iv ^ (k + 1)) * LD;
-#pragma unroll
-            for (int t = 0; t < C::RPT; ++t) xn[t] = bk[sub + t * TPP];
-            bn = LN[iv ^ (k + 1)];
-          }
+          for (int t = 0; t < C::RPT; ++t) xn[t] = bk[sub + t * TPP];
+          bn = LN[iv ^ (k + 1)];
         }
         if (rot && !swp) {
 #pragma unroll
