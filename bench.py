@@ -27,7 +27,7 @@ domains) and on one core.
 
     python bench.py [--steps K] [--warmup W] [--instances B] [--precision fp64|fp32|bf16]
 
-Prints one JSON line.  --gpus N > 1 is refused: this build runs on one GPU.
+Prints one JSON line.  --gpus N > 1 is refused: the library runs on one GPU.
 """
 from __future__ import annotations
 
@@ -755,7 +755,7 @@ def main() -> int:
                     help="only run a plain 512 MiB device-to-device copy (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps(dict(error="this build runs on one GPU only; --gpus must be 1")))
+        print(json.dumps(dict(error="the library runs on one GPU only; --gpus must be 1")))
         return 2
 
     import torch
