@@ -357,7 +357,9 @@ template <int M> struct AnaCfg {
   static constexpr int MAX_SWEEPS = 40;
   // MFMA paths
   static constexpr int KCF = M <= 64 ? 32 : 16;    // FP32: observations per staged chunk
-  static constexpr int LDKF = KCF + 4;             // row stride (floats) of the transposed chunk
+  // row stride (floats) of the transposed chunk: 2 mod 32, so that the 16 rows
+  // and 2 k-offsets of a 32-lane operand load fall in 32 different banks
+  static constexpr int LDKF = KCF + 2;
   static constexpr int KCB = 32;                   // BF16: observations per chunk (one k-step)
   static constexpr int LDKB = KCB + 8;             // row stride (bf16) of the transposed chunk
   static constexpr int KR = M <= 64 ? 32 : 16;     // update: state rows per chunk (16-row tiles)
@@ -469,7 +471,7 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 template <int M>
 __device__ void gather_C_fp64_mfma(AnaSmem<M>& sm, const InstDesc& I, int obs_off, int s, double* dbg) {
   using C = AnaCfg<M>;
-  constexpr int NT = C::NT, KCH = 16, LDK = KCH + 2;
+  constexpr int NT = C::NT, KCH = 16, LDK = KCH + 1;  // LDK odd: the 16 rows of an operand load in 16 bank pairs
   constexpr int TILES = M / 16;
   constexpr int WT = TILES >= 2 ? TILES / 2 : 1;
   static_assert(M <= 64 && (size_t)M * LDK * 8 <= C::STAGE_BYTES, "staging");
@@ -1513,6 +1515,10 @@ __device__ void transform(AnaSmem<M>& sm, const InstDesc& I, int l, double* dbg)
 template <int M, int KCH, typename T>
 struct RowChunk {
   static constexpr int NT = AnaCfg<M>::NT, EPT = KCH * M / NT;
+  // row stride of the staged chunk: M + 1, so that the 16 rows an MFMA operand
+  // load reads for one member (one row per lane) fall in 16 different banks
+  // (a stride of M put them all in one: a 16-way conflict on every load)
+  static constexpr int LDX = M + 1;
   static_assert(KCH * M % NT == 0, "whole chunks per thread");
   T v[EPT];
   int act[EPT];  // M <= 64: actuator indices of the chunk fetched next (see fetch)
@@ -1569,12 +1575,12 @@ struct RowChunk {
   template <typename S>
   __device__ void store(AnaSmem<M>& sm, S* X, int m) {
 #pragma unroll
-    for (int u = 0; u < EPT; ++u) X[(qq0 + u * (NT / M)) * M + jj] = (S)v[u];
+    for (int u = 0; u < EPT; ++u) X[(qq0 + u * (NT / M)) * LDX + jj] = (S)v[u];
     __syncthreads();
     constexpr int TPR = NT / KCH;  // threads per row for the means (8 or 16)
     const int tid = phase_tid(), row = tid / TPR, part = tid % TPR;
     double sum = 0.0;
-    for (int j = part; j < m; j += TPR) sum += (double)X[row * M + j];
+    for (int j = part; j < m; j += TPR) sum += (double)X[row * LDX + j];
     sum = group_sum<TPR>(sum);
     if (part == 0) sm.rc[row] = sum / (double)m;
     __syncthreads();
@@ -1589,7 +1595,8 @@ template <int M>
 __device__ void update_fp64(AnaSmem<M>& sm, const InstDesc& I, int est_off, int e, int cur) {
   using C = AnaCfg<M>;
   constexpr int LDB = C::LDB, KR = 16, CB = M / 16;
-  static_assert((size_t)KR * M * 8 <= C::STAGE_BYTES, "staging");
+  static_assert((size_t)KR * (M + 1) * 8 <= C::STAGE_BYTES, "staging");
+  constexpr int LDX = RowChunk<M, KR, double>::LDX;
   const int m = I.m, tid = phase_tid(), w = tid / 64, lane = tid % 64;
   double* Xd = (double*)sm.stage;
   double* Z = (double*)I.Z + (size_t)2 * est_off * m;
@@ -1611,7 +1618,7 @@ __device__ void update_fp64(AnaSmem<M>& sm, const InstDesc& I, int est_off, int 
         // loaded unconditionally, masked by arithmetic (the staged rows are
         // zero past m, so the product is finite): a load under the mask is a
         // branch and a wait of its own before every MFMA
-        const double a = (k < m ? 1.0 : 0.0) * (Xd[arow * M + k] - xb);
+        const double a = (k < m ? 1.0 : 0.0) * (Xd[arow * LDX + k] - xb);
         const double b = sm.Bm[k * LDB + col];
         acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
       }
@@ -1640,6 +1647,8 @@ __device__ void update_mfma(AnaSmem<M>& sm, const InstDesc& I, int est_off, int 
   float* Xf = (float*)sm.stage;
   float* Z = (float*)I.Z + (size_t)2 * est_off * m;
   RowChunk<M, KR, float> rows;
+  constexpr int LDX = RowChunk<M, KR, float>::LDX;
+  static_assert((size_t)KR * LDX * 4 <= C::STAGE_BYTES, "staging");
   rows.fetch_act(I, est_off, e, 0);
   rows.fetch(I, est_off, e, cur, 0);
   for (int q0 = 0; q0 < 2 * e; q0 += KR) {
@@ -1656,7 +1665,7 @@ __device__ void update_mfma(AnaSmem<M>& sm, const InstDesc& I, int est_off, int 
 #pragma unroll 4
         for (int ks = 0; ks < M / 4; ++ks) {
           const int k = ks * 4 + lane / 16;
-          const float a = (k < m ? 1.f : 0.f) * (Xf[arow * M + k] - xb);  // masked by arithmetic, as above
+          const float a = (k < m ? 1.f : 0.f) * (Xf[arow * LDX + k] - xb);  // masked by arithmetic, as above
           const float b = (float)sm.Bm[k * LDB + col];
           acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
         }
@@ -1671,10 +1680,10 @@ __device__ void update_mfma(AnaSmem<M>& sm, const InstDesc& I, int est_off, int 
             if constexpr (M <= 64) {
               // masked by arithmetic, as above; k runs past M only at M = 16 (the index is clamped)
               const int kc_ = (M % 32 == 0 || k < M) ? k : M - 1;
-              xa = (k < m ? 1.f : 0.f) * (Xf[arow * M + kc_] - xb);
+              xa = (k < m ? 1.f : 0.f) * (Xf[arow * LDX + kc_] - xb);
               tv = (M % 32 == 0 || k < M ? 1.0 : 0.0) * sm.Bm[kc_ * LDB + col];
             } else {  // M = 128: the loads in flight at once would not fit in the registers
-              xa = (k < m) ? Xf[arow * M + k] - xb : 0.f;
+              xa = (k < m) ? Xf[arow * LDX + k] - xb : 0.f;
               tv = sm.Bm[k * LDB + col];
             }
             const __bf16 hi = (__bf16)(float)tv;
