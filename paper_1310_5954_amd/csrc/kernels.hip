@@ -823,18 +823,22 @@ __device__ __forceinline__ void cholesky(AnaSmem<M>& sm) {
       for (int Cc = 0; Cc <= R; ++Cc, ++t) {
         if (t % 4 != w) continue;
         const int rb = c0 + 16 * (R + 1), cb = c0 + 16 * (Cc + 1);
+        // the tile transposed, D[i][j] = B(rb + j, cb + i): a lane's accumulators
+        // then lie along one column of the column-major B, consecutive across
+        // the 16 lanes (along a row they would be LDB apart, an 8-way bank
+        // conflict on every load and store)
         f64x4 acc;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) acc[v] = sm.Bm[(cb + lane % 16) * LDB + rb + lane / 16 + 4 * v];
+        for (int v = 0; v < 4; ++v) acc[v] = sm.Bm[(cb + lane / 16 + 4 * v) * LDB + rb + lane % 16];
 #pragma unroll
         for (int ks = 0; ks < 4; ++ks) {
           const int k = c0 + 4 * ks + lane / 16;
-          const double av = sm.Bm[k * LDB + rb + lane % 16];
-          const double bv = -sm.Bm[k * LDB + cb + lane % 16];
+          const double av = -sm.Bm[k * LDB + cb + lane % 16];
+          const double bv = sm.Bm[k * LDB + rb + lane % 16];
           acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
         }
 #pragma unroll
-        for (int v = 0; v < 4; ++v) sm.Bm[(cb + lane % 16) * LDB + rb + lane / 16 + 4 * v] = acc[v];
+        for (int v = 0; v < 4; ++v) sm.Bm[(cb + lane / 16 + 4 * v) * LDB + rb + lane % 16] = acc[v];
       }
     __syncthreads();
   }
