@@ -1653,11 +1653,57 @@ __device__ void update_mfma(AnaSmem<M>& sm, const InstDesc& I, int est_off, int 
   RowChunk<M, KR, float> rows;
   constexpr int LDX = RowChunk<M, KR, float>::LDX;
   static_assert((size_t)KR * LDX * 4 <= C::STAGE_BYTES, "staging");
+  // BF16, M a multiple of 32: T converted once to its hi and lo BF16 parts,
+  // transposed (Th[j][k], k contiguous, so that a lane's 8 consecutive k of the
+  // B operand are one 16-byte load), in Bm's storage; the staged rows likewise
+  // once per chunk to BF16 X' - xbar (zero past m).  Converting inside the
+  // products repeated the work for every tile and chunk.
+  constexpr bool PRE = P == 2 && M % 32 == 0 && M <= 64;
+  constexpr int LDT = M + 8;  // bf16 row stride: 16-byte rows, banks spread over a pass
+  __bf16* Th = (__bf16*)sm.Bm;
+  __bf16* Tl = Th + M * LDT;
+  __bf16* Xb = (__bf16*)sm.stage;
+  static_assert(!PRE || ((size_t)2 * M * LDT * 2 <= sizeof(sm.Bm) && (size_t)KR * LDT * 2 <= C::STAGE_BYTES),
+                "BF16 copies");
+  if constexpr (PRE) {
+    constexpr int PER = M * M / C::NT;
+    double tv[PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int idx = tid + u * C::NT;
+      tv[u] = sm.Bm[(idx / M) * LDB + idx % M];  // T[k][j], k = idx / M, j = idx % M
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int idx = tid + u * C::NT, k = idx / M, j = idx % M;
+      const __bf16 hi = (__bf16)(float)tv[u];
+      Th[j * LDT + k] = hi;
+      Tl[j * LDT + k] = (__bf16)(float)(tv[u] - (double)(float)hi);
+    }
+    __syncthreads();
+  }
   rows.fetch_act(I, est_off, e, 0);
   rows.fetch(I, est_off, e, cur, 0);
   for (int q0 = 0; q0 < 2 * e; q0 += KR) {
     const int kc = min(KR, 2 * e - q0);
     rows.store(sm, Xf, m);
+    if constexpr (PRE) {
+      constexpr int PER = KR * M / C::NT;
+      float xv[PER];
+#pragma unroll
+      for (int u = 0; u < PER; ++u) {
+        const int idx = tid + u * C::NT, r = idx / M, k = idx % M;
+        xv[u] = (k < m ? 1.f : 0.f) * (Xf[r * LDX + k] - (float)sm.rc[r]);
+      }
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < PER; ++u) {
+        const int idx = tid + u * C::NT;
+        Xb[(idx / M) * LDT + idx % M] = (__bf16)xv[u];
+      }
+      __syncthreads();
+    }
     if (q0 + KR < 2 * e) rows.fetch(I, est_off, e, cur, q0 + KR);
     for (int t = w; t < NTILE; t += 4) {
       const int rb = t / CB, cb = t % CB;
@@ -1672,6 +1718,16 @@ __device__ void update_mfma(AnaSmem<M>& sm, const InstDesc& I, int est_off, int 
           const float a = (k < m ? 1.f : 0.f) * (Xf[arow * LDX + k] - xb);  // masked by arithmetic, as above
           const float b = (float)sm.Bm[k * LDB + col];
           acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
+        }
+      } else if constexpr (PRE) {
+#pragma unroll
+        for (int ks = 0; ks < M / 32; ++ks) {
+          const int k0 = ks * 32 + 8 * (lane / 16);
+          const bf16x8 a = *(const bf16x8*)&Xb[arow * LDT + k0];
+          const bf16x8 bh = *(const bf16x8*)&Th[col * LDT + k0];
+          const bf16x8 bl = *(const bf16x8*)&Tl[col * LDT + k0];
+          acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bh, acc, 0, 0, 0);
+          acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bl, acc, 0, 0, 0);
         }
       } else {
         for (int ks = 0; ks < (M + 31) / 32; ++ks) {
