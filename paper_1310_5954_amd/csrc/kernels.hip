@@ -904,8 +904,12 @@ __device__ __forceinline__ bool gram_converged(const R* B, const R* nrm, R tol2)
   for (int x = 0; x < TM; ++x)
 #pragma unroll
     for (int y = 0; y < TM; ++y) g[x][y] = 0;
+  // lane tj visits the rows from tj on (mod M): the 16 columns tj + 16 x that
+  // a pass of lanes reads then fall in 16 bank pairs (all at one row they sat
+  // in two, a column being LD doubles apart)
 #pragma unroll 2
-  for (int r = 0; r < M; ++r) {
+  for (int r0 = 0; r0 < M; ++r0) {
+    const int r = (r0 + tj) & (M - 1);
     R u[TM], v[TM];
 #pragma unroll
     for (int x = 0; x < TM; ++x) {
@@ -981,7 +985,12 @@ __device__ __forceinline__ int jacobi_core(AnaSmem<M>& sm, int m, R* B, R* nrm, 
       // changed (late sweeps mostly keep it).
       constexpr int PER = M / TPC, CH = PER < 16 ? PER : 16;
       R ss = 0;
-      for (int r = part; r < M; r += TPC) { const R v = B[c * LD + r]; ss = fma(v, v, ss); }
+      // column c's threads start at a row that shifts with c, so that the four
+      // columns a pass of lanes reads fall in different banks
+      for (int j0 = 0; j0 < PER; ++j0) {
+        const R v = B[c * LD + part + TPC * ((j0 + c) & (PER - 1))];
+        ss = fma(v, v, ss);
+      }
       ss = group_sum<TPC>(ss);
       if (part == 0) nrm[c] = ss;
       if (tid == 0) sm.s_rot = 0;  // last read before the previous sweep's closing barrier
@@ -1115,9 +1124,12 @@ __device__ __forceinline__ int jacobi_core(AnaSmem<M>& sm, int m, R* B, R* nrm, 
             for (int u = 0; u < C::RPT; ++u) bj[sub + u * TPP] = sn * xi[u] + c * xc[u];
             al -= t * gsum;
             bc += t * gsum;
-            // every lane of the slot stores the same norm (and flag)
-            LN[jj] = bc;
-            sm.s_rot = 1;
+            // one lane of the slot stores the norm and the flag (all eight storing
+            // the same value saved an exec-mask region but cost ~1 % of the sweep)
+            if (sub == 0) {
+              LN[jj] = bc;
+              sm.s_rot = 1;
+            }
           }
           if (stale && !rot) {
             LR* bj = LB + jj * LD;
