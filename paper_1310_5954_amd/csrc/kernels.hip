@@ -383,6 +383,22 @@ template <int M> struct AnaSmem {
   __device__ double* red() { return (double*)stage; }  // NT partial sums, aliases the staging area
 };
 
+// The entry (i, j) of A = (m-1)/rho I + C into LDS at (i, j) only: for the FP64
+// gather, whose 16 tiles cover both halves and compute C_ij and C_ji with the
+// same products summed in the same order (bitwise equal), so every entry is
+// written once and along rows (the mirrored write went down a column, an 8-way
+// bank conflict).
+template <int M>
+__device__ __forceinline__ void put_A_own(AnaSmem<M>& sm, int i, int j, int m, double c, double a_diag, double* dbg) {
+  double v = c;
+  if (i >= m || j >= m) v = (i == j) ? 1.0 : 0.0;
+  else {
+    if (dbg) dbg[i * m + j] = c;
+    if (i == j) v += a_diag;
+  }
+  sm.Bm[i * AnaCfg<M>::LDB + j] = v;
+}
+
 // Writes the entry (i, j) of A = (m-1)/rho I + C into LDS (symmetrically: only
 // the producer of i <= j writes, to both halves), padded members -> identity.
 template <int M>
@@ -570,7 +586,7 @@ __device__ void gather_C_fp64_mfma(AnaSmem<M>& sm, const InstDesc& I, int obs_of
       for (int b = 0; b < WT; ++b)
 #pragma unroll
         for (int v = 0; v < 4; ++v)
-          put_A<M>(sm, (tr0 + a) * 16 + lane / 16 + 4 * v, (tc0 + b) * 16 + lane % 16, m, acc[a][b][v], I.a_diag, dbg);
+          put_A_own<M>(sm, (tr0 + a) * 16 + lane / 16 + 4 * v, (tc0 + b) * 16 + lane % 16, m, acc[a][b][v], I.a_diag, dbg);
   }
   // b: threads sharing j = tid % M hold partial sums
   sm.red()[tid] = bpart;
@@ -1005,15 +1021,18 @@ __device__ __forceinline__ int jacobi_core(AnaSmem<M>& sm, int m, R* B, R* nrm, 
       const int rank = c < m ? (int)ahead : c;
       if (__syncthreads_or(rank != c)) {
         for (int k0 = 0; k0 < PER; k0 += CH) {
+          // rows rotated by c within the pass, as in the norms: the reads then
+          // avoid bank conflicts, and the writes (to the rank's column, same
+          // rows) mostly do
           R v[CH];
 #pragma unroll
-          for (int k = 0; k < CH; ++k) v[k] = B[c * LD + part + TPC * (k0 + k)];
+          for (int k = 0; k < CH; ++k) v[k] = B[c * LD + part + TPC * (k0 + ((k + c) & (CH - 1)))];
           // every read of this pass's rows (rows TPC k0 .. TPC (k0 + CH) - 1, which no
           // other pass touches) is done before any column moves; the sweep reads
           // the moved columns after the barrier that follows
           __syncthreads();
 #pragma unroll
-          for (int k = 0; k < CH; ++k) B[rank * LD + part + TPC * (k0 + k)] = v[k];
+          for (int k = 0; k < CH; ++k) B[rank * LD + part + TPC * (k0 + ((k + c) & (CH - 1)))] = v[k];
         }
         if (part == 0) nrm[rank] = ss;
         __syncthreads();  // the moved columns and norms before the sweep reads them
