@@ -6,7 +6,9 @@ from __future__ import annotations
 
 import concurrent.futures as cf
 import hashlib
+import json
 import os
+import re
 import subprocess
 import sys
 
@@ -49,11 +51,36 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
+RESOURCES = os.path.join(LIBDIR, "kernel_resources.json")
+_REMARK = re.compile(r"remark:\s+(Function Name|VGPRs|AGPRs|ScratchSize \[bytes/lane\]|Occupancy \[waves/SIMD\]|"
+                     r"VGPRs Spill|LDS Size \[bytes/block\]): (\S+)")
+_KEYS = {"VGPRs": "vgprs", "AGPRs": "agprs", "ScratchSize [bytes/lane]": "scratch_bytes",
+         "Occupancy [waves/SIMD]": "waves_per_simd", "VGPRs Spill": "vgpr_spill", "LDS Size [bytes/block]": "lds_bytes"}
+
+
+def _resources(stderr: str) -> dict:
+    """Per-kernel register, occupancy and LDS figures from the compiler's
+    resource-usage remarks (the device pass of kernels.hip)."""
+    out, cur = {}, None
+    for m in _REMARK.finditer(stderr):
+        key, val = m.group(1), m.group(2)
+        if key == "Function Name":
+            cur = out.setdefault(val, {})
+        elif cur is not None:
+            cur[_KEYS[key]] = int(val)
+    return out
+
+
 def _compile(src: str, obj: str, build_id: str) -> None:
-    cmd = ["hipcc", *FLAGS, f'-DLETKF_BUILD_ID="{build_id}"', "-c", os.path.join(CSRC, src), "-o", obj]
+    remarks = ["-Rpass-analysis=kernel-resource-usage"] if src == "kernels.hip" else []
+    cmd = ["hipcc", *FLAGS, *remarks, f'-DLETKF_BUILD_ID="{build_id}"', "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")
+    if remarks:
+        with open(RESOURCES + ".tmp", "w") as fh:
+            json.dump({"build_id": build_id, "kernels": _resources(r.stderr)}, fh, indent=1, sort_keys=True)
+        os.replace(RESOURCES + ".tmp", RESOURCES)
 
 
 def build(verbose: bool = True) -> str:

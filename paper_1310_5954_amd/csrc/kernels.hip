@@ -1031,8 +1031,13 @@ __device__ __forceinline__ int jacobi_core(AnaSmem<M>& sm, int m, R* B, R* nrm, 
           // other pass touches) is done before any column moves; the sweep reads
           // the moved columns after the barrier that follows
           __syncthreads();
+          // the write addresses recomputed from a copy of c the compiler cannot
+          // see through: kept from the reads, the CH addresses stayed live
+          // across the barrier and raised the kernel's register count
+          int cw = c;
+          __asm__ volatile("" : "+v"(cw));
 #pragma unroll
-          for (int k = 0; k < CH; ++k) B[rank * LD + part + TPC * (k0 + ((k + c) & (CH - 1)))] = v[k];
+          for (int k = 0; k < CH; ++k) B[rank * LD + part + TPC * (k0 + ((k + cw) & (CH - 1)))] = v[k];
         }
         if (part == 0) nrm[rank] = ss;
         __syncthreads();  // the moved columns and norms before the sweep reads them
