@@ -948,6 +948,54 @@ __device__ __forceinline__ bool gram_converged(const R* B, const R* nrm, R tol2)
   return !__syncthreads_or(bad);
 }
 
+// The same test for FP64 columns at M = 64 with the products on the matrix
+// cores: wavefront w forms the 2 x 2 tiles (16 x 16 each) of B^T B at tile rows
+// 2 (w / 2), 2 (w / 2) + 1 and tile columns 2 (w % 2), 2 (w % 2) + 1.  Each lane
+// reads two consecutive rows of its column with one 16-byte load, the A / B
+// operands of two k-steps (rows r0 + 2 k and r0 + 2 k + 1 for the operand's
+// k = lane / 16).  The VALU form spent ~25k cycles per test on 512 LDS loads
+// and 1024 FMAs per thread; this one 64 MFMAs and 32 loads per wavefront.
+template <int LD>
+__device__ __forceinline__ bool gram_converged_mfma64(const double* B, const double* nrm, double tol2) {
+  const int tid = phase_tid(), w = tid / 64, lane = tid % 64;
+  const int tr0 = (w >> 1) * 2, tc0 = (w & 1) * 2;
+  const int kq = lane / 16, cl = lane % 16;
+  f64x4 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 2
+  for (int r0 = 0; r0 < 64; r0 += 8) {
+    const int r = r0 + 2 * kq;
+    double2 av[2], bv[2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      av[a] = *(const double2*)&B[((tr0 + a) * 16 + cl) * LD + r];
+      bv[a] = *(const double2*)&B[((tc0 + a) * 16 + cl) * LD + r];
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a].x, bv[b].x, acc[a][b], 0, 0, 0);
+        acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a].y, bv[b].y, acc[a][b], 0, 0, 0);
+      }
+  }
+  bool bad = false;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = (tr0 + a) * 16 + kq + 4 * v, j = (tc0 + b) * 16 + cl;
+        const double g = acc[a][b][v];
+        bad |= i < j && g * g > tol2 * (nrm[i] * nrm[j]);
+      }
+  return !__syncthreads_or(bad);
+}
+
 // ---- a6 (second half): one-sided (Hestenes) Jacobi on the columns of L ------
 // L J = U Sigma with U the eigenvectors of A = L L^T and lambda = sigma^2, so
 // no rotation accumulator is needed; rounding scales with sqrt(lambda), and
@@ -972,10 +1020,14 @@ __device__ __forceinline__ int jacobi_core(AnaSmem<M>& sm, int m, R* B, R* nrm, 
   const bool active = C::ACTIVE >= NT || tid < C::ACTIVE;
   const int q = tid / TPP, sub = tid % TPP;
   const R tol2 = tol * tol;
-  // Once no rotation of a sweep exceeded this cosine, the columns are close
-  // enough that the next sweep is most likely the one that finds nothing to
-  // do; the Gram test decides that in a fraction of a sweep's cost.
-  const R trig = tol * (R)100 > (R)1e-7 ? tol * (R)100 : (R)1e-7;
+  // Once no rotation of a sweep had a relative off-diagonal above trig, the
+  // next sweep is likely to find nothing to do, and the Gram test (a fraction
+  // of a sweep's cost) is tried instead.  trig = tol^(1/3) / 5: on a CPU
+  // replay of the 375 domains of the 84 x 84 map this is where fewer wasted
+  // final sweeps stop paying for more failed Gram tests (FP64, tol 4.5e-13:
+  // 7.63 -> 7.08 sweeps and 0.44 -> 1.03 Gram tests per domain against the
+  // former 1e-7; tol 1e-6: 6.96 -> 6.3 sweeps; tol 1e-4 stays at 6.0).
+  const R trig = (R)0.2 * cbrt(tol);
   const R trig2 = trig * trig;
   const R tol4 = (R)4 * tol2, trig4 = (R)4 * trig2;
   constexpr bool PREFETCH = C::RPT <= 16;
@@ -1213,7 +1265,12 @@ __device__ __forceinline__ int jacobi_core(AnaSmem<M>& sm, int m, R* B, R* nrm, 
     ++sweeps;
     const int any = sm.s_rot;
     const int any_big = __syncthreads_or(big >= 0);
-    if (!any || (!any_big && gram_converged<R, M, LD>(B, nrm, tol2))) {
+    bool gram = false;
+    if (any && !any_big) {
+      if constexpr (sizeof(R) == 8 && M == 64 && LD % 2 == 0) gram = gram_converged_mfma64<LD>((const double*)B, (const double*)nrm, (double)tol2);
+      else gram = gram_converged<R, M, LD>(B, nrm, tol2);
+    }
+    if (!any || gram) {
       converged = true;
       break;
     }
