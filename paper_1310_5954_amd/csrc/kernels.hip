@@ -504,80 +504,86 @@ __device__ void gather_C_fp64_mfma(AnaSmem<M>& sm, const InstDesc& I, int obs_of
   double bpart = 0.0;
   const double* Yp = (const double*)I.Yp;
   const int nobs = 2 * s;
-  // Thread (kk0 = tid / M, j = tid % M) stages observations kk0 + e NT / M of
-  // every chunk for member j.  The next chunk's rows are loaded into registers
-  // before the current chunk's MFMAs, so their latency overlaps the products.
-  constexpr int EPT = KCH * M / NT;
-  static_assert(KCH * M % NT == 0, "whole chunks per thread");
-  // M >= 64: a wavefront's lanes share kk0, so the observation's row, r and d are scalar loads
-  const int kk0 = M >= 64 ? __builtin_amdgcn_readfirstlane(tid / M) : tid / M, j = tid % M;
-  // per staged value: y, sqrt(r) (host-computed) and d, in two register sets
-  // that alternate between chunks: fetch() only issues loads, into the set
-  // the chunk after this one stages from, so they stay in flight across this
-  // chunk's products (with one set the compiler copied the fetched registers
-  // early, which waited for the loads right after the first product)
-  struct Vals {
-    double y[EPT], s[EPT], d[EPT];
-  };
-  Vals va, vb;
+  // The domain's observation table (row of Y', sqrt(r), sqrt(r) d) is staged
+  // in LDS, in the space A takes only once the products are done, by segments
+  // of SEG observations (one segment on the ELT maps).  The chunk loop then
+  // issues only the loads of Y' rows, three chunks of them in flight: with the
+  // index, r and d loads in the loop, each chunk's loads waited on the
+  // previous chunk's and a chunk spent ~5k cycles for ~1k of products.
+  constexpr int SEG = (M * C::LDB * 8 / 20) / KCH * KCH;
+  static_assert(SEG >= KCH && SEG % 2 == 0, "observation table");
+  int* rowT = reinterpret_cast<int*>(sm.Bm);
+  double* sT = sm.Bm + SEG / 2;
+  double* sdT = sT + SEG;
   const int32_t* obs_row = I.obs_row + 2 * obs_off;
   const double* obs_sr = I.obs_sr + 2 * obs_off;
   const double* dvec = I.d;
-  // The row indices run one chunk ahead of the loads that use them, so a
-  // fetch never waits for its own index loads (that wait, before the
-  // chunk's products, exposed their latency on every chunk).
-  int row[EPT];
-  auto fetch_rows = [&](int q0) {
-#pragma unroll
-    for (int e = 0; e < EPT; ++e) {
-      const int q = q0 + kk0 + e * (NT / M);
-      row[e] = (q < nobs && j < m) ? gload(obs_row + q) : -1;
-    }
-  };
-  auto fetch = [&](Vals& v, int q0) {  // chunk q0, whose row indices are in row[]
-#pragma unroll
-    for (int e = 0; e < EPT; ++e) {
-      const int q = q0 + kk0 + e * (NT / M);
-      v.s[e] = q < nobs ? gload(obs_sr + q) : 0.0;
-      v.y[e] = v.d[e] = 0.0;
-      if (row[e] >= 0) {
-        v.d[e] = gload(dvec + row[e]);
-        v.y[e] = gload(Yp + (size_t)row[e] * m + j);
+  // Thread (kk0 = tid / M, j = tid % M) stages observations kk0 + e NT / M of
+  // every chunk for member j.
+  constexpr int EPT = KCH * M / NT;
+  static_assert(KCH * M % NT == 0, "whole chunks per thread");
+  // M >= 64: a wavefront's lanes share kk0, so their table reads are broadcasts
+  const int kk0 = M >= 64 ? __builtin_amdgcn_readfirstlane(tid / M) : tid / M, j = tid % M;
+  for (int g0 = 0; g0 < nobs; g0 += SEG) {
+    const int gn = nobs - g0 < SEG ? nobs - g0 : SEG;
+    const int gr = (gn + KCH - 1) / KCH * KCH;
+    // (the previous segment's last chunk ended with a barrier)
+    for (int q = tid; q < gr; q += NT) {
+      int rw = 0;
+      double sr = 0.0, sd = 0.0;
+      if (q < gn) {
+        rw = gload(obs_row + g0 + q);
+        sr = gload(obs_sr + g0 + q);
+        sd = sr * gload(dvec + rw);
       }
-    }
-    fetch_rows(q0 + KCH);
-  };
-  auto chunk = [&](const Vals& v, Vals& next, int q0) {
-#pragma unroll
-    for (int e = 0; e < EPT; ++e) {
-      const double sy = v.s[e] * v.y[e];
-      bpart = fma(v.s[e] * v.d[e], sy, bpart);  // r d y with r = sqrt(r)^2
-      At[j * LDK + kk0 + e * (NT / M)] = sy;
+      rowT[q] = rw;
+      sT[q] = sr;
+      sdT[q] = sd;
     }
     __syncthreads();
-    if (q0 + KCH < nobs) fetch(next, q0 + KCH);
-    if (wave_on) {
+    auto fetch = [&](double (&y)[EPT], int q0) {  // Y' of chunk q0 (segment-relative)
 #pragma unroll
-      for (int ks = 0; ks < KCH / 4; ++ks) {
-        double av[WT], bv[WT];
+      for (int e = 0; e < EPT; ++e) {
+        const int q = q0 + kk0 + e * (NT / M);
+        y[e] = 0.0;
+        if (q < gn && j < m) y[e] = gload(Yp + (size_t)rowT[q] * m + j);
+      }
+    };
+    auto chunk = [&](const double (&y)[EPT], double (&next)[EPT], int q0) {
 #pragma unroll
-        for (int a = 0; a < WT; ++a) {
-          av[a] = At[((tr0 + a) * 16 + lane % 16) * LDK + ks * 4 + lane / 16];
-          bv[a] = At[((tc0 + a) * 16 + lane % 16) * LDK + ks * 4 + lane / 16];
+      for (int e = 0; e < EPT; ++e) {
+        const int q = q0 + kk0 + e * (NT / M);  // < gr: the table's tail is zero
+        const double sy = sT[q] * y[e];
+        bpart = fma(sdT[q], sy, bpart);  // r d y with r = sqrt(r)^2
+        At[j * LDK + kk0 + e * (NT / M)] = sy;
+      }
+      __syncthreads();
+      if (q0 + 2 * KCH < gn) fetch(next, q0 + 2 * KCH);
+      if (wave_on) {
+#pragma unroll
+        for (int ks = 0; ks < KCH / 4; ++ks) {
+          double av[WT], bv[WT];
+#pragma unroll
+          for (int a = 0; a < WT; ++a) {
+            av[a] = At[((tr0 + a) * 16 + lane % 16) * LDK + ks * 4 + lane / 16];
+            bv[a] = At[((tc0 + a) * 16 + lane % 16) * LDK + ks * 4 + lane / 16];
+          }
+#pragma unroll
+          for (int a = 0; a < WT; ++a)
+#pragma unroll
+            for (int b = 0; b < WT; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
         }
-#pragma unroll
-        for (int a = 0; a < WT; ++a)
-#pragma unroll
-          for (int b = 0; b < WT; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
       }
+      __syncthreads();
+    };
+    double ya[EPT], yb[EPT], yc[EPT];
+    fetch(ya, 0);
+    if (KCH < gn) fetch(yb, KCH);
+    for (int q0 = 0; q0 < gn; q0 += 3 * KCH) {
+      chunk(ya, yc, q0);
+      if (q0 + KCH < gn) chunk(yb, ya, q0 + KCH);
+      if (q0 + 2 * KCH < gn) chunk(yc, yb, q0 + 2 * KCH);
     }
-    __syncthreads();
-  };
-  fetch_rows(0);
-  fetch(va, 0);
-  for (int q0 = 0; q0 < nobs; q0 += 2 * KCH) {
-    chunk(va, vb, q0);
-    if (q0 + KCH < nobs) chunk(vb, va, q0 + KCH);
   }
   if (wave_on) {
 #pragma unroll
