@@ -773,6 +773,140 @@ __device__ void gather_C_mfma(AnaSmem<M>& sm, const InstDesc& I, int obs_off, in
   __syncthreads();
 }
 
+// The BF16 paths at M <= 64: the same products as gather_C_mfma, with the
+// observation table staged in LDS first (as in the FP64 gather: row of Y',
+// sqrt(r), sqrt(r) d, in the space A takes afterwards), so that the chunk
+// loop issues only the FP32 loads of Y' rows, three chunks in flight.  With
+// the index, r and d loads in the loop a chunk of 32 observations spent
+// ~6.6k cycles for a few hundred cycles of products.
+template <int P, int M>
+__device__ void gather_C_bf16_tab(AnaSmem<M>& sm, const InstDesc& I, int obs_off, int s, double* dbg) {
+  using C = AnaCfg<M>;
+  static_assert(P >= 2 && M <= 64, "BF16 paths, M <= 64");
+  constexpr int NT = C::NT, KCH = C::KCB, LDKB = C::LDKB;
+  constexpr int TILES = M / 16;
+  constexpr int WT = TILES >= 2 ? TILES / 2 : 1;
+  const int m = I.m, tid = phase_tid(), w = tid / 64, lane = tid % 64;
+  const bool wave_on = TILES >= 2 || w == 0;
+  const int tr0 = TILES >= 2 ? (w / 2) * WT : 0;
+  const int tc0 = TILES >= 2 ? (w % 2) * WT : 0;
+  f32x4 acc[WT][WT];
+#pragma unroll
+  for (int a = 0; a < WT; ++a)
+#pragma unroll
+    for (int b = 0; b < WT; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+  double bpart = 0.0;
+  const float* Yp = (const float*)I.Yp;
+  const int nobs = 2 * s;
+  constexpr int SEG = (M * C::LDB * 8 / 20) / KCH * KCH;
+  static_assert(SEG >= KCH && SEG % 2 == 0, "observation table");
+  int* rowT = reinterpret_cast<int*>(sm.Bm);
+  double* sT = sm.Bm + SEG / 2;
+  double* sdT = sT + SEG;
+  const int32_t* obs_row = I.obs_row + 2 * obs_off;
+  const double* obs_sr = I.obs_sr + 2 * obs_off;
+  const double* dvec = I.d;
+  // Thread (kk0 = tid / M, j = tid % M) stages observations kk0 + e NT / M of
+  // every chunk for member j.
+  constexpr int EPT = KCH * M / NT;
+  static_assert(KCH * M % NT == 0, "whole chunks per thread");
+  const int kk0 = M >= 64 ? __builtin_amdgcn_readfirstlane(tid / M) : tid / M, j = tid % M;
+  __bf16* Ah = (__bf16*)sm.stage;
+  __bf16* Al = Ah + M * LDKB;
+  for (int g0 = 0; g0 < nobs; g0 += SEG) {
+    const int gn = nobs - g0 < SEG ? nobs - g0 : SEG;
+    const int gr = (gn + KCH - 1) / KCH * KCH;
+    // (the previous segment's last chunk ended with a barrier)
+    for (int q = tid; q < gr; q += NT) {
+      int rw = 0;
+      double sr = 0.0, sd = 0.0;
+      if (q < gn) {
+        rw = gload(obs_row + g0 + q);
+        sr = gload(obs_sr + g0 + q);
+        sd = sr * gload(dvec + rw);
+      }
+      rowT[q] = rw;
+      sT[q] = sr;
+      sdT[q] = sd;
+    }
+    __syncthreads();
+    auto fetch = [&](float (&y)[EPT], int q0) {  // Y' of chunk q0 (segment-relative)
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) {
+        const int q = q0 + kk0 + e * (NT / M);
+        y[e] = 0.f;
+        if (q < gn && j < m) y[e] = gload(Yp + (size_t)rowT[q] * m + j);
+      }
+    };
+    auto chunk = [&](const float (&y)[EPT], float (&next)[EPT], int q0) {
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) {
+        const int q = q0 + kk0 + e * (NT / M);  // < gr: the table's tail is zero
+        const int kk = kk0 + e * (NT / M);
+        const double sy = sT[q] * (double)y[e];
+        bpart += sdT[q] * sy;  // r d y with r = sqrt(r)^2
+        // split BF16: x = hi + lo with hi = bf16(x), lo = bf16(x - hi)
+        const float xf = (float)sy;
+        const __bf16 hi = (__bf16)xf;
+        Ah[j * LDKB + kk] = hi;
+        Al[j * LDKB + kk] = (__bf16)(xf - (float)hi);
+      }
+      __syncthreads();
+      if (q0 + 2 * KCH < gn) fetch(next, q0 + 2 * KCH);
+      if (wave_on) {
+        // C += hi hi^T + hi lo^T + lo hi^T (the lo lo^T term is below FP32 rounding)
+        bf16x8 ah[WT], al[WT], bh[WT], bl[WT];
+#pragma unroll
+        for (int a = 0; a < WT; ++a) {
+          const int ra = ((tr0 + a) * 16 + lane % 16) * LDKB + 8 * (lane / 16);
+          const int rb = ((tc0 + a) * 16 + lane % 16) * LDKB + 8 * (lane / 16);
+          ah[a] = *(const bf16x8*)(Ah + ra);
+          al[a] = *(const bf16x8*)(Al + ra);
+          bh[a] = *(const bf16x8*)(Ah + rb);
+          bl[a] = *(const bf16x8*)(Al + rb);
+        }
+#pragma unroll
+        for (int a = 0; a < WT; ++a)
+#pragma unroll
+          for (int b = 0; b < WT; ++b) {
+            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bh[b], acc[a][b], 0, 0, 0);
+            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bl[b], acc[a][b], 0, 0, 0);
+            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[a], bh[b], acc[a][b], 0, 0, 0);
+          }
+      }
+      __syncthreads();
+    };
+    float ya[EPT], yb[EPT], yc[EPT];
+    fetch(ya, 0);
+    if (KCH < gn) fetch(yb, KCH);
+    for (int q0 = 0; q0 < gn; q0 += 3 * KCH) {
+      chunk(ya, yc, q0);
+      if (q0 + KCH < gn) chunk(yb, ya, q0 + KCH);
+      if (q0 + 2 * KCH < gn) chunk(yc, yb, q0 + 2 * KCH);
+    }
+  }
+  if (wave_on) {
+#pragma unroll
+    for (int a = 0; a < WT; ++a)
+#pragma unroll
+      for (int b = 0; b < WT; ++b)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i = (tr0 + a) * 16 + 4 * (lane / 16) + v, jj = (tc0 + b) * 16 + lane % 16;
+          put_A<M>(sm, i, jj, m, (double)acc[a][b][v], I.a_diag, dbg);
+        }
+  }
+  // b: threads sharing j = tid % M hold partial sums
+  sm.red()[tid] = bpart;
+  __syncthreads();
+  if (tid < M) {
+    double t = 0.0;
+    for (int q = tid; q < NT; q += M) t += sm.red()[q];
+    sm.bvec[tid] = tid < m ? t : 0.0;
+  }
+  __syncthreads();
+}
+
 // ---- a6 (first half): Cholesky factor A = L L^T (FP64) ----------------------
 // Right-looking, by panels of 16 columns.  Wavefront 0 factors a panel on its
 // own: lane l holds rows c0 + l (and c0 + 64 + l at M = 128) of the panel's
@@ -1931,6 +2065,7 @@ __device__ void analyse_item(AnaSmem<M>& sm, const InstDesc* __restrict__ tab, c
 
   if constexpr (P == 0 && M <= 64) gather_C_fp64_mfma<M>(sm, I, obs_off, s, dbg);
   else if constexpr (P == 0) gather_C_fp64<M>(sm, I, obs_off, s, dbg);
+  else if constexpr (P >= 2 && M <= 64) gather_C_bf16_tab<P, M>(sm, I, obs_off, s, dbg);
   else gather_C_mfma<P, M>(sm, I, obs_off, s, dbg);
   if constexpr (P == 0) {
     __syncthreads();
