@@ -146,10 +146,22 @@ def test_ensemble_sizes_and_padding_fp64(m):
 
 def test_global_domain_many_chunks_fp64():
     """One domain holding the whole 15x15 pupil: 450 observation rows and
-    512 state rows stream through the LDS chunks."""
+    512 state rows stream through the LDS chunks (at m = 16 the observation
+    table goes through LDS in four segments of 144 rows)."""
     case = build_case(1, global_map=True)
     X, k = oracle_spin_up(case, 2)
     _check_step(case, X, k, FP64, debug=True)
+
+
+@pytest.mark.parametrize("precision,fp32_rotations", [(FP32, False), (BF16, False), (BF16, True)])
+def test_global_domain_many_chunks_low_precision(precision, fp32_rotations):
+    """The same global domain on the FP32 and BF16 paths: at m = 16 the BF16
+    gathers stage the observation table in segments of 128 rows, so the 450
+    rows take four segments (the FP64 gather's segments are 144 rows)."""
+    case = build_case(1, global_map=True)
+    assert case.m == 16 and 2 * np.diff(case.dmap.obs_ptr)[0] > 3 * 128
+    X, k = oracle_spin_up(case, 2)
+    _check_step(case, X, k, precision, debug=True, fp32_rotations=fp32_rotations)
 
 
 def test_domain_without_observations_is_identity():
