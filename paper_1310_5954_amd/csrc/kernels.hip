@@ -511,7 +511,7 @@ __device__ void gather_C_fp64_mfma(AnaSmem<M>& sm, const InstDesc& I, int obs_of
   // index, r and d loads in the loop, each chunk's loads waited on the
   // previous chunk's and a chunk spent ~5k cycles for ~1k of products.
   constexpr int SEG = (M * C::LDB * 8 / 20) / KCH * KCH;
-  static_assert(SEG >= KCH && SEG % 2 == 0, "observation table");
+  static_assert(SEG >= KCH && SEG % 2 == 0 && (size_t)SEG * (4 + 8 + 8) <= sizeof(sm.Bm), "observation table");
   int* rowT = reinterpret_cast<int*>(sm.Bm);
   double* sT = sm.Bm + SEG / 2;
   double* sdT = sT + SEG;
@@ -799,7 +799,7 @@ __device__ void gather_C_bf16_tab(AnaSmem<M>& sm, const InstDesc& I, int obs_off
   const float* Yp = (const float*)I.Yp;
   const int nobs = 2 * s;
   constexpr int SEG = (M * C::LDB * 8 / 20) / KCH * KCH;
-  static_assert(SEG >= KCH && SEG % 2 == 0, "observation table");
+  static_assert(SEG >= KCH && SEG % 2 == 0 && (size_t)SEG * (4 + 8 + 8) <= sizeof(sm.Bm), "observation table");
   int* rowT = reinterpret_cast<int*>(sm.Bm);
   double* sT = sm.Bm + SEG / 2;
   double* sdT = sT + SEG;
