@@ -121,6 +121,7 @@ struct letkf_handle {
   hipGraphExec_t graph_exec = nullptr;
   // analysis launch: persistent grid and domain order (letkf_autotune)
   int ana_grid = 0;
+  int num_cu = 0;            // CUs of the device (the analysis launch's issue-priority rule)
   int max_rows = 0;            // most state rows of a domain (2 e), for the m > 128 launch sequence
   int order = LETKF_ORDER_COST;
   // serving

@@ -1023,6 +1023,13 @@ __device__ __forceinline__ float approx_rsq(float x) { return __builtin_amdgcn_r
 __device__ __forceinline__ double approx_rcp(double x) { return __builtin_amdgcn_rcp(x); }
 __device__ __forceinline__ float approx_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ double rsqrt_acc(double x) { return rsqrt_1_2(x); }
+// Issue priority of the calling wavefront (0..3; wavefront-uniform argument).
+__device__ __forceinline__ void set_issue_prio(int p) {
+  if (p >= 3) __builtin_amdgcn_s_setprio(3);
+  else if (p == 2) __builtin_amdgcn_s_setprio(2);
+  else if (p == 1) __builtin_amdgcn_s_setprio(1);
+  else __builtin_amdgcn_s_setprio(0);
+}
 // the word holding the sign: non-negative exactly when x >= +0
 __device__ __forceinline__ int sign_word(double x) { return (int)(__double_as_longlong(x) >> 32); }
 __device__ __forceinline__ int sign_word(float x) { return __float_as_int(x); }
@@ -1151,7 +1158,7 @@ __device__ __forceinline__ bool gram_converged_mfma64(const double* B, const dou
 // the sweeps done; `converged` is set when a sweep rotated nothing or the
 // Gram test passed, and stays false when the sweep cap ended the loop.
 template <typename R, int M, int LD>
-__device__ __forceinline__ int jacobi_core(AnaSmem<M>& sm, int m, R* B, R* nrm, R tol, bool& converged) {
+__device__ __forceinline__ int jacobi_core(AnaSmem<M>& sm, int m, R* B, R* nrm, R tol, bool& converged, bool fair) {
   using C = AnaCfg<M>;
   constexpr int NT = C::NT, TPP = C::TPP;
   constexpr int PSW = 64 / TPP;  // pair slots per wavefront
@@ -1182,6 +1189,8 @@ __device__ __forceinline__ int jacobi_core(AnaSmem<M>& sm, int m, R* B, R* nrm, 
   int sweeps = 0;
   converged = false;
   for (; sweeps < C::MAX_SWEEPS;) {
+    // progress-ordered issue (see k_analysis): the priority falls as the sweeps go by
+    if (fair) set_issue_prio(sweeps < 3 ? 3 : sweeps < 5 ? 2 : sweeps < 6 ? 1 : 0);
     {
       constexpr int TPC = NT / M;  // threads per column for the norms
       const int c = tid / TPC, part = tid % TPC;
@@ -1434,7 +1443,7 @@ __device__ __forceinline__ int jacobi_core(AnaSmem<M>& sm, int m, R* B, R* nrm, 
 // columns at stride M + TPP inside the double storage), rotated, and widened
 // back.  The other paths rotate in FP64.
 template <int P, int M>
-__device__ int jacobi(AnaSmem<M>& sm, int m, bool& converged) {
+__device__ int jacobi(AnaSmem<M>& sm, int m, bool& converged, bool fair) {
   using C = AnaCfg<M>;
   if constexpr (P == 3) {
     // In-place width change by chunks of CC columns (at most 16 values per
@@ -1465,7 +1474,7 @@ __device__ int jacobi(AnaSmem<M>& sm, int m, bool& converged) {
       }
     }
     __syncthreads();
-    const int sweeps = jacobi_core<float, M, LDF>(sm, m, Bf, nf, 1e-4f, converged);
+    const int sweeps = jacobi_core<float, M, LDF>(sm, m, Bf, nf, 1e-4f, converged, fair);
     for (int c0 = M - CC; c0 >= 0; c0 -= CC) {
       float v[PER];
 #pragma unroll
@@ -1484,7 +1493,7 @@ __device__ int jacobi(AnaSmem<M>& sm, int m, bool& converged) {
     return sweeps;
   } else {
     const double tol = P == 0 ? 32.0 * (double)M * 1.1102230246251565e-16 : (P == 1 ? 1e-6 : 1e-4);
-    return jacobi_core<double, M, C::LDB>(sm, m, sm.Bm, sm.nrm, tol, converged);
+    return jacobi_core<double, M, C::LDB>(sm, m, sm.Bm, sm.nrm, tol, converged, fair);
   }
 }
 
@@ -2042,7 +2051,7 @@ __device__ void sort_diag(AnaSmem<M>& sm, int m) {
 }
 
 template <int P, int M>
-__device__ void analyse_item(AnaSmem<M>& sm, const InstDesc* __restrict__ tab, const ClassBatch& cb, int item) {
+__device__ void analyse_item(AnaSmem<M>& sm, const InstDesc* __restrict__ tab, const ClassBatch& cb, int item, bool fair) {
   using C = AnaCfg<M>;
   const int eb = find_entry(cb.dom_off, cb.n, item);
   const InstDesc& I = tab[cb.inst[eb]];
@@ -2057,6 +2066,7 @@ __device__ void analyse_item(AnaSmem<M>& sm, const InstDesc* __restrict__ tab, c
     if (dbg && threadIdx.x == 0) dbg[2 * m * m + m + k] = (double)clock64();
   };
   stamp(0);
+  if (fair) set_issue_prio(3);
   if (dbg && threadIdx.x == 0) {  // debug: where the workgroup runs (HW_ID: SE, SH, CU, SIMD; XCC_ID)
     dbg[2 * m * m + m + 6] = (double)__builtin_amdgcn_s_getreg(4 | (31 << 11));
     dbg[2 * m * m + m + 7] = (double)__builtin_amdgcn_s_getreg(20 | (31 << 11));
@@ -2084,8 +2094,9 @@ __device__ void analyse_item(AnaSmem<M>& sm, const InstDesc* __restrict__ tab, c
   cholesky<M>(sm);
   stamp(2);
   bool converged = false;
-  const int sweeps = jacobi<P, M>(sm, m, converged);
+  const int sweeps = jacobi<P, M>(sm, m, converged, fair);
   stamp(3);
+  if (fair) set_issue_prio(0);
   transform<P, M>(sm, I, l, dbg);
   stamp(4);
   if (threadIdx.x == 0) {
@@ -2107,16 +2118,28 @@ __device__ void analyse_item(AnaSmem<M>& sm, const InstDesc* __restrict__ tab, c
 // class occupies) and the heaviest domains, which come first in each
 // instance's order, start first.  Every workgroup leaves once a claim passes
 // the item count.
+// fair != 0 (launches whose workgroups start together with at most two on a
+// CU: the plain path): the wavefronts' issue priority falls with the item's
+// progress (3 from its start, then by Jacobi sweeps done: 2 from the 3rd,
+// 1 from the 5th, 0 from the 6th and after the eigensolve).  A SIMD issues
+// from the oldest of its ready wavefronts, so of two domains sharing a CU the
+// first dispatched ran nearly as if alone and the second got the leftover
+// slots, then finished alone at one wavefront per SIMD: on the 84 x 84 map
+// the pairs ended at 493k and 659k cycles (mean), with the priorities 566k
+// and 612k, and the plain FP64 launch went 296 -> 275 us.  With three or
+// more workgroups per CU (the serving batches) either ordering of the
+// priorities made the batches slower (serving -11 % with this one), so the
+// server launches with fair = 0.
 template <int P, int M>
 __global__ __launch_bounds__(256) void k_analysis(const InstDesc* __restrict__ tab,
-                                                  BatchHdr* __restrict__ hdr, int cls) {
+                                                  BatchHdr* __restrict__ hdr, int cls, int fair) {
   __shared__ AnaSmem<M> sm;
   __shared__ int s_next;
   ClassBatch& cb = hdr->cls[cls];
   const int total = cb.dom_off[cb.n];
   int item = blockIdx.x;
   while (item < total) {
-    analyse_item<P, M>(sm, tab, cb, item);
+    analyse_item<P, M>(sm, tab, cb, item, fair != 0);
     if (threadIdx.x == 0) s_next = (int)gridDim.x + (int)atomicAdd(&cb.next, 1u);
     __syncthreads();
     item = s_next;
@@ -2894,9 +2917,9 @@ void launch_big_analysis(int items, int rows_max, int m_max, const InstDesc* tab
                      cls);
 }
 
-void launch_analysis(int cls, int grid, const InstDesc* tab, BatchHdr* hdr, hipStream_t s) {
+void launch_analysis(int cls, int grid, const InstDesc* tab, BatchHdr* hdr, hipStream_t s, int fair) {
   if (grid <= 0 || cls == kBigClass) return;  // the m > 128 class runs launch_big_analysis
-#define LETKF_LAUNCH_ANA(K) hipLaunchKernelGGL(K, dim3(grid), dim3(256), 0, s, tab, hdr, cls)
+#define LETKF_LAUNCH_ANA(K) hipLaunchKernelGGL(K, dim3(grid), dim3(256), 0, s, tab, hdr, cls, fair)
   LETKF_ANA_KERNEL(cls, LETKF_LAUNCH_ANA);
 #undef LETKF_LAUNCH_ANA
 }

@@ -19,8 +19,13 @@ void launch_rows(int cls, int mode, int act_rows, const InstDesc* tab, BatchHdr*
 void launch_pistons(int cls, int domain_items, const InstDesc* tab, BatchHdr* hdr, hipStream_t s);
 // The persistent analysis kernel with `grid` workgroups: they share the
 // class's domain items through its work counter, which the slope kernel
-// launched before it zeroes, so any grid >= 1 covers every item.
-void launch_analysis(int cls, int grid, const InstDesc* tab, BatchHdr* hdr, hipStream_t s);
+// launched before it zeroes, so any grid >= 1 covers every item.  fair != 0:
+// progress-ordered issue priorities, for launches whose workgroups start
+// together at most two to a CU (analysis_fair_grid).
+void launch_analysis(int cls, int grid, const InstDesc* tab, BatchHdr* hdr, hipStream_t s, int fair = 0);
+// Whether a plain launch of `grid` workgroups on `num_cu` CUs takes the
+// progress-ordered priorities: at most two of its workgroups share a CU.
+inline int analysis_fair_grid(int grid, int num_cu) { return grid <= 2 * num_cu ? 1 : 0; }
 // Analysis workgroups of the class one CU holds at once (LDS and registers).
 int analysis_blocks_per_cu(int cls);
 

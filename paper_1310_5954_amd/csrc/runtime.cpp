@@ -550,7 +550,7 @@ static void launch_domain_analysis(letkf_handle* h, hipStream_t s) {
   if (h->cls == letkf::kBigClass)
     letkf::launch_big_analysis(h->P.n_dom, h->max_rows, h->P.m, dev_desc(h), dev_hdr(h), s);
   else
-    letkf::launch_analysis(h->cls, h->ana_grid, dev_desc(h), dev_hdr(h), s);
+    letkf::launch_analysis(h->cls, h->ana_grid, dev_desc(h), dev_hdr(h), s, letkf::analysis_fair_grid(h->ana_grid, h->num_cu));
 }
 
 namespace letkf {
@@ -675,7 +675,9 @@ int upload_order_vec(letkf_handle* h, const std::vector<int32_t>& order, int pol
 // domains so far, the tuning launches included (which all analyse the current
 // frame, so its timing here favours it somewhat); the per-domain sweep sums
 // are restored afterwards like the states.  max_grid > 0 caps the grids
-// (candidates and default).
+// (candidates and default).  `balanced` is set for the plain path, whose
+// launches take the progress-ordered issue priorities where
+// analysis_fair_grid allows, and its candidates are timed the same way.
 int tune_class(int cls, const InstDesc* tab, BatchHdr* hdr, int slope_rows, int items,
                const std::vector<letkf_handle*>& insts, int num_cu, int reps, bool balanced, int max_grid,
                hipStream_t s, letkf_tuning* res, int* grid_out) {
@@ -709,7 +711,7 @@ int tune_class(int cls, const InstDesc* tab, BatchHdr* hdr, int slope_rows, int 
     for (int r = 0; r <= reps; ++r) {
       launch_slopes(cls, slope_rows, tab, hdr, s);
       LETKF_HIP(hipEventRecord(e0, s));
-      launch_analysis(cls, grid, tab, hdr, s);
+      launch_analysis(cls, grid, tab, hdr, s, balanced ? analysis_fair_grid(grid, num_cu) : 0);
       LETKF_HIP(hipEventRecord(e1, s));
       LETKF_HIP(hipGetLastError());
       LETKF_HIP(hipEventSynchronize(e1));
@@ -818,6 +820,7 @@ int letkf_create(const letkf_dims* dims, const letkf_model* model, const letkf_d
     int num_cu = 0;
     if (hipDeviceGetAttribute(&num_cu, hipDeviceAttributeMultiprocessorCount, h->device) != hipSuccess || num_cu < 1)
       rc = fail(LETKF_EDEVICE, "hipDeviceGetAttribute");
+    h->num_cu = num_cu;
     h->ana_grid = std::min(h->P.n_dom, analysis_blocks_per_cu(h->cls) * num_cu);
     for (int l = 0; l < h->P.n_dom; ++l)
       h->max_rows = std::max(h->max_rows, 2 * (h->P.est_ptr[l + 1] - h->P.est_ptr[l]));
@@ -991,7 +994,7 @@ int letkf_step_noalloc(letkf_handle* h, const double* y_dev, double* pred_dev, v
   const InstDesc* tab = (const InstDesc*)(sp + lay.desc);
   BatchHdr* hdr = (BatchHdr*)(sp + lay.hdr);
   launch_slopes(h->cls, h->P.p(), tab, hdr, s);
-  launch_analysis(h->cls, h->ana_grid, tab, hdr, s);
+  launch_analysis(h->cls, h->ana_grid, tab, hdr, s, analysis_fair_grid(h->ana_grid, h->num_cu));
   if (h->P.flags & LETKF_FLAG_PISTONS) launch_pistons(h->cls, h->P.n_dom, tab, hdr, s);
   launch_rows(h->cls, 2, h->P.n_act, tab, hdr, s);
   LETKF_HIP(hipGetLastError());
